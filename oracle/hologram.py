@@ -1,0 +1,181 @@
+"""Hologram generation loops in FP64 (oracle; test infrastructure).
+
+Follows, in order:
+  * Background section: far field of a 100%-fill SLM = 2D DFT
+    (Eqs. fouriertrans2d5c/d); Fresnel holograms add a quadratic phase term.
+  * Algorithms section: quantisation = adapting the ideal aperture to the
+    SLM's states; the "three freedoms" (amplitude, phase, scale).
+  * Floating Points section: every image is scaled automatically.
+  * Iterative Fourier Transform Algorithms section: Gerchberg-Saxton (GS)
+    and its weighted variant.
+  * Time-Averaged Algorithms section: OSPR and adaptive OSPR.
+
+Readings where the paper is silent (each is restated in the design notes):
+  * Target preparation: T is scaled so that sum T^2 = Nx Ny.  For binary
+    phase (L = 2) the replay of a real +-1 hologram is centro-symmetric,
+    |R(u)| = |R(-u)|, so T is first replaced by the closest symmetric
+    intensity, T <- sqrt((T(u)^2 + T(-u)^2) / 2), -u taken about the centre.
+  * GS order: f0 -> [R = forward(f); nmse; R' = T R/|R|; g = backward(R');
+    f = P_L(g)] x K -> nmse of the final, projected field.  The initial
+    field is an unquantised random phase (or a supplied field / levels).
+  * Weighted GS: w_k = clamp(w_{k-1} * (T / max(|R|, eps)) / m_{k-1},
+    1e-6, 1e6) on the support Omega = {T > 0}; m_{k-1} = mean of w_{k-1}
+    over Omega (m_0 = mean of the initial weights); R' = w_k T R/|R|.
+  * Fresnel: single-transform Fresnel with chirp
+    Q[y][x] = exp(i pi p^2 ((x - Nx/2)^2 + (y - Ny/2)^2) / (lambda z));
+    forward R = centre(DFT(f Q)), backward f = IDFT(uncentre(R)) conj(Q).
+  * OSPR: subframe n draws a uniform random replay phase phi_n, takes the
+    binary projection of IDFT(T_n e^{i phi_n}), accumulates |R_n|^2 and
+    reports the NMSE of the running-average amplitude sqrt(A_n / n).
+    Adaptive feedback (compensating the cumulative error): the next
+    subframe asks for the intensity still missing after n+1 frames,
+    T_{n+1}^2 = max(0, (n+1) T^2 - A_n).  No global scale is needed: the
+    binary projection ignores the scale of T_{n+1}, and Parseval fixes
+    mean(A_n) = n = n mean(T^2) exactly.
+"""
+import numpy as np
+
+from . import dft as _dft
+from . import philox as _ph
+from . import slm as _slm
+from . import metrics as _m
+
+EPS = 1e-6
+W_MIN = 1e-6
+W_MAX = 1e6
+
+
+def mirror(T):
+    """T(-u) about the replay centre: index (N - i) mod N along each axis."""
+    ny, nx = T.shape
+    iy = (-np.arange(ny)) % ny
+    ix = (-np.arange(nx)) % nx
+    return T[np.ix_(iy, ix)]
+
+
+def prepare_target(T_raw, L):
+    """Target preparation (automatic scaling; binary symmetrisation)."""
+    T = np.asarray(T_raw, dtype=np.float64)
+    if np.any(~np.isfinite(T)) or np.any(T < 0):
+        raise ValueError("target amplitude must be finite and non-negative")
+    if L == 2:
+        T = np.sqrt(0.5 * (T * T + mirror(T) ** 2))
+    e = float(np.sum(T * T))
+    if e <= 0.0:
+        raise ValueError("target has zero energy")
+    ny, nx = T.shape
+    return T * np.sqrt(nx * ny / e)
+
+
+def fresnel_chirp(ny, nx, wavelength, pitch, z):
+    """Quadratic phase Q[y][x] on centred pixel coordinates; None = Fourier."""
+    if z is None or not np.isfinite(z) or z <= 0:
+        return None
+    y = np.arange(ny, dtype=np.float64) - ny / 2
+    x = np.arange(nx, dtype=np.float64) - nx / 2
+    r2 = y[:, None] ** 2 + x[None, :] ** 2
+    ph = np.pi * pitch * pitch * r2 / (wavelength * z)
+    return np.cos(ph) + 1j * np.sin(ph)
+
+
+def forward(f, Q=None):
+    """SLM plane -> centred replay plane."""
+    f = np.asarray(f, dtype=np.complex128)
+    if Q is not None:
+        f = f * Q
+    return _dft.centre(_dft.dft2(f))
+
+
+def backward(Rc, Q=None):
+    """Centred replay plane -> SLM plane (inverse of forward())."""
+    g = _dft.idft2(_dft.uncentre(np.asarray(Rc, dtype=np.complex128)))
+    if Q is not None:
+        g = g * np.conj(Q)
+    return g
+
+
+def _phase_of(R):
+    A = np.abs(R)
+    return np.where(A > 0, R / np.where(A > 0, A, 1.0), 1.0 + 0j), A
+
+
+def fienup_error(T, A):
+    """Unscaled replay error sum (|R| - T)^2, the quantity GS never increases."""
+    return float(np.sum((np.asarray(A) - np.asarray(T)) ** 2))
+
+
+def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
+       weighted=False, weights=None, optics=None, batch_item=0):
+    """Gerchberg-Saxton / weighted GS.  Returns a dict of final state.
+
+    optics = (wavelength_m, pitch_m, z_m) selects a Fresnel hologram.
+    Keys: field (f_K), levels (k_K or None), replay (R_K), nmse (K+1),
+    fienup (K+1), weights (w_K), m (mean of w_K on Omega), target (prepared T).
+    """
+    T = prepare_target(T_raw, L)
+    ny, nx = T.shape
+    Q = fresnel_chirp(ny, nx, *optics) if optics is not None else None
+    if init_field is not None:
+        f = np.asarray(init_field, dtype=np.complex128)
+    elif init_levels is not None:
+        f = _slm.level_phasor(np.asarray(init_levels, dtype=np.int64), L)
+    else:
+        f = np.exp(1j * _ph.phase_field(seed, _ph.TAG_INIT, ny, nx, batch_item))
+    levels = None if init_levels is None else np.asarray(init_levels, np.int64)
+    omega = T > 0
+    w = np.ones_like(T) if weights is None else np.asarray(weights, dtype=np.float64).copy()
+    m = float(np.mean(w[omega])) if np.any(omega) else 1.0
+    nm, fe = [], []
+    for _ in range(iters):
+        R = forward(f, Q)
+        ph, A = _phase_of(R)
+        nm.append(_m.nmse(T, A))
+        fe.append(fienup_error(T, A))
+        if weighted:
+            ratio = T / np.maximum(A, EPS)
+            w = np.where(omega, np.clip(w * ratio / m, W_MIN, W_MAX), w)
+            m = float(np.mean(w[omega]))
+            Rp = w * T * ph
+        else:
+            Rp = T * ph
+        g = backward(Rp, Q)
+        f, levels = _slm.project(g, L)
+    R = forward(f, Q)
+    A = np.abs(R)
+    nm.append(_m.nmse(T, A))
+    fe.append(fienup_error(T, A))
+    return dict(field=f, levels=levels, replay=R, nmse=np.array(nm),
+                fienup=np.array(fe), weights=w, m=m, target=T)
+
+
+def ospr(T_raw, subframes, adaptive, seed=0, batch_item=0):
+    """OSPR / adaptive OSPR with binary phase subframes.
+
+    Returns levels (subframes, Ny, Nx), nmse per subframe of the running
+    time-averaged replay amplitude, and the accumulated intensity A_N.
+    """
+    T = prepare_target(T_raw, 2)
+    ny, nx = T.shape
+    A = np.zeros_like(T)
+    Tn = T.copy()
+    levels, nm = [], []
+    for n in range(1, subframes + 1):
+        phi = _ph.phase_field(seed, _ph.TAG_OSPR + n, ny, nx, batch_item)
+        g = backward(Tn * np.exp(1j * phi))
+        h, k = _slm.project(g, 2)
+        R = forward(h)
+        A = A + np.abs(R) ** 2
+        avg = A / n
+        nm.append(_m.nmse(T, np.sqrt(avg)))
+        if adaptive:
+            Tn = np.sqrt(np.maximum(0.0, (n + 1) * T * T - A))
+        levels.append(k)
+    return dict(levels=np.array(levels), nmse=np.array(nm), accum=A, target=T)
+
+
+def fresnel_propagate(field, wavelength, pitch, z, direction):
+    """+1: SLM -> centred replay; -1: centred replay -> SLM."""
+    field = np.asarray(field, dtype=np.complex128)
+    ny, nx = field.shape
+    Q = fresnel_chirp(ny, nx, wavelength, pitch, z)
+    return forward(field, Q) if direction > 0 else backward(field, Q)
