@@ -1,0 +1,183 @@
+"""Benchmark of the weighted-GS hot path on one MI355X.
+
+Workload: weighted Gerchberg-Saxton, binary-phase SLM, 1024x1024 complex64,
+100 iterations per hologram, target = sum of 32 Gaussians in the central
+512x512 window (seeded synthetic stand-in for the paper's images).  A step
+is one complete hg_gs_batched call (set-up, 100 iterations, NMSE finisher)
+over a batch of B such holograms already resident in HBM; the default
+B = 32 makes the working set (~0.9 GB) exceed the 256 MB Infinity Cache so
+the figure is an HBM figure.  value = B * 100 * steps / seconds
+(hologram-iterations per second).
+
+Prints one JSON line.  The roofline object reports the column pass (the
+kernel that moves the most bytes per launch), timed with hipEvents on the
+launch stream during a second, instrumented pass over the same steps.  The
+cpu_baseline leg times the FP64 oracle on this host on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GS iter/s at 1024^2 c64 (%HBM peak); time-to-NMSE learned-init vs plain GS"
+HBM_PEAK_GBS = 8000.0
+N = 1024
+ITERS = 100
+LEVELS = 2
+# algorithmic HBM bytes per pixel: weighted column pass = field r+w (16) +
+# target r (4) + weights r+w (8); its final launch (NMSE only) = field r (8)
+# + target r (4); row pass = field r+w (16), + levels w (1) on the last.
+COL_BYTES, COL_FINAL_BYTES, ROW_BYTES = 28, 12, 16
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(budget_s=20.0):
+    """FP64 oracle weighted GS on one 1024^2 target: iterations per second."""
+    import numpy as np
+    import synth
+    from oracle import hologram
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    T = synth.gaussian_target(N, seed=2)
+    t0 = time.perf_counter()
+    hologram.gs(T, 1, LEVELS, seed=1, weighted=True)
+    t1 = time.perf_counter() - t0  # one iteration + final evaluation
+    k = int(max(2, min(50, budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    hologram.gs(T, k, LEVELS, seed=1, weighted=True)
+    dt = time.perf_counter() - t0
+    return {"value": k / dt, "unit": "iter/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"one 1024x1024 binary weighted-GS hologram, {k} iterations (+1 final "
+                      f"evaluation), FP64 DFT-matrix oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-b1", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import ctypes
+    import torch
+    import synth
+    import paper_2008_12214_amd as hg
+    from paper_2008_12214_amd._binding import hg_problem
+
+    dev = torch.device("cuda:0")
+    lib = hg.lib()
+
+    def setup(B):
+        targets = [torch.from_numpy(synth.gaussian_target(N, seed=2, batch_item=b)).to(dev) for b in range(B)]
+        levels = [torch.empty((N, N), dtype=torch.uint8, device=dev) for _ in range(B)]
+        nmse = [torch.empty(ITERS + 1, dtype=torch.float64, device=dev) for _ in range(B)]
+        arr = (hg_problem * B)()
+        for b in range(B):
+            arr[b] = hg_problem(N, N, LEVELS, ITERS, 1, 0.0, 0.0, 0.0, targets[b].data_ptr(),
+                                levels[b].data_ptr(), nmse[b].data_ptr())
+        nbytes = lib.hg_gs_batched_workspace_size(arr, B)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        stream = torch.cuda.current_stream(dev)
+        sp = ctypes.c_void_p(stream.cuda_stream)
+
+        def step():
+            st = lib.hg_gs_batched(arr, B, 1, ctypes.c_void_p(ws.data_ptr()), nbytes, sp)
+            if st != 0:
+                raise RuntimeError(hg.hg_last_error())
+        return step, (targets, levels, nmse, ws, arr)
+
+    def timed(step, k):
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(k):
+            step()
+        torch.cuda.synchronize(dev)
+        return time.perf_counter() - t0
+
+    B = args.batch
+    log(f"batch {B} x {N}^2 weighted GS, {ITERS} iterations, warmup {args.warmup}, steps {args.steps}")
+    step, keep = setup(B)
+    for _ in range(args.warmup):
+        step()
+    dt = timed(step, args.steps)
+    value = B * ITERS * args.steps / dt
+    log(f"timed {dt:.3f} s -> {value:.1f} hologram-iterations/s")
+    nm_final = float(keep[2][0][-1].item())
+
+    # instrumented pass: per-kernel device time with hipEvents on the launch stream
+    hg.hg_timing_enable(True)
+    hg.hg_timing_read()
+    timed(step, args.steps)
+    kt = hg.hg_timing_read()
+    hg.hg_timing_enable(False)
+    px = N * N * B
+    col_bytes = args.steps * (ITERS * COL_BYTES + COL_FINAL_BYTES) * px
+    # row launches: one initial pass (writes the field, 8 B/px) + ITERS passes
+    row_bytes = args.steps * (8 + ITERS * ROW_BYTES + 1) * px
+    col_avg_ms = kt["col_ms"] / kt["col_launches"]
+    row_avg_ms = kt["row_ms"] / kt["row_launches"]
+    col_gbs = col_bytes / (kt["col_ms"] * 1e-3) / 1e9
+    row_gbs = row_bytes / (kt["row_ms"] * 1e-3) / 1e9
+    iter_gbs = (ITERS * (COL_BYTES + ROW_BYTES)) * px * args.steps / dt / 1e9
+    log(f"column pass avg {col_avg_ms * 1e3:.1f} us ({col_gbs:.0f} GB/s), row pass avg {row_avg_ms * 1e3:.1f} us "
+        f"({row_gbs:.0f} GB/s)")
+    del step, keep
+    torch.cuda.empty_cache()
+
+    b1 = None
+    if not args.no_b1:
+        step1, keep1 = setup(1)
+        for _ in range(args.warmup):
+            step1()
+        k1 = max(args.steps, 10)
+        dt1 = timed(step1, k1)
+        b1 = {"iter_per_s": ITERS * k1 / dt1, "us_per_iteration": dt1 / (k1 * ITERS) * 1e6,
+              "algorithmic_GBs": (COL_BYTES + ROW_BYTES) * N * N * ITERS * k1 / dt1 / 1e9}
+        log(f"B=1: {b1['iter_per_s']:.0f} iter/s, {b1['us_per_iteration']:.1f} us/iteration")
+        del step1, keep1
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline()
+        log(f"oracle {cpu['value']:.3f} iter/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"wgs_binary_{N}x{N}_{ITERS}it", "batch": B, "grid": [N, N], "iters": ITERS,
+                   "slm_levels": LEVELS, "target": "gaussian sum, 32 blobs, central window"},
+        "roofline": {"bound": "hbm", "achieved": round(col_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(col_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "column pass k_col<1024,16,8> (weighted)",
+                     "bytes_per_launch": int(col_bytes / kt["col_launches"]),
+                     "avg_launch_us": round(col_avg_ms * 1e3, 2)},
+        "cpu_baseline": cpu,
+        "extra": {"row_pass": {"avg_launch_us": round(row_avg_ms * 1e3, 2), "achieved_GBs": round(row_gbs, 1)},
+                  "whole_iteration_algorithmic_GBs": round(iter_gbs, 1),
+                  "whole_iteration_frac": round(iter_gbs / HBM_PEAK_GBS, 4),
+                  "per_hologram_iter_per_s": round(value / B, 1), "b1": b1,
+                  "final_nmse_item0": nm_final},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

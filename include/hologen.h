@@ -1,0 +1,189 @@
+/*
+ * hologen.h -- C ABI of the MI355X (gfx950) hologram-generation hot path.
+ *
+ * The operations are those of the HoloGen paper (Christopher, Kadis, Gordon,
+ * Wilkinson, arXiv 2008.12214): iterative Fourier transform algorithms
+ * (Gerchberg-Saxton and weighted GS, "Iterative Fourier Transform
+ * Algorithms" section), one-step phase retrieval and adaptive OSPR
+ * ("Time-Averaged Algorithms" section), Fourier and Fresnel propagation
+ * (Background section, Eqs. fouriertrans2d5c/d and the quadratic phase term
+ * of Fresnel holograms), and projection onto binary or multi-level phase
+ * SLMs (Algorithms section; Example section, Listing 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every buffer argument is a DEVICE pointer owned by the caller.  The
+ *    library never frees caller memory, never allocates device memory and
+ *    never synchronises the stream: work is enqueued on `stream` (a
+ *    hipStream_t; NULL = the default stream) and the call returns.  Results
+ *    are valid once the stream has reached that point.
+ *  - Arrays are row-major [y][x] with Nx columns.  Complex data is
+ *    interleaved complex64 (hg_complex).  Grid sizes ny and nx are
+ *    independent powers of two in [64, 4096].
+ *  - Transforms are unitary (1/sqrt(Nx Ny)).  Replay-plane arrays (target,
+ *    weights, replay field, OSPR accumulator) are CENTRED: zero frequency
+ *    at (ny/2, nx/2).  SLM-plane arrays (levels, SLM field) are in natural
+ *    pixel order.
+ *  - slm_levels: 0 = continuous phase (g/|g|); L in [2, 256] = uniform phase
+ *    levels 2 pi k / L, k stored as uint8 (L = 2 is binary {0, pi}).  The
+ *    level of a field value g is k = floor(arg(g) L / (2 pi) + 1/2) mod L.
+ *  - The target amplitude is scaled internally so that sum T^2 = Nx Ny
+ *    (automatic image scaling, "Floating Points" section); for L = 2 it is
+ *    first symmetrised, T(u) <- sqrt((T(u)^2 + T(-u)^2)/2), because the
+ *    replay of a real +-1 hologram is centro-symmetric.
+ *  - NMSE is the scale-optimal normalised error of the replay amplitude A:
+ *    1 - (sum T A)^2 / (sum T^2 sum A^2), sums in FP64 ("Error Metrics"
+ *    section, Eq. mse, at the best uniform scale).
+ *  - Random phases come from Philox4x64-10 (Salmon et al., SC'11) with key
+ *    (seed, (item << 32) | tag), counter (p >> 2, 0, 0, 0), word p & 3 for
+ *    pixel p = y*Nx + x, phase 2 pi (word >> 40) 2^-24.  Tags: 1 = initial
+ *    SLM phase, 0x100 + n = OSPR subframe n.
+ *  - Workspace: `workspace` must hold at least the size returned by the
+ *    matching *_workspace_size query, 256-byte aligned.  Its contents need
+ *    no initialisation and are clobbered.  Calls that share a workspace
+ *    must be ordered on one stream.
+ *  - Errors: argument checks run on the host before any HIP call; on error
+ *    nothing is enqueued and hg_last_error() holds a thread-local message.
+ *    A HIP launch failure returns HG_ERR_HIP.  Non-finite results are not
+ *    detected asynchronously: they appear as NaN in nmse_out.
+ */
+#ifndef HOLOGEN_H
+#define HOLOGEN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hg_complex { float x, y; } hg_complex;
+
+typedef enum hg_status {
+  HG_OK = 0,
+  HG_ERR_INVALID_ARG = 1,      /* null/inconsistent pointer, bad level count, iters < 1, ... */
+  HG_ERR_UNSUPPORTED_SIZE = 2, /* ny or nx not a power of two in [64, 4096]                 */
+  HG_ERR_WORKSPACE = 3,        /* workspace null, misaligned or smaller than the query      */
+  HG_ERR_HIP = 4               /* a HIP runtime call or kernel launch failed                */
+} hg_status;
+
+enum hg_op { HG_OP_GS = 1, HG_OP_WGS = 2, HG_OP_OSPR = 3, HG_OP_PROPAGATE = 4 };
+
+/* Bytes of workspace needed by one call of `op` on an ny x nx grid with
+ * `iters` iterations (GS/WGS) or subframes (OSPR); ignored for
+ * HG_OP_PROPAGATE.  Returns 0 for unsupported arguments. */
+size_t hg_workspace_size(int op, int ny, int nx, int iters);
+
+/* Gerchberg-Saxton ("Iterative Fourier Transform Algorithms" section).
+ *   target        [ny][nx] float, centred replay-plane amplitude, >= 0, not all 0
+ *   iters         >= 1 iterations of: forward transform, replay constraint
+ *                 R' = T R/|R| (R = 0 -> T), inverse transform, SLM projection
+ *   slm_levels    0 or 2..256
+ *   seed          Philox seed of the initial phase (used when both init
+ *                 pointers are NULL); the initial field is unquantised
+ *   init_levels   nullable [ny][nx] uint8 start levels (< slm_levels, L >= 2)
+ *   init_field    nullable [ny][nx] complex start field; wins over init_levels
+ *   wavelength_m, pitch_m, z_m
+ *                 Fresnel hologram when z_m > 0 and finite: chirp
+ *                 exp(i pi p^2 ((x-nx/2)^2 + (y-ny/2)^2) / (lambda z)) applied
+ *                 before the forward transform and conjugated after the
+ *                 inverse; otherwise Fourier (both others ignored)
+ *   levels_out    [ny][nx] uint8 final levels; required when slm_levels >= 2,
+ *                 ignored (may be NULL) when slm_levels == 0
+ *   slm_field_out nullable [ny][nx] complex final SLM field f_K
+ *   replay_out    nullable [ny][nx] complex centred replay of f_K
+ *   nmse_out      nullable iters+1 doubles: nmse[k] is the NMSE of the
+ *                 replay of f_k (nmse[0] = initial field)                    */
+hg_status hg_gs(const float* target, int ny, int nx, int iters, int slm_levels, uint64_t seed,
+                const uint8_t* init_levels, const hg_complex* init_field,
+                double wavelength_m, double pitch_m, double z_m,
+                uint8_t* levels_out, hg_complex* slm_field_out, hg_complex* replay_out,
+                double* nmse_out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Weighted GS (named in the "Iterative Fourier Transform Algorithms"
+ * section; the update rule is this library's reading, a leaky log-domain
+ * integrator of the amplitude error):
+ *   w_k = clamp(w_{k-1} max(T, 0.1) / max(|R|, 0.1) / m_{k-1}, 1e-6, 1e6)^0.7
+ *   on T > 0 (w unchanged elsewhere), m_{k-1} = mean of w_{k-1} over T > 0,
+ *   R' = w_k T R / |R|, with T and |R| at unit rms.
+ * Arguments as hg_gs, plus
+ *   weights_inout nullable [ny][nx] float centred weights: read as w_0 and
+ *                 overwritten with w_K; NULL starts from w_0 = 1.            */
+hg_status hg_wgs(const float* target, int ny, int nx, int iters, int slm_levels, uint64_t seed,
+                 const uint8_t* init_levels, const hg_complex* init_field,
+                 double wavelength_m, double pitch_m, double z_m,
+                 uint8_t* levels_out, hg_complex* slm_field_out, hg_complex* replay_out,
+                 double* nmse_out, float* weights_inout,
+                 void* workspace, size_t workspace_bytes, void* stream);
+
+/* OSPR / adaptive OSPR with binary-phase subframes ("Time-Averaged
+ * Algorithms" section).  Subframe n = 1..subframes: random replay phase
+ * phi_n (Philox tag 0x100 + n), h_n = binary projection of
+ * IDFT(T_n e^{i phi_n}), A_n = A_{n-1} + |DFT(h_n)|^2,
+ * nmse[n-1] = NMSE(T, sqrt(A_n / n)).  adaptive != 0 feeds back the missing
+ * intensity, T_{n+1}^2 = max(0, (n+1) T^2 - A_n); adaptive == 0 keeps T.
+ *   levels_out    [subframes][ny][nx] uint8 in {0, 1}, required
+ *   nmse_out      nullable `subframes` doubles
+ *   accum_out     nullable [ny][nx] float, A_N (centred)                     */
+hg_status hg_ospr(const float* target, int ny, int nx, int subframes, int adaptive, uint64_t seed,
+                  uint8_t* levels_out, double* nmse_out, float* accum_out,
+                  void* workspace, size_t workspace_bytes, void* stream);
+
+/* Unitary Fourier / Fresnel propagation of a complex field (Background
+ * section).  direction = +1: SLM plane -> centred replay plane,
+ * out = centre(DFT(in * Q)); direction = -1: centred replay -> SLM plane,
+ * out = IDFT(uncentre(in)) * conj(Q).  Q is the chirp of hg_gs (Q = 1 when
+ * z_m <= 0 or not finite).  in and out may alias.                            */
+hg_status hg_fresnel_propagate(const hg_complex* in, hg_complex* out, int ny, int nx,
+                               double wavelength_m, double pitch_m, double z_m, int direction,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* The random phase field the library draws: out[y][x] = exp(2 pi i u24)
+ * with u24 the top 24 bits of the Philox word of pixel p = y*nx + x under
+ * key (seed, (item << 32) | tag), as described above.  tag 1 with item 0 is
+ * hg_gs's initial SLM phase; tag 0x100 + n is OSPR subframe n's replay
+ * phase.  No workspace.                                                      */
+hg_status hg_random_phase(uint64_t seed, uint32_t item, uint32_t tag, int ny, int nx, hg_complex* out,
+                          void* stream);
+
+/* Batch processing (program summary: batch processing of many images):
+ * many independent GS problems of possibly different sizes in one call.
+ * Problems are grouped by (ny, nx); each group runs as one batched launch
+ * per pass.  Per-problem fields mirror hg_gs (Philox item = index in the
+ * array, so problem b draws key (seed, (b << 32) | 1)).                      */
+typedef struct hg_problem {
+  int ny, nx, slm_levels, iters;
+  uint64_t seed;
+  double wavelength_m, pitch_m, z_m;
+  const float* target;
+  uint8_t* levels_out;   /* required when slm_levels >= 2 */
+  double* nmse_out;      /* nullable, iters+1 */
+} hg_problem;
+
+size_t hg_gs_batched_workspace_size(const hg_problem* problems, int count);
+hg_status hg_gs_batched(const hg_problem* problems, int count, int weighted,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* Kernel timing (instrumentation for benchmarks).  While enabled, every
+ * launch of a column pass, row pass or set-up kernel made by this process
+ * is bracketed by a pair of hipEvents on the stream it is launched on.
+ * hg_timing_read waits for the recorded events, returns the summed device
+ * time (ms) and launch count per category since the last read, and resets
+ * them.  Enabling adds host work per launch; leave it off otherwise.        */
+typedef struct hg_kernel_times {
+  double col_ms, row_ms, setup_ms;
+  long long col_launches, row_launches, setup_launches;
+} hg_kernel_times;
+void hg_timing_enable(int on);
+hg_status hg_timing_read(hg_kernel_times* out);
+
+/* Static text for a status code, and the thread-local detail of the last
+ * error raised on this thread ("" if none). */
+const char* hg_status_string(hg_status status);
+const char* hg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOLOGEN_H */

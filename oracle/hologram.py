@@ -18,9 +18,18 @@ Readings where the paper is silent (each is restated in the design notes):
   * GS order: f0 -> [R = forward(f); nmse; R' = T R/|R|; g = backward(R');
     f = P_L(g)] x K -> nmse of the final, projected field.  The initial
     field is an unquantised random phase (or a supplied field / levels).
-  * Weighted GS: w_k = clamp(w_{k-1} * (T / max(|R|, eps)) / m_{k-1},
-    1e-6, 1e6) on the support Omega = {T > 0}; m_{k-1} = mean of w_{k-1}
-    over Omega (m_0 = mean of the initial weights); R' = w_k T R/|R|.
+  * Weighted GS (the paper names weighting only): a leaky log-domain
+    integrator of the amplitude error,
+      w_k = clamp(w_{k-1} * ratio / m_{k-1}, 1e-6, 1e6) ** GAMMA,
+      ratio = max(T, EPS) / max(|R|, EPS),
+    on the support Omega = {T > 0} (w unchanged elsewhere); m_{k-1} = mean
+    of w_{k-1} over Omega (m_0 = mean of the initial weights);
+    R' = w_k T R/|R|.  T and |R| have unit rms (Parseval), so EPS = 0.1 is
+    relative to the mean replay level; flooring both sides keeps a
+    consistent target a fixed point and bounds the ratio's sensitivity to
+    rounding in |R| near speckle zeros.  GAMMA = 1 is the plain
+    multiplicative rule, which diverges for binary phase; GAMMA = 0.7 keeps
+    the weights bounded.
   * Fresnel: single-transform Fresnel with chirp
     Q[y][x] = exp(i pi p^2 ((x - Nx/2)^2 + (y - Ny/2)^2) / (lambda z));
     forward R = centre(DFT(f Q)), backward f = IDFT(uncentre(R)) conj(Q).
@@ -40,7 +49,9 @@ from . import philox as _ph
 from . import slm as _slm
 from . import metrics as _m
 
-EPS = 1e-6
+EPS = 1e-6          # OSPR intensity floor
+WGS_EPS = 0.1       # weighted-GS amplitude floor (unit-rms units)
+WGS_GAMMA = 0.7     # weighted-GS leak exponent
 W_MIN = 1e-6
 W_MAX = 1e6
 
@@ -109,8 +120,9 @@ def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
     """Gerchberg-Saxton / weighted GS.  Returns a dict of final state.
 
     optics = (wavelength_m, pitch_m, z_m) selects a Fresnel hologram.
-    Keys: field (f_K), levels (k_K or None), replay (R_K), nmse (K+1),
-    fienup (K+1), weights (w_K), m (mean of w_K on Omega), target (prepared T).
+    Keys: field (f_K), levels (k_K or None), g (the last field before
+    projection), replay (R_K), nmse (K+1), fienup (K+1), weights (w_K),
+    m (mean of w_K on Omega), target (prepared T).
     """
     T = prepare_target(T_raw, L)
     ny, nx = T.shape
@@ -126,14 +138,15 @@ def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
     w = np.ones_like(T) if weights is None else np.asarray(weights, dtype=np.float64).copy()
     m = float(np.mean(w[omega])) if np.any(omega) else 1.0
     nm, fe = [], []
+    g = None
     for _ in range(iters):
         R = forward(f, Q)
         ph, A = _phase_of(R)
         nm.append(_m.nmse(T, A))
         fe.append(fienup_error(T, A))
         if weighted:
-            ratio = T / np.maximum(A, EPS)
-            w = np.where(omega, np.clip(w * ratio / m, W_MIN, W_MAX), w)
+            ratio = np.maximum(T, WGS_EPS) / np.maximum(A, WGS_EPS)
+            w = np.where(omega, np.clip(w * ratio / m, W_MIN, W_MAX) ** WGS_GAMMA, w)
             m = float(np.mean(w[omega]))
             Rp = w * T * ph
         else:
@@ -144,8 +157,25 @@ def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
     A = np.abs(R)
     nm.append(_m.nmse(T, A))
     fe.append(fienup_error(T, A))
-    return dict(field=f, levels=levels, replay=R, nmse=np.array(nm),
+    return dict(field=f, levels=levels, g=g, replay=R, nmse=np.array(nm),
                 fienup=np.array(fe), weights=w, m=m, target=T)
+
+
+def ospr_subframe(T, A_prev, n, adaptive, seed=0, batch_item=0):
+    """Subframe n >= 1 of (adaptive) OSPR from the accumulated intensity A_{n-1}.
+
+    T is the prepared target.  Returns (levels_n, g_n, A_n, nmse_n).
+    """
+    ny, nx = T.shape
+    if adaptive and n > 1:
+        Tn = np.sqrt(np.maximum(0.0, n * T * T - A_prev))
+    else:
+        Tn = T
+    phi = _ph.phase_field(seed, _ph.TAG_OSPR + n, ny, nx, batch_item)
+    g = backward(Tn * np.exp(1j * phi))
+    h, k = _slm.project(g, 2)
+    A = A_prev + np.abs(forward(h)) ** 2
+    return k, g, A, _m.nmse(T, np.sqrt(A / n))
 
 
 def ospr(T_raw, subframes, adaptive, seed=0, batch_item=0):
@@ -155,21 +185,12 @@ def ospr(T_raw, subframes, adaptive, seed=0, batch_item=0):
     time-averaged replay amplitude, and the accumulated intensity A_N.
     """
     T = prepare_target(T_raw, 2)
-    ny, nx = T.shape
     A = np.zeros_like(T)
-    Tn = T.copy()
     levels, nm = [], []
     for n in range(1, subframes + 1):
-        phi = _ph.phase_field(seed, _ph.TAG_OSPR + n, ny, nx, batch_item)
-        g = backward(Tn * np.exp(1j * phi))
-        h, k = _slm.project(g, 2)
-        R = forward(h)
-        A = A + np.abs(R) ** 2
-        avg = A / n
-        nm.append(_m.nmse(T, np.sqrt(avg)))
-        if adaptive:
-            Tn = np.sqrt(np.maximum(0.0, (n + 1) * T * T - A))
+        k, _, A, e = ospr_subframe(T, A, n, adaptive, seed, batch_item)
         levels.append(k)
+        nm.append(e)
     return dict(levels=np.array(levels), nmse=np.array(nm), accum=A, target=T)
 
 

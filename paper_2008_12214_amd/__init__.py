@@ -1,0 +1,17 @@
+"""MI355X-native hologram generation (HoloGen's iterative Fourier transform hot path).
+
+The compute path is the HIP library ``libhologen.so`` (C ABI in
+``include/hologen.h``).  This package is a thin ctypes binding with the same
+entry-point names: it checks tensor placement, allocates outputs and the
+workspace through PyTorch, and passes raw device pointers and the current
+stream.  Every step of the path runs in the library's kernels; there is no
+CPU fallback, and importing fails loudly if the library has not been built.
+"""
+from ._binding import (  # noqa: F401
+    HG_OK, HG_ERR_INVALID_ARG, HG_ERR_UNSUPPORTED_SIZE, HG_ERR_WORKSPACE, HG_ERR_HIP,
+    HG_OP_GS, HG_OP_WGS, HG_OP_OSPR, HG_OP_PROPAGATE,
+    HologenError, lib, lib_path,
+    hg_workspace_size, hg_gs, hg_wgs, hg_ospr, hg_fresnel_propagate,
+    hg_gs_batched, hg_gs_batched_workspace_size, hg_random_phase, hg_status_string, hg_last_error,
+    hg_timing_enable, hg_timing_read,
+)

@@ -1,0 +1,542 @@
+// C ABI of the hologram hot path (declared in include/hologen.h): argument
+// validation on the host, workspace carving, and the launch sequences of the
+// GS / weighted GS / OSPR / propagation pipelines on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <type_traits>
+#include <vector>
+
+#include "hologen.h"
+#include "hg_kernels.hpp"
+
+namespace {
+
+using namespace hg;
+
+thread_local char g_err[512] = "";
+
+hg_status fail(hg_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// optional per-launch timing with hipEvents
+// ---------------------------------------------------------------------------
+enum TimeCat { TC_COL = 0, TC_ROW = 1, TC_SETUP = 2 };
+struct Timing {
+  bool on = false;
+  std::vector<hipEvent_t> pool;  // reusable events
+  size_t used = 0;
+  std::vector<std::pair<int, size_t>> marks;  // (category, index of the start event)
+} g_timing;
+
+hipEvent_t timing_event() {
+  if (g_timing.used == g_timing.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_timing.pool.push_back(e);
+  }
+  return g_timing.pool[g_timing.used++];
+}
+
+// RAII bracket around one launch
+struct TimeScope {
+  int cat;
+  hipStream_t st;
+  size_t start = (size_t)-1;
+  TimeScope(int c, hipStream_t s) : cat(c), st(s) {
+    if (!g_timing.on) return;
+    hipEvent_t e = timing_event();
+    if (!e) return;
+    start = g_timing.used - 1;
+    hipEventRecord(e, st);
+  }
+  ~TimeScope() {
+    if (start == (size_t)-1) return;
+    hipEvent_t e = timing_event();
+    if (!e) return;
+    hipEventRecord(e, st);
+    g_timing.marks.push_back({cat, start});
+  }
+};
+
+bool pow2_in_range(int n) { return n >= 64 && n <= 4096 && (n & (n - 1)) == 0; }
+
+// ---------------------------------------------------------------------------
+// launch geometry per transform length (E = 16 elements per thread)
+// ---------------------------------------------------------------------------
+constexpr int kE = 16;
+template <int N> struct RowCfg {
+  static constexpr int T = N / kE;
+  static constexpr int RPB = T >= 256 ? 1 : 256 / T;  // rows per workgroup
+};
+template <int N> struct ColCfg {
+  static constexpr int C = N <= 512 ? 16 : (N == 1024 ? 8 : (N == 2048 ? 4 : 2));  // columns per tile
+};
+int col_tile(int ny) { return ny <= 512 ? 16 : (ny == 1024 ? 8 : (ny == 2048 ? 4 : 2)); }
+
+template <class F> bool with_size(int n, F&& f) {
+  switch (n) {
+    case 64: f(std::integral_constant<int, 64>{}); return true;
+    case 128: f(std::integral_constant<int, 128>{}); return true;
+    case 256: f(std::integral_constant<int, 256>{}); return true;
+    case 512: f(std::integral_constant<int, 512>{}); return true;
+    case 1024: f(std::integral_constant<int, 1024>{}); return true;
+    case 2048: f(std::integral_constant<int, 2048>{}); return true;
+    case 4096: f(std::integral_constant<int, 4096>{}); return true;
+    default: return false;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout of one size class (B problems of ny x nx)
+// ---------------------------------------------------------------------------
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t desc, field, tprep, wbuf, accum, twx, twy, chirp, part, total;
+  int nblk, slots;
+};
+
+Layout make_layout(int op, int ny, int nx, int B, int kmax) {
+  Layout L{};
+  const size_t px = (size_t)ny * nx * B;
+  L.nblk = nx / col_tile(ny);
+  L.slots = (op == HG_OP_OSPR ? kmax : kmax + 1) + 1;  // + energy slot
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  L.desc = take(sizeof(Desc) * B);
+  L.field = take(px * sizeof(float2));
+  L.tprep = take(px * sizeof(float));
+  L.wbuf = take(op == HG_OP_WGS ? px * sizeof(float) : 0);
+  L.accum = take(op == HG_OP_OSPR ? px * sizeof(float) : 0);
+  L.twx = take(nx * sizeof(float2));
+  L.twy = take(ny * sizeof(float2));
+  L.chirp = take((size_t)B * (nx + ny) * sizeof(float2));
+  L.part = take((size_t)B * L.slots * L.nblk * 4 * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+Layout make_prop_layout(int ny, int nx) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  L.twx = take(nx * sizeof(float2));
+  L.twy = take(ny * sizeof(float2));
+  L.chirp = take((size_t)(nx + ny) * sizeof(float2));
+  L.total = o;
+  return L;
+}
+
+template <class T> T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
+
+double chirp_rate(double lambda, double pitch, double z) {
+  if (!(z > 0.0) || !std::isfinite(z)) return 0.0;
+  return pitch * pitch / (lambda * z);
+}
+bool is_fresnel(double lambda, double pitch, double z) { return chirp_rate(lambda, pitch, z) != 0.0; }
+
+// ---------------------------------------------------------------------------
+// small upload kernels: descriptors by value (no host->device copies, so the
+// whole sequence stays on the stream and is graph-capturable)
+// ---------------------------------------------------------------------------
+struct DescPack { Desc d[8]; int count; };
+__global__ void k_set_desc(Desc* dst, DescPack pk) {
+  const int i = threadIdx.x;
+  if (i < pk.count) dst[i] = pk.d[i];
+}
+
+hg_status check_launch() {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
+  return HG_OK;
+}
+
+hg_status upload_descs(Desc* dst, const std::vector<Desc>& ds, hipStream_t st) {
+  for (size_t i = 0; i < ds.size(); i += 8) {
+    DescPack pk{};
+    pk.count = (int)std::min<size_t>(8, ds.size() - i);
+    for (int j = 0; j < pk.count; ++j) pk.d[j] = ds[i + j];
+    hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, st, dst + i, pk);
+  }
+  return check_launch();
+}
+
+void launch_twiddles(float2* tw, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, st, tw, n);
+}
+
+void launch_chirps(float2* chirp, int ny, int nx, const std::vector<double>& rates, hipStream_t st) {
+  for (size_t i = 0; i < rates.size(); i += 32) {
+    ChirpArgs ca{};
+    ca.count = (int)std::min<size_t>(32, rates.size() - i);
+    for (int j = 0; j < ca.count; ++j) ca.a[j] = rates[i + j];
+    hipLaunchKernelGGL(k_chirps, dim3((nx + ny + 255) / 256, ca.count), dim3(256), 0, st, chirp, ny, nx, ca,
+                       (int)i);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass launchers
+// ---------------------------------------------------------------------------
+bool launch_row(const Batch& bt, int B, bool fresnel, int mode, int arg, const float2* pin, float2* pout,
+                hipStream_t st) {
+  TimeScope ts(TC_ROW, st);
+  return with_size(bt.nx, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    using C = RowCfg<N>;
+    const dim3 grid(bt.ny / C::RPB, B), block(C::RPB * C::T);
+    if (fresnel)
+      hipLaunchKernelGGL((k_row<N, kE, C::RPB, true>), grid, block, 0, st, bt, mode, arg, pin, pout);
+    else
+      hipLaunchKernelGGL((k_row<N, kE, C::RPB, false>), grid, block, 0, st, bt, mode, arg, pin, pout);
+  });
+}
+
+bool launch_col(const Batch& bt, int B, int mode, int arg, int adaptive, const float2* pin, float2* pout,
+                hipStream_t st) {
+  TimeScope ts(TC_COL, st);
+  return with_size(bt.ny, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    constexpr int C = ColCfg<N>::C;
+    const dim3 grid(bt.nx / C, B), block(C * (N / kE));
+    hipLaunchKernelGGL((k_col<N, kE, C>), grid, block, 0, st, bt, mode, arg, adaptive, pin, pout);
+  });
+}
+
+bool launch_setup(const Batch& bt, int B, int weighted, hipStream_t st) {
+  TimeScope ts(TC_SETUP, st);
+  return with_size(bt.ny, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    constexpr int C = ColCfg<N>::C;
+    const dim3 grid(bt.nx / C, B), block(C * (N / kE));
+    hipLaunchKernelGGL((k_energy<N, kE, C>), grid, block, 0, st, bt);
+    hipLaunchKernelGGL((k_prepare<N, kE, C>), grid, block, 0, st, bt, weighted);
+  });
+}
+
+Batch make_batch(void* ws, const Layout& L, int ny, int nx) {
+  Batch bt{};
+  bt.desc = at<Desc>(ws, L.desc);
+  bt.field = at<float2>(ws, L.field);
+  bt.tprep = at<float>(ws, L.tprep);
+  bt.wbuf = at<float>(ws, L.wbuf);
+  bt.accum = at<float>(ws, L.accum);
+  bt.tw_x = at<float2>(ws, L.twx);
+  bt.tw_y = at<float2>(ws, L.twy);
+  bt.chirp = at<float2>(ws, L.chirp);
+  bt.part = at<double>(ws, L.part);
+  bt.ny = ny;
+  bt.nx = nx;
+  bt.nblk = L.nblk;
+  bt.slots = L.slots;
+  bt.fwd_scale = (float)(1.0 / std::sqrt((double)nx * (double)ny));
+  return bt;
+}
+
+// Whole GS / WGS pipeline for one size class.
+hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::vector<double>& rates, bool weighted,
+                       void* ws, const Layout& L, hipStream_t st) {
+  const int B = (int)ds.size();
+  int kmax = 0;
+  for (const Desc& d : ds) kmax = std::max(kmax, d.iters);
+  Batch bt = make_batch(ws, L, ny, nx);
+  hg_status s = upload_descs(const_cast<Desc*>(bt.desc), ds, st);
+  if (s != HG_OK) return s;
+  launch_twiddles(const_cast<float2*>(bt.tw_x), nx, st);
+  if (ny != nx) launch_twiddles(const_cast<float2*>(bt.tw_y), ny, st);
+  else bt.tw_y = bt.tw_x;
+  bool fresnel = false;
+  for (double r : rates) fresnel |= (r != 0.0);
+  if (fresnel) launch_chirps(const_cast<float2*>(bt.chirp), ny, nx, rates, st);
+  launch_setup(bt, B, weighted ? 1 : 0, st);
+  launch_row(bt, B, fresnel, ROW_INIT, 0, nullptr, nullptr, st);
+  const int cmode = weighted ? COL_WGS : COL_GS;
+  for (int k = 1; k <= kmax; ++k) {
+    launch_col(bt, B, cmode, k, 0, nullptr, nullptr, st);
+    launch_row(bt, B, fresnel, ROW_ITER, k, nullptr, nullptr, st);
+  }
+  launch_col(bt, B, cmode, kmax + 1, 0, nullptr, nullptr, st);
+  hipLaunchKernelGGL(k_finish, dim3(B, (kmax + 1 + 255) / 256), dim3(256), 0, st, bt, B, 0);
+  return check_launch();
+}
+
+hg_status check_ws(void* ws, size_t bytes, size_t need) {
+  if (!ws) return fail(HG_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(HG_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (bytes < need) return fail(HG_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", bytes, need);
+  return HG_OK;
+}
+
+hg_status check_common(const float* target, int ny, int nx, int iters, int L) {
+  if (!pow2_in_range(ny) || !pow2_in_range(nx))
+    return fail(HG_ERR_UNSUPPORTED_SIZE, "ny=%d nx=%d: each must be a power of two in [64, 4096]", ny, nx);
+  if (!target) return fail(HG_ERR_INVALID_ARG, "target is NULL");
+  if (iters < 1) return fail(HG_ERR_INVALID_ARG, "iters=%d must be >= 1", iters);
+  if (!(L == 0 || (L >= 2 && L <= 256))) return fail(HG_ERR_INVALID_ARG, "slm_levels=%d: 0 or 2..256", L);
+  return HG_OK;
+}
+
+hg_status gs_common(bool weighted, const float* target, int ny, int nx, int iters, int L, uint64_t seed,
+                    const uint8_t* init_levels, const hg_complex* init_field, double lambda, double pitch,
+                    double z, uint8_t* levels_out, hg_complex* field_out, hg_complex* replay_out,
+                    double* nmse_out, float* weights, void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  hg_status s = check_common(target, ny, nx, iters, L);
+  if (s != HG_OK) return s;
+  if (L >= 2 && !levels_out) return fail(HG_ERR_INVALID_ARG, "levels_out is required when slm_levels >= 2");
+  if (init_levels && L < 2) return fail(HG_ERR_INVALID_ARG, "init_levels needs slm_levels >= 2");
+  if (is_fresnel(lambda, pitch, z) && !(lambda > 0.0 && pitch > 0.0 && std::isfinite(lambda) && std::isfinite(pitch)))
+    return fail(HG_ERR_INVALID_ARG, "Fresnel needs wavelength_m > 0 and pitch_m > 0");
+  const int op = weighted ? HG_OP_WGS : HG_OP_GS;
+  const Layout Lo = make_layout(op, ny, nx, 1, iters);
+  s = check_ws(ws, ws_bytes, Lo.total);
+  if (s != HG_OK) return s;
+  Desc d{};
+  d.target = target;
+  d.levels_out = levels_out;
+  d.nmse_out = nmse_out;
+  d.field_out = reinterpret_cast<float2*>(field_out);
+  d.replay_out = reinterpret_cast<float2*>(replay_out);
+  d.weights = weights;
+  d.user_weights = weights ? 1 : 0;
+  d.init_levels = init_levels;
+  d.init_field = reinterpret_cast<const float2*>(init_field);
+  d.seed = seed;
+  d.item = 0;
+  d.L = L;
+  d.iters = iters;
+  std::vector<Desc> ds{d};
+  std::vector<double> rates{chirp_rate(lambda, pitch, z)};
+  return run_gs_class(ny, nx, ds, rates, weighted, ws, Lo, static_cast<hipStream_t>(stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hg_status_string(hg_status s) {
+  switch (s) {
+    case HG_OK: return "ok";
+    case HG_ERR_INVALID_ARG: return "invalid argument";
+    case HG_ERR_UNSUPPORTED_SIZE: return "unsupported size";
+    case HG_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case HG_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* hg_last_error(void) { return g_err; }
+
+void hg_timing_enable(int on) { g_timing.on = on != 0; }
+
+hg_status hg_timing_read(hg_kernel_times* out) {
+  g_err[0] = 0;
+  if (!out) return fail(HG_ERR_INVALID_ARG, "out is NULL");
+  *out = hg_kernel_times{};
+  for (auto& m : g_timing.marks) {
+    float ms = 0.f;
+    if (hipEventSynchronize(g_timing.pool[m.second + 1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, g_timing.pool[m.second], g_timing.pool[m.second + 1]) != hipSuccess)
+      return fail(HG_ERR_HIP, "hipEvent timing failed");
+    if (m.first == TC_COL) { out->col_ms += ms; out->col_launches++; }
+    else if (m.first == TC_ROW) { out->row_ms += ms; out->row_launches++; }
+    else { out->setup_ms += ms; out->setup_launches++; }
+  }
+  g_timing.marks.clear();
+  g_timing.used = 0;
+  return HG_OK;
+}
+
+size_t hg_workspace_size(int op, int ny, int nx, int iters) {
+  if (!pow2_in_range(ny) || !pow2_in_range(nx)) return 0;
+  if (op == HG_OP_PROPAGATE) return make_prop_layout(ny, nx).total;
+  if (op != HG_OP_GS && op != HG_OP_WGS && op != HG_OP_OSPR) return 0;
+  if (iters < 1) return 0;
+  return make_layout(op, ny, nx, 1, iters).total;
+}
+
+hg_status hg_gs(const float* target, int ny, int nx, int iters, int slm_levels, uint64_t seed,
+                const uint8_t* init_levels, const hg_complex* init_field, double wavelength_m, double pitch_m,
+                double z_m, uint8_t* levels_out, hg_complex* slm_field_out, hg_complex* replay_out,
+                double* nmse_out, void* workspace, size_t workspace_bytes, void* stream) {
+  return gs_common(false, target, ny, nx, iters, slm_levels, seed, init_levels, init_field, wavelength_m, pitch_m,
+                   z_m, levels_out, slm_field_out, replay_out, nmse_out, nullptr, workspace, workspace_bytes, stream);
+}
+
+hg_status hg_wgs(const float* target, int ny, int nx, int iters, int slm_levels, uint64_t seed,
+                 const uint8_t* init_levels, const hg_complex* init_field, double wavelength_m, double pitch_m,
+                 double z_m, uint8_t* levels_out, hg_complex* slm_field_out, hg_complex* replay_out,
+                 double* nmse_out, float* weights_inout, void* workspace, size_t workspace_bytes, void* stream) {
+  return gs_common(true, target, ny, nx, iters, slm_levels, seed, init_levels, init_field, wavelength_m, pitch_m,
+                   z_m, levels_out, slm_field_out, replay_out, nmse_out, weights_inout, workspace, workspace_bytes,
+                   stream);
+}
+
+hg_status hg_ospr(const float* target, int ny, int nx, int subframes, int adaptive, uint64_t seed,
+                  uint8_t* levels_out, double* nmse_out, float* accum_out, void* workspace, size_t workspace_bytes,
+                  void* stream) {
+  g_err[0] = 0;
+  hg_status s = check_common(target, ny, nx, subframes, 2);
+  if (s != HG_OK) return s;
+  if (!levels_out) return fail(HG_ERR_INVALID_ARG, "levels_out is required");
+  const Layout Lo = make_layout(HG_OP_OSPR, ny, nx, 1, subframes);
+  s = check_ws(workspace, workspace_bytes, Lo.total);
+  if (s != HG_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Desc d{};
+  d.target = target;
+  d.levels_out = levels_out;
+  d.nmse_out = nmse_out;
+  d.accum_out = accum_out;
+  d.seed = seed;
+  d.L = 2;
+  d.iters = subframes;
+  Batch bt = make_batch(workspace, Lo, ny, nx);
+  s = upload_descs(const_cast<Desc*>(bt.desc), {d}, st);
+  if (s != HG_OK) return s;
+  launch_twiddles(const_cast<float2*>(bt.tw_x), nx, st);
+  if (ny != nx) launch_twiddles(const_cast<float2*>(bt.tw_y), ny, st);
+  else bt.tw_y = bt.tw_x;
+  launch_setup(bt, 1, 0, st);
+  launch_col(bt, 1, COL_OSPR_FIRST, 1, adaptive, nullptr, nullptr, st);
+  for (int n = 1; n <= subframes; ++n) {
+    launch_row(bt, 1, false, ROW_OSPR, n, nullptr, nullptr, st);
+    launch_col(bt, 1, n == subframes ? COL_OSPR_FINAL : COL_OSPR, n + 1, adaptive, nullptr, nullptr, st);
+  }
+  hipLaunchKernelGGL(k_finish, dim3(1, (subframes + 255) / 256), dim3(256), 0, st, bt, 1, 1);
+  return check_launch();
+}
+
+hg_status hg_fresnel_propagate(const hg_complex* in, hg_complex* out, int ny, int nx, double wavelength_m,
+                               double pitch_m, double z_m, int direction, void* workspace, size_t workspace_bytes,
+                               void* stream) {
+  g_err[0] = 0;
+  if (!pow2_in_range(ny) || !pow2_in_range(nx))
+    return fail(HG_ERR_UNSUPPORTED_SIZE, "ny=%d nx=%d: each must be a power of two in [64, 4096]", ny, nx);
+  if (!in || !out) return fail(HG_ERR_INVALID_ARG, "in and out must be non-NULL");
+  if (direction != 1 && direction != -1) return fail(HG_ERR_INVALID_ARG, "direction must be +1 or -1");
+  const bool fres = is_fresnel(wavelength_m, pitch_m, z_m);
+  if (fres && !(wavelength_m > 0.0 && pitch_m > 0.0 && std::isfinite(wavelength_m) && std::isfinite(pitch_m)))
+    return fail(HG_ERR_INVALID_ARG, "Fresnel needs wavelength_m > 0 and pitch_m > 0");
+  const Layout Lo = make_prop_layout(ny, nx);
+  hg_status s = check_ws(workspace, workspace_bytes, Lo.total);
+  if (s != HG_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Batch bt{};
+  bt.tw_x = at<float2>(workspace, Lo.twx);
+  bt.tw_y = ny != nx ? at<float2>(workspace, Lo.twy) : bt.tw_x;
+  bt.chirp = at<float2>(workspace, Lo.chirp);
+  bt.ny = ny;
+  bt.nx = nx;
+  launch_twiddles(const_cast<float2*>(bt.tw_x), nx, st);
+  if (ny != nx) launch_twiddles(const_cast<float2*>(bt.tw_y), ny, st);
+  if (fres) launch_chirps(const_cast<float2*>(bt.chirp), ny, nx, {chirp_rate(wavelength_m, pitch_m, z_m)}, st);
+  const float2* fin = reinterpret_cast<const float2*>(in);
+  float2* fout = reinterpret_cast<float2*>(out);
+  if (direction > 0) {
+    launch_row(bt, 1, fres, ROW_PROP_FWD, 0, fin, fout, st);
+    launch_col(bt, 1, COL_PROP_FWD, 0, 0, fout, fout, st);
+  } else {
+    launch_col(bt, 1, COL_PROP_BWD, 0, 0, fin, fout, st);
+    launch_row(bt, 1, fres, ROW_PROP_BWD, 0, fout, fout, st);
+  }
+  return check_launch();
+}
+
+hg_status hg_random_phase(uint64_t seed, uint32_t item, uint32_t tag, int ny, int nx, hg_complex* out,
+                          void* stream) {
+  g_err[0] = 0;
+  if (!pow2_in_range(ny) || !pow2_in_range(nx))
+    return fail(HG_ERR_UNSUPPORTED_SIZE, "ny=%d nx=%d: each must be a power of two in [64, 4096]", ny, nx);
+  if (!out) return fail(HG_ERR_INVALID_ARG, "out is NULL");
+  const int npix = ny * nx;
+  hipLaunchKernelGGL(k_random_phase, dim3((npix + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     reinterpret_cast<float2*>(out), seed, item, tag, npix);
+  return check_launch();
+}
+
+size_t hg_gs_batched_workspace_size(const hg_problem* probs, int count) {
+  if (!probs || count < 1) return 0;
+  std::vector<std::pair<int, int>> order;
+  std::map<std::pair<int, int>, std::pair<int, int>> cls;  // (ny,nx) -> (count, kmax)
+  for (int i = 0; i < count; ++i) {
+    const hg_problem& p = probs[i];
+    if (!pow2_in_range(p.ny) || !pow2_in_range(p.nx) || p.iters < 1) return 0;
+    auto key = std::make_pair(p.ny, p.nx);
+    auto it = cls.find(key);
+    if (it == cls.end()) { cls[key] = {1, p.iters}; order.push_back(key); }
+    else { it->second.first++; it->second.second = std::max(it->second.second, p.iters); }
+  }
+  size_t total = 0;
+  for (auto& k : order) {
+    // the weighted layout is the larger one; one query serves both modes
+    total += make_layout(HG_OP_WGS, k.first, k.second, cls[k].first, cls[k].second).total;
+  }
+  return total;
+}
+
+hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* workspace, size_t workspace_bytes,
+                        void* stream) {
+  g_err[0] = 0;
+  if (!probs || count < 1) return fail(HG_ERR_INVALID_ARG, "problems is NULL or count < 1");
+  for (int i = 0; i < count; ++i) {
+    const hg_problem& p = probs[i];
+    hg_status s = check_common(p.target, p.ny, p.nx, p.iters, p.slm_levels);
+    if (s != HG_OK) return fail(s, "problem %d: %s", i, g_err);
+    if (p.slm_levels >= 2 && !p.levels_out) return fail(HG_ERR_INVALID_ARG, "problem %d: levels_out required", i);
+    if (is_fresnel(p.wavelength_m, p.pitch_m, p.z_m) &&
+        !(p.wavelength_m > 0.0 && p.pitch_m > 0.0 && std::isfinite(p.wavelength_m) && std::isfinite(p.pitch_m)))
+      return fail(HG_ERR_INVALID_ARG, "problem %d: Fresnel needs wavelength_m > 0 and pitch_m > 0", i);
+  }
+  const size_t need = hg_gs_batched_workspace_size(probs, count);
+  hg_status s = check_ws(workspace, workspace_bytes, need);
+  if (s != HG_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<std::pair<int, int>> order;
+  std::map<std::pair<int, int>, std::vector<int>> members;
+  for (int i = 0; i < count; ++i) {
+    auto key = std::make_pair(probs[i].ny, probs[i].nx);
+    if (!members.count(key)) order.push_back(key);
+    members[key].push_back(i);
+  }
+  size_t off = 0;
+  for (auto& key : order) {
+    const std::vector<int>& idx = members[key];
+    std::vector<Desc> ds;
+    std::vector<double> rates;
+    int kmax = 0;
+    for (int i : idx) {
+      const hg_problem& p = probs[i];
+      Desc d{};
+      d.target = p.target;
+      d.levels_out = p.levels_out;
+      d.nmse_out = p.nmse_out;
+      d.seed = p.seed;
+      d.item = (uint32_t)i;
+      d.L = p.slm_levels;
+      d.iters = p.iters;
+      ds.push_back(d);
+      rates.push_back(chirp_rate(p.wavelength_m, p.pitch_m, p.z_m));
+      kmax = std::max(kmax, p.iters);
+    }
+    const Layout Lo = make_layout(HG_OP_WGS, key.first, key.second, (int)idx.size(), kmax);
+    s = run_gs_class(key.first, key.second, ds, rates, weighted != 0, static_cast<char*>(workspace) + off, Lo, st);
+    if (s != HG_OK) return s;
+    off += Lo.total;
+  }
+  return HG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,512 @@
+// Kernels of the hologram hot path for gfx950.
+//
+// One iteration of GS / weighted GS is two passes over the complex64 SLM
+// field held in one HBM buffer in natural [y][x] order:
+//   column pass: forward column FFT -> replay constraint (+ NMSE partials,
+//                weights) -> inverse column FFT, one workgroup per tile of C
+//                columns, the whole column resident in registers + LDS;
+//   row pass:    inverse row FFT -> SLM projection -> forward row FFT, one
+//                group of NX/E threads per row.
+// Both passes read and write every pixel exactly once (16 B/px each).  The
+// replay plane is centred by modulating the SLM plane with (-1)^(x+y) (the
+// DFT shift theorem), folded into the Fresnel chirp for Fresnel holograms,
+// so target, weights and replay share the field's natural layout.
+#pragma once
+#include "hg_device.hpp"
+
+namespace hg {
+
+constexpr int kMaxWaves = 16;
+
+// Per-problem descriptor (device memory).  Replay-plane arrays are centred.
+struct Desc {
+  const float* target;        // raw target amplitude [ny][nx]
+  uint8_t* levels_out;        // final levels (GS) or [subframes][ny][nx] (OSPR)
+  double* nmse_out;           // iters+1 (GS) or subframes (OSPR)
+  float2* field_out;          // final SLM field (nullable)
+  float2* replay_out;         // final centred replay (nullable)
+  float* weights;             // WGS weights: user buffer or workspace
+  const uint8_t* init_levels; // nullable
+  const float2* init_field;   // nullable
+  float* accum_out;           // OSPR accumulator out (nullable)
+  uint64_t seed;
+  uint32_t item;              // Philox item
+  int L;                      // SLM levels (0 = continuous)
+  int iters;                  // GS iterations / OSPR subframes
+  int user_weights;           // weights came from the caller
+  int pad_;
+};
+
+// Launch-uniform view of one size class of problems (passed by value).
+struct Batch {
+  const Desc* desc;
+  float2* field;        // [B][ny][nx]
+  float* tprep;         // [B][ny][nx] prepared target
+  float* wbuf;          // [B][ny][nx] workspace weights (if not user-owned)
+  float* accum;         // [B][ny][nx] OSPR accumulator
+  const float2* tw_x;   // nx twiddles exp(-2 pi i m / nx)
+  const float2* tw_y;   // ny twiddles
+  const float2* chirp;  // [B][nx + ny]: cx[x] (-1)^x, then cy[y] (-1)^y
+  double* part;         // [B][slots][nblk][4] partial sums
+  int ny, nx;
+  int nblk;             // column tiles per problem (= nx / C)
+  int slots;            // partial slots per problem
+  float fwd_scale;      // 1/sqrt(nx ny)
+  int pad_;
+};
+
+__device__ __forceinline__ double* part_ptr(const Batch& bt, int b, int slot, int blk) {
+  return bt.part + (((size_t)b * bt.slots + slot) * bt.nblk + blk) * 4;
+}
+
+// ---------------------------------------------------------------------------
+// LDS exchange policies
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+
+// Row transforms: private LDS region per row, ping-pong buffers so each
+// exchange needs one barrier.
+struct RowEx {
+  float2* b[2];
+  int w, rd;
+  __device__ void before_read() { __syncthreads(); rd = w; w ^= 1; }
+  __device__ void before_write() {}
+  __device__ float2 read(int i) const { return b[rd][lds_pad(i)]; }
+  __device__ void write(int i, float2 v) { b[w][lds_pad(i)] = v; }
+};
+
+// Column tile: C interleaved columns, element (i, c) at pad(i) * C + c.
+// Single buffer (the tile is large): barrier before reads and before writes.
+template <int C> struct ColEx {
+  float2* s;
+  int c;
+  __device__ void before_read() { __syncthreads(); }
+  __device__ void before_write() { __syncthreads(); }
+  __device__ float2 read(int i) const { return s[lds_pad(i) * C + c]; }
+  __device__ void write(int i, float2 v) { s[lds_pad(i) * C + c] = v; }
+};
+
+// ---------------------------------------------------------------------------
+// deterministic block reduction of 4 float sums into FP64
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int NT>
+__device__ __forceinline__ void block_sum4(float a0, float a1, float a2, float a3, double (&red)[kMaxWaves][4],
+                                           double (&tot)[4]) {
+  constexpr int NW = (NT + 63) / 64;
+  const double d0 = wave_sum((double)a0), d1 = wave_sum((double)a1);
+  const double d2 = wave_sum((double)a2), d3 = wave_sum((double)a3);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) { red[wv][0] = d0; red[wv][1] = d1; red[wv][2] = d2; red[wv][3] = d3; }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double acc = 0.0;
+    for (int w = 0; w < NW; ++w) acc += red[w][threadIdx.x];
+    tot[threadIdx.x] = acc;
+  }
+  __syncthreads();
+}
+
+// Sum field `f` of slot `slot` over all nblk blocks of problem b, in a fixed
+// order (every block computes the identical value).
+template <int NT>
+__device__ __forceinline__ double slot_total(const Batch& bt, int b, int slot, int f, double* bcast) {
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < bt.nblk; i += 64) s += part_ptr(bt, b, slot, i)[f];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) *bcast = s;
+  }
+  __syncthreads();
+  return *bcast;
+}
+
+// ---------------------------------------------------------------------------
+// table kernels (FP64 arithmetic, stored as complex64)
+// ---------------------------------------------------------------------------
+__global__ void k_twiddles(float2* tw, int n) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  double s, c;
+  sincospi(2.0 * (double)m / (double)n, &s, &c);
+  tw[m] = make_float2((float)c, (float)-s);
+}
+
+// cx[x] = exp(i pi p^2 (x - nx/2)^2 / (lambda z)) (-1)^x, then cy likewise.
+// a = p^2 / (lambda z) (0 for Fourier); phase in half-turns = a d^2, reduced
+// exactly mod 2 before the FP64 sincospi.
+struct ChirpArgs { double a[32]; int count; };
+__global__ void k_chirps(float2* chirp, int ny, int nx, ChirpArgs ca, int first) {
+  const int b = blockIdx.y;
+  if (b >= ca.count) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nx + ny) return;
+  const bool isx = i < nx;
+  const int q = isx ? i : i - nx;
+  const int n = isx ? nx : ny;
+  const double d = (double)(q - n / 2);
+  double ht = fmod(ca.a[b] * d * d, 2.0);
+  if (q & 1) ht += 1.0;
+  double s, c;
+  sincospi(ht, &s, &c);
+  chirp[(size_t)(first + b) * (nx + ny) + i] = make_float2((float)c, (float)s);
+}
+
+// ---------------------------------------------------------------------------
+// set-up: target energy, prepared target, weights
+// ---------------------------------------------------------------------------
+// Column-tile elementwise kernels share the column pass's tiling so their
+// block partials line up with its slots.
+template <int NY, int E, int C>
+__global__ __launch_bounds__(C * (NY / E)) void k_energy(Batch bt) {
+  constexpr int T = NY / E, NT = C * T;
+  __shared__ double red[kMaxWaves][4];
+  const int b = blockIdx.y, blk = blockIdx.x;
+  const int c = threadIdx.x % C, t = threadIdx.x / C;
+  const int u = blk * C + c;
+  const float* tg = bt.desc[b].target;
+  float e = 0.0f;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const float v = tg[(size_t)(t + T * j) * bt.nx + u];
+    e += v * v;
+  }
+  __shared__ double tot[4];
+  block_sum4<NT>(e, 0.f, 0.f, 0.f, red, tot);
+  if (threadIdx.x == 0) part_ptr(bt, b, bt.slots - 1, blk)[0] = tot[0];
+}
+
+template <int NY, int E, int C>
+__global__ __launch_bounds__(C * (NY / E)) void k_prepare(Batch bt, int weighted) {
+  constexpr int T = NY / E, NT = C * T;
+  __shared__ double red[kMaxWaves][4];
+  __shared__ double bc;
+  const int b = blockIdx.y, blk = blockIdx.x;
+  const int c = threadIdx.x % C, t = threadIdx.x / C;
+  const int u = blk * C + c;
+  const Desc& d = bt.desc[b];
+  const double e = slot_total<NT>(bt, b, bt.slots - 1, 0, &bc);
+  const float scale = (float)sqrt((double)bt.nx * (double)bt.ny / e);
+  const size_t off = (size_t)b * bt.ny * bt.nx;
+  float* w = d.user_weights ? d.weights : bt.wbuf + off;
+  float om = 0.f, ws = 0.f;
+  const int um = (bt.nx - u) & (bt.nx - 1);
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int v = t + T * j;
+    const size_t idx = (size_t)v * bt.nx + u;
+    float tv = d.target[idx];
+    if (d.L == 2) {
+      const int vm = (bt.ny - v) & (bt.ny - 1);
+      const float tm = d.target[(size_t)vm * bt.nx + um];
+      tv = sqrtf(0.5f * (tv * tv + tm * tm));
+    }
+    tv *= scale;
+    bt.tprep[off + idx] = tv;
+    if (weighted) {
+      float wv = 1.0f;
+      if (d.user_weights) wv = w[idx]; else w[idx] = 1.0f;
+      if (tv > 0.f) { om += 1.f; ws += wv; }
+    }
+  }
+  if (weighted) {
+    // slot slots-1 field 1: |Omega|; slot 0 field 3: sum of w_0 over Omega
+    __shared__ double tmp[4];
+    block_sum4<NT>(om, ws, 0.f, 0.f, red, tmp);
+    if (threadIdx.x == 0) {
+      part_ptr(bt, b, bt.slots - 1, blk)[1] = tmp[0];
+      part_ptr(bt, b, 0, blk)[3] = tmp[1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// row pass
+// ---------------------------------------------------------------------------
+enum RowMode { ROW_INIT = 0, ROW_ITER = 1, ROW_OSPR = 2, ROW_PROP_FWD = 3, ROW_PROP_BWD = 4 };
+
+// Modulation m[y][x] applied before the forward row FFT and conjugated after
+// the inverse one: (-1)^(x+y) for Fourier, chirp * (-1)^(x+y) for Fresnel.
+template <bool FRESNEL>
+__device__ __forceinline__ float2 modulate(float2 v, int x, int y, const float2* cx, float2 cyv, bool conj) {
+  if constexpr (FRESNEL) {
+    const float2 m = cmul(cx[x], cyv);
+    return conj ? cmulc(v, m) : cmul(v, m);
+  } else {
+    return ((x + y) & 1) ? make_float2(-v.x, -v.y) : v;
+  }
+}
+
+// mode      ROW_INIT: build f0, forward FFT.  ROW_ITER: inverse FFT, project,
+//           forward FFT (iteration k = arg).  ROW_OSPR: same with L = 2 and
+//           the levels of subframe arg written.  ROW_PROP_*: propagation.
+template <int NX, int E, int RPB, bool FRESNEL>
+__global__ __launch_bounds__(RPB * (NX / E)) void k_row(Batch bt, int mode, int arg, const float2* pin, float2* pout) {
+  using P = Plan<NX, E>;
+  constexpr int T = P::T;
+  constexpr int NT = RPB * T;
+  constexpr int LW = NX + NX / 16;
+  constexpr bool XCH = P::ns > 1;
+  __shared__ float2 lds[XCH ? RPB * 2 * LW : 1];
+  const int b = blockIdx.y;
+  const int r = threadIdx.x / T, t = threadIdx.x % T;
+  const int y = blockIdx.x * RPB + r;
+  const size_t off = (size_t)b * bt.ny * NX;
+  float2* row = bt.field + off + (size_t)y * NX;
+  const float2* cx = bt.chirp + (size_t)b * (NX + bt.ny);
+  const float2 cyv = FRESNEL ? cx[NX + y] : make_float2(1.f, 0.f);
+  RowEx ex;
+  ex.b[0] = lds + (XCH ? r * 2 * LW : 0);
+  ex.b[1] = ex.b[0] + (XCH ? LW : 0);
+  ex.w = 0;
+  ex.rd = 0;
+  float2 v[E];
+
+  if (mode == ROW_PROP_FWD || mode == ROW_PROP_BWD) {
+    const float2* src = pin + off + (size_t)y * NX;
+    float2* dst = pout + off + (size_t)y * NX;
+    const float s = rsqrtf((float)NX);
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = src[t + T * j];
+    if (mode == ROW_PROP_FWD) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = cscale(modulate<FRESNEL>(v[j], t + T * j, y, cx, cyv, false), s);
+      fft<NX, E, -1>(v, t, bt.tw_x, ex);
+    } else {
+      fft<NX, E, +1>(v, t, bt.tw_x, ex);
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = cscale(modulate<FRESNEL>(v[j], t + T * j, y, cx, cyv, true), s);
+    }
+#pragma unroll
+    for (int j = 0; j < E; ++j) dst[t + T * j] = v[j];
+    return;
+  }
+
+  const Desc& d = bt.desc[b];
+  if (mode == ROW_ITER && arg > d.iters) return;  // uniform per block
+  if (mode == ROW_INIT) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int x = t + T * j;
+      const size_t idx = (size_t)y * NX + x;
+      float2 f;
+      if (d.init_field) f = d.init_field[idx];
+      else if (d.init_levels) f = level_phasor(d.init_levels[idx], d.L);
+      else f = philox_phasor(philox_pixel_word(d.seed, d.item, 1u, idx));
+      v[j] = modulate<FRESNEL>(f, x, y, cx, cyv, false);
+    }
+  } else {
+    const int L = (mode == ROW_OSPR) ? 2 : d.L;
+    const bool last = (mode == ROW_OSPR) || (arg == d.iters);
+    uint8_t* lev = d.levels_out;
+    if (mode == ROW_OSPR) lev += (size_t)(arg - 1) * bt.ny * NX;
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = row[t + T * j];
+    fft<NX, E, +1>(v, t, bt.tw_x, ex);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int x = t + T * j;
+      const float2 g = modulate<FRESNEL>(v[j], x, y, cx, cyv, true);
+      float2 f;
+      if (L == 0) {
+        f = unit_phase(g);
+      } else {
+        const int k = level_index(g, L);
+        f = level_phasor(k, L);
+        if (last && lev) lev[(size_t)y * NX + x] = (uint8_t)k;
+      }
+      if (last && d.field_out && mode != ROW_OSPR) d.field_out[(size_t)y * NX + x] = f;
+      v[j] = modulate<FRESNEL>(f, x, y, cx, cyv, false);
+    }
+  }
+  fft<NX, E, -1>(v, t, bt.tw_x, ex);
+#pragma unroll
+  for (int j = 0; j < E; ++j) row[t + T * j] = v[j];
+}
+
+// ---------------------------------------------------------------------------
+// column pass
+// ---------------------------------------------------------------------------
+enum ColMode {
+  COL_GS = 0,          // iteration k = arg: partials for nmse[k-1], R' = T R/|R|
+  COL_WGS = 1,         // as COL_GS with the weight update
+  COL_OSPR_FIRST = 3,  // T e^{i phi_1} -> inverse FFT
+  COL_OSPR = 4,        // subframe arg >= 2: finish subframe arg-1, start arg
+  COL_OSPR_FINAL = 5,  // finish the last subframe
+  COL_PROP_FWD = 6,
+  COL_PROP_BWD = 7
+};
+
+// weighted GS: amplitude floor (unit-rms units), leak exponent, clamp
+constexpr float kWgsEps = 0.1f, kWgsGamma = 0.7f, kWMin = 1e-6f, kWMax = 1e6f;
+
+template <int NY, int E, int C>
+__global__ __launch_bounds__(C * (NY / E)) void k_col(Batch bt, int mode, int arg, int adaptive,
+                                                      const float2* pin, float2* pout) {
+  using P = Plan<NY, E>;
+  constexpr int T = P::T, NT = C * T;
+  __shared__ float2 lds[(NY + NY / 16) * C];
+  __shared__ double red[kMaxWaves][4];
+  __shared__ double bc;
+  const int b = blockIdx.y, blk = blockIdx.x;
+  const int c = threadIdx.x % C, t = threadIdx.x / C;
+  const int u = blk * C + c;
+  const int NX = bt.nx;
+  const size_t off = (size_t)b * NY * NX;
+  float2* fld = bt.field + off;
+  ColEx<C> ex{lds, c};
+  float2 v[E];
+
+  if (mode == COL_PROP_FWD || mode == COL_PROP_BWD) {
+    const float2* src = pin + off;
+    float2* dst = pout + off;
+    const float s = rsqrtf((float)NY);
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = src[(size_t)(t + T * j) * NX + u];
+    if (mode == COL_PROP_FWD) fft<NY, E, -1>(v, t, bt.tw_y, ex);
+    else fft<NY, E, +1>(v, t, bt.tw_y, ex);
+#pragma unroll
+    for (int j = 0; j < E; ++j) dst[(size_t)(t + T * j) * NX + u] = cscale(v[j], s);
+    return;
+  }
+
+  const Desc& d = bt.desc[b];
+  const float* tp = bt.tprep + off;
+  __shared__ double tot[4];
+  float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f, s_w = 0.f;
+
+  if (mode == COL_GS || mode == COL_WGS) {
+    // column pass k of a problem with K iterations: k <= K iterates, k = K + 1
+    // only measures the final field (NMSE, replay out), k > K + 1 is idle.
+    const int k = arg;
+    if (k > d.iters + 1) return;  // uniform per block
+    const bool fin = (k == d.iters + 1);
+    float m_prev = 1.0f;
+    float* w = nullptr;
+    if (mode == COL_WGS && !fin) {
+      const double om = slot_total<NT>(bt, b, bt.slots - 1, 1, &bc);
+      const double wsum = slot_total<NT>(bt, b, k - 1, 3, &bc);
+      m_prev = (float)(wsum / (om > 0.0 ? om : 1.0));
+      w = d.user_weights ? d.weights : bt.wbuf + off;
+    }
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = fld[(size_t)(t + T * j) * NX + u];
+    fft<NY, E, -1>(v, t, bt.tw_y, ex);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const size_t idx = (size_t)(t + T * j) * NX + u;
+      const float2 Rr = v[j];  // unscaled replay, centred index (t + T j, u)
+      const float a2 = Rr.x * Rr.x + Rr.y * Rr.y;
+      const float inv = a2 > 0.f ? rsqrtf(a2) : 0.f;
+      const float A = a2 * inv * bt.fwd_scale;  // |R| of the unitary transform
+      const float Tv = tp[idx];
+      s_ta += Tv * A;
+      s_aa += A * A;
+      s_tt += Tv * Tv;
+      if (fin) {
+        if (d.replay_out) d.replay_out[idx] = cscale(Rr, bt.fwd_scale);
+        continue;
+      }
+      float amp = Tv;
+      if (mode == COL_WGS && Tv > 0.f) {
+        const float ratio = fmaxf(Tv, kWgsEps) / fmaxf(A, kWgsEps);
+        const float wn = powf(fminf(fmaxf(w[idx] * ratio / m_prev, kWMin), kWMax), kWgsGamma);
+        w[idx] = wn;
+        s_w += wn;
+        amp = wn * Tv;
+      }
+      v[j] = a2 > 0.f ? cscale(Rr, amp * inv) : make_float2(amp, 0.f);
+    }
+    block_sum4<NT>(s_ta, s_aa, s_tt, s_w, red, tot);
+    if (threadIdx.x == 0) {
+      double* pp = part_ptr(bt, b, k - 1, blk);
+      pp[0] = tot[0]; pp[1] = tot[1]; pp[2] = tot[2];
+      if (mode == COL_WGS && !fin) part_ptr(bt, b, k, blk)[3] = tot[3];
+    }
+    if (fin) return;
+    fft<NY, E, +1>(v, t, bt.tw_y, ex);
+#pragma unroll
+    for (int j = 0; j < E; ++j) fld[(size_t)(t + T * j) * NX + u] = v[j];
+    return;
+  }
+
+  // OSPR.  Subframe n's column work: finish subframe n-1 (forward FFT,
+  // accumulate, NMSE partials, feedback), then start subframe n (random
+  // replay phase, inverse FFT).
+  const int n = arg;
+  const int N = d.iters;
+  float* acc = bt.accum + off;
+  if (mode != COL_OSPR_FIRST) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = fld[(size_t)(t + T * j) * NX + u];
+    fft<NY, E, -1>(v, t, bt.tw_y, ex);
+  }
+  const float inv_prev = 1.0f / (float)(n - 1);
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int row = t + T * j;
+    const size_t idx = (size_t)row * NX + u;
+    const float Tv = tp[idx];
+    float Tn = Tv;
+    if (mode != COL_OSPR_FIRST) {
+      const float2 R = cscale(v[j], bt.fwd_scale);
+      const float a = (n == 2 ? 0.f : acc[idx]) + (R.x * R.x + R.y * R.y);  // A_{n-1}
+      if (mode == COL_OSPR_FINAL) {
+        if (d.accum_out) d.accum_out[idx] = a;
+      } else {
+        acc[idx] = a;
+      }
+      const float avg = a * inv_prev;
+      s_ta += Tv * sqrtf(avg);
+      s_aa += avg;
+      s_tt += Tv * Tv;
+      if (adaptive) Tn = sqrtf(fmaxf(0.f, (float)n * Tv * Tv - a));
+    }
+    if (mode != COL_OSPR_FINAL) {
+      const float2 ph = philox_phasor(philox_pixel_word(d.seed, d.item, 0x100u + (uint32_t)n, idx));
+      v[j] = cscale(ph, Tn);
+    }
+  }
+  if (mode != COL_OSPR_FIRST) {
+    block_sum4<NT>(s_ta, s_aa, s_tt, 0.f, red, tot);
+    if (threadIdx.x == 0) {
+      double* pp = part_ptr(bt, b, n - 2, blk);
+      pp[0] = tot[0]; pp[1] = tot[1]; pp[2] = tot[2];
+    }
+  }
+  if (mode == COL_OSPR_FINAL) return;
+  fft<NY, E, +1>(v, t, bt.tw_y, ex);
+#pragma unroll
+  for (int j = 0; j < E; ++j) fld[(size_t)(t + T * j) * NX + u] = v[j];
+}
+
+__global__ void k_random_phase(float2* out, uint64_t seed, uint32_t item, uint32_t tag, int npix) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  out[p] = philox_phasor(philox_pixel_word(seed, item, tag, (uint64_t)p));
+}
+
+// nmse[k] = 1 - sta^2 / (stt saa) from the block partials of slot k; a GS
+// problem has iters + 1 values, an OSPR problem `iters` (= subframes).
+__global__ void k_finish(Batch bt, int count, int ospr) {
+  const int b = blockIdx.x;
+  const int k = threadIdx.x + blockIdx.y * blockDim.x;
+  if (b >= count) return;
+  const Desc& d = bt.desc[b];
+  if (!d.nmse_out || k >= d.iters + (ospr ? 0 : 1)) return;
+  double sta = 0.0, saa = 0.0, stt = 0.0;
+  for (int i = 0; i < bt.nblk; ++i) {
+    const double* pp = part_ptr(bt, b, k, i);
+    sta += pp[0]; saa += pp[1]; stt += pp[2];
+  }
+  d.nmse_out[k] = (saa > 0.0 && stt > 0.0) ? 1.0 - sta * sta / (stt * saa) : 1.0;
+}
+
+}  // namespace hg

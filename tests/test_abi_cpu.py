@@ -1,0 +1,86 @@
+"""C-ABI checks that need no GPU: exported symbols, status strings, workspace
+queries and host-side argument validation (which runs before any HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2008_12214_amd as hg
+from conftest import ROOT
+
+L = hg.lib()
+FAKE = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
+
+
+def test_every_declared_symbol_is_exported():
+    hdr = open(os.path.join(ROOT, "include", "hologen.h")).read()
+    names = set(re.findall(r"\b(hg_[a-z_]+)\s*\(", hdr))
+    assert {"hg_gs", "hg_wgs", "hg_ospr", "hg_fresnel_propagate", "hg_gs_batched"} <= names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings():
+    for s in range(5):
+        assert hg.hg_status_string(s)
+    assert hg.hg_status_string(99) == "unknown status"
+
+
+def test_workspace_queries():
+    g = hg.hg_workspace_size(hg.HG_OP_GS, 1024, 1024, 100)
+    w = hg.hg_workspace_size(hg.HG_OP_WGS, 1024, 1024, 100)
+    o = hg.hg_workspace_size(hg.HG_OP_OSPR, 512, 512, 24)
+    assert g >= 1024 * 1024 * 12 and w >= g + 1024 * 1024 * 4 and o >= 512 * 512 * 16
+    assert hg.hg_workspace_size(hg.HG_OP_GS, 1000, 1024, 10) == 0
+    assert hg.hg_workspace_size(hg.HG_OP_GS, 32, 32, 10) == 0
+    assert hg.hg_workspace_size(hg.HG_OP_GS, 8192, 64, 10) == 0
+    assert hg.hg_workspace_size(hg.HG_OP_GS, 64, 64, 0) == 0
+    assert hg.hg_workspace_size(99, 64, 64, 1) == 0
+    assert hg.hg_workspace_size(hg.HG_OP_PROPAGATE, 64, 4096, 0) > 0
+
+
+def _gs(target=FAKE, ny=64, nx=64, iters=5, levels=8, levels_out=FAKE, ws=FAKE, wsb=1 << 30, init_levels=None,
+        z=0.0, lam=0.0, pitch=0.0):
+    return L.hg_gs(target, ny, nx, iters, levels, 1, init_levels, None, lam, pitch, z, levels_out, None, None,
+                   None, ws, wsb, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(ny=100), hg.HG_ERR_UNSUPPORTED_SIZE),
+    (dict(nx=32), hg.HG_ERR_UNSUPPORTED_SIZE),
+    (dict(nx=8192), hg.HG_ERR_UNSUPPORTED_SIZE),
+    (dict(target=None), hg.HG_ERR_INVALID_ARG),
+    (dict(iters=0), hg.HG_ERR_INVALID_ARG),
+    (dict(levels=1), hg.HG_ERR_INVALID_ARG),
+    (dict(levels=257), hg.HG_ERR_INVALID_ARG),
+    (dict(levels_out=None), hg.HG_ERR_INVALID_ARG),
+    (dict(levels=0, init_levels=FAKE), hg.HG_ERR_INVALID_ARG),
+    (dict(z=0.1, lam=0.0, pitch=8e-6), hg.HG_ERR_INVALID_ARG),
+    (dict(ws=None), hg.HG_ERR_WORKSPACE),
+    (dict(ws=ctypes.c_void_p(0x10010)), hg.HG_ERR_WORKSPACE),
+    (dict(wsb=1024), hg.HG_ERR_WORKSPACE),
+])
+def test_gs_validation(kw, status):
+    assert _gs(**kw) == status
+    assert hg.hg_last_error() != ""
+
+
+def test_wgs_ospr_propagate_batched_validation():
+    assert L.hg_wgs(FAKE, 64, 64, 0, 2, 1, None, None, 0.0, 0.0, 0.0, FAKE, None, None, None, None, FAKE, 1 << 30,
+                    None) == hg.HG_ERR_INVALID_ARG
+    assert L.hg_ospr(FAKE, 64, 64, 4, 1, 1, None, None, None, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG
+    assert L.hg_ospr(FAKE, 64, 64, 4, 1, 1, FAKE, None, None, FAKE, 16, None) == hg.HG_ERR_WORKSPACE
+    assert L.hg_fresnel_propagate(FAKE, FAKE, 64, 64, 0.0, 0.0, 0.0, 0, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG
+    assert L.hg_fresnel_propagate(None, FAKE, 64, 64, 0.0, 0.0, 0.0, 1, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG
+    assert L.hg_random_phase(1, 0, 1, 48, 64, FAKE, None) == hg.HG_ERR_UNSUPPORTED_SIZE
+    assert L.hg_gs_batched(None, 0, 0, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG
+    probs = (hg._binding.hg_problem * 2)()
+    probs[0] = hg._binding.hg_problem(64, 64, 8, 3, 1, 0, 0, 0, 0x10000, 0x10000, None)
+    probs[1] = hg._binding.hg_problem(128, 64, 8, 3, 1, 0, 0, 0, 0x10000, None, None)
+    assert L.hg_gs_batched(probs, 2, 0, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG
+    assert "problem 1" in hg.hg_last_error()
+    probs[1] = hg._binding.hg_problem(128, 64, 8, 3, 1, 0, 0, 0, 0x10000, 0x10000, None)
+    need = L.hg_gs_batched_workspace_size(probs, 2)
+    assert need > L.hg_workspace_size(hg.HG_OP_WGS, 64, 64, 3)
+    assert L.hg_gs_batched(probs, 2, 0, FAKE, need - 256, None) == hg.HG_ERR_WORKSPACE

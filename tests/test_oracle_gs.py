@@ -170,3 +170,15 @@ def test_direct_search_on_8x8_reaches_local_minimum():
     # exhaustive over 16 free pixels around the DS optimum cannot lose to it
     _, e16 = search.exhaustive(T, 2, free=range(16), base_levels=lev)
     assert e16 <= e + 1e-9
+
+
+@pytest.mark.parametrize("L", [2, 8])
+def test_weighting_improves_convergence(L):
+    # Iterative Fourier Transform Algorithms section: weighting is a GS
+    # variant that improves convergence; the weights stay bounded
+    T = synth.gaussian_target(64, seed=2)
+    plain = hologram.gs(T, 40, L, seed=1)
+    wgs = hologram.gs(T, 40, L, seed=1, weighted=True)
+    assert wgs["nmse"][-1] < plain["nmse"][-1]
+    om = wgs["target"] > 0
+    assert 1e-4 < wgs["weights"][om].min() and wgs["weights"][om].max() < 1e2
