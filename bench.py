@@ -26,12 +26,12 @@ sys.path.insert(0, ROOT)
 METRIC = "GS iter/s at 1024^2 c64 (%HBM peak); time-to-NMSE learned-init vs plain GS"
 HBM_PEAK_GBS = 8000.0
 N = 1024
-ITERS = 100
 LEVELS = 2
 # algorithmic HBM bytes per pixel: weighted column pass = field r+w (16) +
 # target r (4) + weights r+w (8); its final launch (NMSE only) = field r (8)
 # + target r (4); row pass = field r+w (16), + levels w (1) on the last.
 COL_BYTES, COL_FINAL_BYTES, ROW_BYTES = 28, 12, 16
+ITERS = 100
 
 
 def log(*a):
@@ -69,7 +69,11 @@ def main():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-b1", action="store_true")
+    ap.add_argument("--iters", type=int, default=100,
+                    help="iterations per hologram (100 is the workload; fewer only for short profiles)")
     args = ap.parse_args()
+    global ITERS
+    ITERS = args.iters
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -166,7 +170,7 @@ def main():
                    "slm_levels": LEVELS, "target": "gaussian sum, 32 blobs, central window"},
         "roofline": {"bound": "hbm", "achieved": round(col_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(col_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "column pass k_col<1024,16,8> (weighted)",
+                     "kernel": "column pass k_col<1024,C,COL_WGS> (weighted GS)",
                      "bytes_per_launch": int(col_bytes / kt["col_launches"]),
                      "avg_launch_us": round(col_avg_ms * 1e3, 2)},
         "cpu_baseline": cpu,

@@ -35,9 +35,12 @@
  *    1 - (sum T A)^2 / (sum T^2 sum A^2), sums in FP64 ("Error Metrics"
  *    section, Eq. mse, at the best uniform scale).
  *  - Random phases come from Philox4x64-10 (Salmon et al., SC'11) with key
- *    (seed, (item << 32) | tag), counter (p >> 2, 0, 0, 0), word p & 3 for
- *    pixel p = y*Nx + x, phase 2 pi (word >> 40) 2^-24.  Tags: 1 = initial
- *    SLM phase, 0x100 + n = OSPR subframe n.
+ *    (seed, (item << 32) | tag).  The plane is split into lines of length n
+ *    (axis 1: rows, n = nx; axis 0: columns, n = ny); element i of line l
+ *    takes output word (i div n/4) of the block at counter
+ *    (i mod n/4, l, 0, 0), and its phase is 2 pi (word >> 40) 2^-24.
+ *    Tag 1 = initial SLM phase (axis 1); tag 0x100 + n = OSPR subframe n's
+ *    replay phase (axis 0).
  *  - Workspace: `workspace` must hold at least the size returned by the
  *    matching *_workspace_size query, 256-byte aligned.  Its contents need
  *    no initialisation and are clobbered.  Calls that share a workspace
@@ -139,11 +142,11 @@ hg_status hg_fresnel_propagate(const hg_complex* in, hg_complex* out, int ny, in
                                void* workspace, size_t workspace_bytes, void* stream);
 
 /* The random phase field the library draws: out[y][x] = exp(2 pi i u24)
- * with u24 the top 24 bits of the Philox word of pixel p = y*nx + x under
- * key (seed, (item << 32) | tag), as described above.  tag 1 with item 0 is
- * hg_gs's initial SLM phase; tag 0x100 + n is OSPR subframe n's replay
- * phase.  No workspace.                                                      */
-hg_status hg_random_phase(uint64_t seed, uint32_t item, uint32_t tag, int ny, int nx, hg_complex* out,
+ * with u24 the top 24 bits of the Philox word of element (y, x) of stream
+ * (seed, item, tag) split into lines along `axis`, as described above.
+ * (tag 1, axis 1, item 0) is hg_gs's initial SLM phase; (0x100 + n, axis 0)
+ * is OSPR subframe n's replay phase.  No workspace.                         */
+hg_status hg_random_phase(uint64_t seed, uint32_t item, uint32_t tag, int axis, int ny, int nx, hg_complex* out,
                           void* stream);
 
 /* Batch processing (program summary: batch processing of many images):
@@ -163,6 +166,25 @@ typedef struct hg_problem {
 size_t hg_gs_batched_workspace_size(const hg_problem* problems, int count);
 hg_status hg_gs_batched(const hg_problem* problems, int count, int weighted,
                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* Launch configuration and autotuning (the paper's FFT benchmarking, "Fast
+ * Fourier Transforms" section, shows throughput is set by the transform;
+ * the tile schedule that runs it fastest depends on grid size and batch).
+ * Each (ny, nx, batch class) -- batch < 8 or >= 8 -- has a column-tile
+ * width (columns per column-pass workgroup) and a row-pass group size (rows
+ * per workgroup), from a built-in table unless tuned or set.
+ * hg_autotune times every compiled candidate on the device (weighted-GS
+ * column pass, binary row pass, on a synthetic flat target in `workspace`),
+ * keeps the fastest for later calls in this process and returns it.  It
+ * synchronises `stream`.  hg_set_launch_config installs a configuration
+ * (0, 0 restores the built-in table); an uncompiled one is rejected.
+ * Configurations change speed only: results are identical up to the order
+ * of floating-point partial sums in the NMSE reduction.                     */
+size_t hg_autotune_workspace_size(int ny, int nx, int batch);
+hg_status hg_autotune(int ny, int nx, int batch, int* col_tile, int* rows_per_group, void* workspace,
+                      size_t workspace_bytes, void* stream);
+hg_status hg_set_launch_config(int ny, int nx, int batch, int col_tile, int rows_per_group);
+hg_status hg_get_launch_config(int ny, int nx, int batch, int* col_tile, int* rows_per_group);
 
 /* Kernel timing (instrumentation for benchmarks).  While enabled, every
  * launch of a column pass, row pass or set-up kernel made by this process

@@ -12,14 +12,18 @@ products), and permutes/mixes:
 and the key is bumped by the Weyl constants between rounds.
 
 How the hologram method draws its random numbers (a reading; the paper
-does not specify a generator):
+does not specify a generator).  A plane is split into lines of length n
+(rows, n = Nx, for the SLM-plane initial phase; columns, n = Ny, for the
+replay-plane OSPR phases); element i of line l uses
 
     key     = (seed, (b << 32) | tag)     b = batch item (0 unbatched)
-    counter = (p >> 2, 0, 0, 0)           p = y * Nx + x, word p & 3
+    counter = (i mod n/4, l, 0, 0)        one block serves i, i + n/4, i + n/2, i + 3n/4
+    word    = i div (n/4)                 output word 0..3 of the block
     u24     = (word >> 40) * 2^-24        exact in float32 and float64
     phase   = 2 pi u24
 
-Tags: INIT = 1 (initial SLM phase), OSPR subframe n uses 0x100 + n.
+Tags: INIT = 1 (initial SLM phase, row lines), OSPR subframe n uses
+0x100 + n (replay phase, column lines).
 Vectorised with numpy uint64 arithmetic; 64x64->128 products are formed
 from 32-bit halves.
 """
@@ -69,14 +73,23 @@ def philox4x64_10(ctr, key):
     return c0, c1, c2, c3
 
 
-def pixel_words(seed, tag, npix, batch_item=0):
-    """One 64-bit word per pixel index p in [0, npix), mapping above."""
-    p = np.arange(npix, dtype=np.uint64)
-    ctr0 = p >> np.uint64(2)
+def line_words(seed, tag, ny, nx, axis, batch_item=0):
+    """One 64-bit word per element of an ny x nx plane, mapping above.
+
+    axis = 1: lines are rows (i = x, l = y); axis = 0: lines are columns
+    (i = y, l = x).  Returns an (ny, nx) uint64 array.
+    """
+    n, nl = (nx, ny) if axis == 1 else (ny, nx)
+    q = n // 4
+    i = np.arange(q, dtype=np.uint64)
+    l = np.arange(nl, dtype=np.uint64)
+    ctr0 = np.repeat(i[None, :], nl, axis=0).ravel()
+    ctr1 = np.repeat(l[:, None], q, axis=1).ravel()
     z = np.zeros_like(ctr0)
     key = (np.uint64(seed), np.uint64(((batch_item & 0xFFFFFFFF) << 32) | (tag & 0xFFFFFFFF)))
-    words = np.stack(philox4x64_10((ctr0, z, z, z), key), axis=0)  # (4, npix)
-    return words[(p & np.uint64(3)).astype(np.int64), np.arange(npix)]
+    blocks = np.stack(philox4x64_10((ctr0, ctr1, z, z), key), axis=0).reshape(4, nl, q)
+    lines = np.concatenate([blocks[w] for w in range(4)], axis=1)  # (nl, n): word w covers i in [w q, (w+1) q)
+    return lines if axis == 1 else lines.T.copy()
 
 
 def u24(words):
@@ -85,6 +98,9 @@ def u24(words):
 
 
 def phase_field(seed, tag, ny, nx, batch_item=0):
-    """Uniform random phases 2 pi u24 on an Ny x Nx grid (float64)."""
-    w = pixel_words(seed, tag, ny * nx, batch_item)
-    return (2.0 * np.pi * u24(w)).reshape(ny, nx)
+    """Uniform random phases 2 pi u24 on an Ny x Nx grid (float64).
+
+    The initial SLM phase (tag INIT) uses row lines, OSPR phases column lines.
+    """
+    axis = 1 if tag == TAG_INIT else 0
+    return 2.0 * np.pi * u24(line_words(seed, tag, ny, nx, axis, batch_item))

@@ -13,5 +13,5 @@ from ._binding import (  # noqa: F401
     HologenError, lib, lib_path,
     hg_workspace_size, hg_gs, hg_wgs, hg_ospr, hg_fresnel_propagate,
     hg_gs_batched, hg_gs_batched_workspace_size, hg_random_phase, hg_status_string, hg_last_error,
-    hg_timing_enable, hg_timing_read,
+    hg_timing_enable, hg_timing_read, hg_autotune, hg_set_launch_config, hg_get_launch_config,
 )

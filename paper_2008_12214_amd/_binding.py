@@ -70,11 +70,19 @@ def lib():
         L.hg_fresnel_propagate.restype = _i
         L.hg_fresnel_propagate.argtypes = [_vp, _vp, _i, _i, _d, _d, _d, _i, _vp, _sz, _vp]
         L.hg_random_phase.restype = _i
-        L.hg_random_phase.argtypes = [_u64, ctypes.c_uint32, ctypes.c_uint32, _i, _i, _vp, _vp]
+        L.hg_random_phase.argtypes = [_u64, ctypes.c_uint32, ctypes.c_uint32, _i, _i, _i, _vp, _vp]
         L.hg_gs_batched_workspace_size.restype = _sz
         L.hg_gs_batched_workspace_size.argtypes = [ctypes.POINTER(hg_problem), _i]
         L.hg_gs_batched.restype = _i
         L.hg_gs_batched.argtypes = [ctypes.POINTER(hg_problem), _i, _i, _vp, _sz, _vp]
+        L.hg_autotune_workspace_size.restype = _sz
+        L.hg_autotune_workspace_size.argtypes = [_i, _i, _i]
+        L.hg_autotune.restype = _i
+        L.hg_autotune.argtypes = [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), _vp, _sz, _vp]
+        L.hg_set_launch_config.restype = _i
+        L.hg_set_launch_config.argtypes = [_i, _i, _i, _i, _i]
+        L.hg_get_launch_config.restype = _i
+        L.hg_get_launch_config.argtypes = [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]
         L.hg_timing_enable.restype = None
         L.hg_timing_enable.argtypes = [_i]
         L.hg_timing_read.restype = _i
@@ -98,6 +106,27 @@ def hg_last_error():
 def _check(status):
     if status != HG_OK:
         raise HologenError(status, hg_last_error() or hg_status_string(status))
+
+
+def hg_autotune(ny, nx, batch=1, device="cuda", stream=None):
+    """Time the compiled tile schedules for (ny, nx, batch); returns (col_tile, rows_per_group)."""
+    torch = _torch()
+    dev = torch.device(device)
+    ws = _workspace(int(lib().hg_autotune_workspace_size(ny, nx, batch)), dev, None)
+    c, r = _i(0), _i(0)
+    _check(lib().hg_autotune(ny, nx, batch, ctypes.byref(c), ctypes.byref(r), _ptr(ws), ws.numel(),
+                             _stream(dev, stream)))
+    return c.value, r.value
+
+
+def hg_set_launch_config(ny, nx, batch, col_tile, rows_per_group):
+    _check(lib().hg_set_launch_config(ny, nx, batch, col_tile, rows_per_group))
+
+
+def hg_get_launch_config(ny, nx, batch=1):
+    c, r = _i(0), _i(0)
+    _check(lib().hg_get_launch_config(ny, nx, batch, ctypes.byref(c), ctypes.byref(r)))
+    return c.value, r.value
 
 
 def hg_timing_enable(on=True):
@@ -218,12 +247,12 @@ def hg_fresnel_propagate(field, wavelength_m=0.0, pitch_m=0.0, z_m=0.0, directio
     return out
 
 
-def hg_random_phase(seed, item, tag, ny, nx, device="cuda", stream=None):
-    """The library's Philox phasor field exp(2 pi i u24) for (seed, item, tag)."""
+def hg_random_phase(seed, item, tag, axis, ny, nx, device="cuda", stream=None):
+    """The library's Philox phasor field exp(2 pi i u24) for (seed, item, tag) on lines along `axis`."""
     torch = _torch()
     dev = torch.device(device)
     out = torch.empty((ny, nx), dtype=torch.complex64, device=dev)
-    _check(lib().hg_random_phase(seed & (2**64 - 1), item, tag, ny, nx, _ptr(out), _stream(dev, stream)))
+    _check(lib().hg_random_phase(seed & (2**64 - 1), item, tag, axis, ny, nx, _ptr(out), _stream(dev, stream)))
     return out
 
 

@@ -1,19 +1,24 @@
 // C ABI of the hologram hot path (declared in include/hologen.h): argument
-// validation on the host, workspace carving, and the launch sequences of the
-// GS / weighted GS / OSPR / propagation pipelines on the caller's stream.
+// validation on the host, workspace carving, launch configuration (default
+// table or autotuned), and the launch sequences of the GS / weighted GS /
+// OSPR / propagation pipelines on the caller's stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
 #include "hologen.h"
-#include "hg_kernels.hpp"
+#include "hg_launch.hpp"
 
 namespace {
 
@@ -59,31 +64,18 @@ struct TimeScope {
     hipEvent_t e = timing_event();
     if (!e) return;
     start = g_timing.used - 1;
-    hipEventRecord(e, st);
+    (void)hipEventRecord(e, st);
   }
   ~TimeScope() {
     if (start == (size_t)-1) return;
     hipEvent_t e = timing_event();
     if (!e) return;
-    hipEventRecord(e, st);
+    (void)hipEventRecord(e, st);
     g_timing.marks.push_back({cat, start});
   }
 };
 
 bool pow2_in_range(int n) { return n >= 64 && n <= 4096 && (n & (n - 1)) == 0; }
-
-// ---------------------------------------------------------------------------
-// launch geometry per transform length (E = 16 elements per thread)
-// ---------------------------------------------------------------------------
-constexpr int kE = 16;
-template <int N> struct RowCfg {
-  static constexpr int T = N / kE;
-  static constexpr int RPB = T >= 256 ? 1 : 256 / T;  // rows per workgroup
-};
-template <int N> struct ColCfg {
-  static constexpr int C = N <= 512 ? 16 : (N == 1024 ? 8 : (N == 2048 ? 4 : 2));  // columns per tile
-};
-int col_tile(int ny) { return ny <= 512 ? 16 : (ny == 1024 ? 8 : (ny == 2048 ? 4 : 2)); }
 
 template <class F> bool with_size(int n, F&& f) {
   switch (n) {
@@ -99,19 +91,60 @@ template <class F> bool with_size(int n, F&& f) {
 }
 
 // ---------------------------------------------------------------------------
+// launch configuration: column-tile width C (by column length ny) and rows
+// per row-pass workgroup RPB (by row length nx); defaults, overridden by
+// hg_autotune / hg_set_launch_config for the same (ny, nx, batch class)
+// ---------------------------------------------------------------------------
+struct Cfg { int C, RPB; };
+
+int min_col_tile(int ny) {
+  for (int c : {1, 2, 4, 8, 16})
+    if (col_ok(ny, c)) return c;
+  return 16;
+}
+
+Cfg default_cfg(int ny, int nx, int B) {
+  Cfg c{};
+  switch (ny) {
+    case 64: c.C = 16; break;
+    case 128: c.C = 16; break;
+    case 256: c.C = 8; break;
+    case 512: c.C = 8; break;
+    case 1024: c.C = 4; break;
+    case 2048: c.C = 4; break;
+    default: c.C = 2; break;
+  }
+  const int T = nx / kE;
+  c.RPB = T >= 256 ? 1 : 256 / T;
+  (void)B;
+  return c;
+}
+
+int batch_class(int B) { return B >= 8 ? 1 : 0; }
+
+std::mutex g_cfg_mu;
+std::map<std::tuple<int, int, int>, Cfg> g_tuned;
+
+Cfg get_cfg(int ny, int nx, int B) {
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  auto it = g_tuned.find(std::make_tuple(ny, nx, batch_class(B)));
+  return it != g_tuned.end() ? it->second : default_cfg(ny, nx, B);
+}
+
+// ---------------------------------------------------------------------------
 // workspace layout of one size class (B problems of ny x nx)
 // ---------------------------------------------------------------------------
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t desc, field, tprep, wbuf, accum, twx, twy, chirp, part, total;
-  int nblk, slots;
+  int max_nblk, slots;
 };
 
 Layout make_layout(int op, int ny, int nx, int B, int kmax) {
   Layout L{};
   const size_t px = (size_t)ny * nx * B;
-  L.nblk = nx / col_tile(ny);
+  L.max_nblk = nx / min_col_tile(ny);
   L.slots = (op == HG_OP_OSPR ? kmax : kmax + 1) + 1;  // + energy slot
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
@@ -123,7 +156,7 @@ Layout make_layout(int op, int ny, int nx, int B, int kmax) {
   L.twx = take(nx * sizeof(float2));
   L.twy = take(ny * sizeof(float2));
   L.chirp = take((size_t)B * (nx + ny) * sizeof(float2));
-  L.part = take((size_t)B * L.slots * L.nblk * 4 * sizeof(double));
+  L.part = take((size_t)B * L.slots * L.max_nblk * 4 * sizeof(double));
   L.total = o;
   return L;
 }
@@ -157,24 +190,28 @@ __global__ void k_set_desc(Desc* dst, DescPack pk) {
   if (i < pk.count) dst[i] = pk.d[i];
 }
 
+__global__ void k_fill(float* p, size_t n, float v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 hg_status check_launch() {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(HG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
   return HG_OK;
 }
 
-hg_status upload_descs(Desc* dst, const std::vector<Desc>& ds, hipStream_t st) {
+void upload_descs(Desc* dst, const std::vector<Desc>& ds, hipStream_t st) {
   for (size_t i = 0; i < ds.size(); i += 8) {
     DescPack pk{};
     pk.count = (int)std::min<size_t>(8, ds.size() - i);
     for (int j = 0; j < pk.count; ++j) pk.d[j] = ds[i + j];
     hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, st, dst + i, pk);
   }
-  return check_launch();
 }
 
 void launch_twiddles(float2* tw, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, st, tw, n);
+  with_size(n, [&](auto nc) { launch_twiddles_t<decltype(nc)::value>(tw, st); });
 }
 
 void launch_chirps(float2* chirp, int ny, int nx, const std::vector<double>& rates, hipStream_t st) {
@@ -190,43 +227,28 @@ void launch_chirps(float2* chirp, int ny, int nx, const std::vector<double>& rat
 // ---------------------------------------------------------------------------
 // pass launchers
 // ---------------------------------------------------------------------------
-bool launch_row(const Batch& bt, int B, bool fresnel, int mode, int arg, const float2* pin, float2* pout,
-                hipStream_t st) {
+void launch_row(const Batch& bt, int RPB, int B, bool fresnel, int lk, int mode, int arg, const float2* pin,
+                float2* pout, hipStream_t st) {
   TimeScope ts(TC_ROW, st);
-  return with_size(bt.nx, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    using C = RowCfg<N>;
-    const dim3 grid(bt.ny / C::RPB, B), block(C::RPB * C::T);
-    if (fresnel)
-      hipLaunchKernelGGL((k_row<N, kE, C::RPB, true>), grid, block, 0, st, bt, mode, arg, pin, pout);
-    else
-      hipLaunchKernelGGL((k_row<N, kE, C::RPB, false>), grid, block, 0, st, bt, mode, arg, pin, pout);
+  with_size(bt.nx, [&](auto nc) {
+    launch_row_t<decltype(nc)::value>(RPB, fresnel, lk, bt, B, mode, arg, pin, pout, st);
   });
 }
 
-bool launch_col(const Batch& bt, int B, int mode, int arg, int adaptive, const float2* pin, float2* pout,
+void launch_col(const Batch& bt, int C, int B, int mode, int arg, int adaptive, const float2* pin, float2* pout,
                 hipStream_t st) {
   TimeScope ts(TC_COL, st);
-  return with_size(bt.ny, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    constexpr int C = ColCfg<N>::C;
-    const dim3 grid(bt.nx / C, B), block(C * (N / kE));
-    hipLaunchKernelGGL((k_col<N, kE, C>), grid, block, 0, st, bt, mode, arg, adaptive, pin, pout);
+  with_size(bt.ny, [&](auto nc) {
+    launch_col_t<decltype(nc)::value>(C, bt, B, mode, arg, adaptive, pin, pout, st);
   });
 }
 
-bool launch_setup(const Batch& bt, int B, int weighted, hipStream_t st) {
+void launch_setup(const Batch& bt, int C, int B, int weighted, hipStream_t st) {
   TimeScope ts(TC_SETUP, st);
-  return with_size(bt.ny, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    constexpr int C = ColCfg<N>::C;
-    const dim3 grid(bt.nx / C, B), block(C * (N / kE));
-    hipLaunchKernelGGL((k_energy<N, kE, C>), grid, block, 0, st, bt);
-    hipLaunchKernelGGL((k_prepare<N, kE, C>), grid, block, 0, st, bt, weighted);
-  });
+  with_size(bt.ny, [&](auto nc) { launch_setup_t<decltype(nc)::value>(C, bt, B, weighted, st); });
 }
 
-Batch make_batch(void* ws, const Layout& L, int ny, int nx) {
+Batch make_batch(void* ws, const Layout& L, int ny, int nx, int C) {
   Batch bt{};
   bt.desc = at<Desc>(ws, L.desc);
   bt.field = at<float2>(ws, L.field);
@@ -234,12 +256,12 @@ Batch make_batch(void* ws, const Layout& L, int ny, int nx) {
   bt.wbuf = at<float>(ws, L.wbuf);
   bt.accum = at<float>(ws, L.accum);
   bt.tw_x = at<float2>(ws, L.twx);
-  bt.tw_y = at<float2>(ws, L.twy);
+  bt.tw_y = ny != nx ? at<float2>(ws, L.twy) : bt.tw_x;
   bt.chirp = at<float2>(ws, L.chirp);
   bt.part = at<double>(ws, L.part);
   bt.ny = ny;
   bt.nx = nx;
-  bt.nblk = L.nblk;
+  bt.nblk = nx / C;
   bt.slots = L.slots;
   bt.fwd_scale = (float)(1.0 / std::sqrt((double)nx * (double)ny));
   return bt;
@@ -250,24 +272,33 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
                        void* ws, const Layout& L, hipStream_t st) {
   const int B = (int)ds.size();
   int kmax = 0;
-  for (const Desc& d : ds) kmax = std::max(kmax, d.iters);
-  Batch bt = make_batch(ws, L, ny, nx);
-  hg_status s = upload_descs(const_cast<Desc*>(bt.desc), ds, st);
-  if (s != HG_OK) return s;
+  bool all_bin = true;
+  for (const Desc& d : ds) {
+    kmax = std::max(kmax, d.iters);
+    all_bin &= (d.L == 2);
+  }
+  const Cfg cfg = get_cfg(ny, nx, B);
+  Batch bt = make_batch(ws, L, ny, nx, cfg.C);
+  upload_descs(const_cast<Desc*>(bt.desc), ds, st);
   launch_twiddles(const_cast<float2*>(bt.tw_x), nx, st);
   if (ny != nx) launch_twiddles(const_cast<float2*>(bt.tw_y), ny, st);
-  else bt.tw_y = bt.tw_x;
   bool fresnel = false;
   for (double r : rates) fresnel |= (r != 0.0);
   if (fresnel) launch_chirps(const_cast<float2*>(bt.chirp), ny, nx, rates, st);
-  launch_setup(bt, B, weighted ? 1 : 0, st);
-  launch_row(bt, B, fresnel, ROW_INIT, 0, nullptr, nullptr, st);
+  launch_setup(bt, cfg.C, B, weighted ? 1 : 0, st);
+  const int lk = all_bin ? LK_BIN : LK_ANY;
+  launch_row(bt, cfg.RPB, B, fresnel, lk, ROW_INIT, 0, nullptr, nullptr, st);
   const int cmode = weighted ? COL_WGS : COL_GS;
   for (int k = 1; k <= kmax; ++k) {
-    launch_col(bt, B, cmode, k, 0, nullptr, nullptr, st);
-    launch_row(bt, B, fresnel, ROW_ITER, k, nullptr, nullptr, st);
+    launch_col(bt, cfg.C, B, cmode, k, 0, nullptr, nullptr, st);
+    launch_row(bt, cfg.RPB, B, fresnel, lk, ROW_ITER, k, nullptr, nullptr, st);
   }
-  launch_col(bt, B, cmode, kmax + 1, 0, nullptr, nullptr, st);
+  // final measurement pass of every distinct iteration count in the class
+  std::vector<int> ks;
+  for (const Desc& d : ds) ks.push_back(d.iters);
+  std::sort(ks.begin(), ks.end());
+  ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+  for (int k : ks) launch_col(bt, cfg.C, B, COL_FINAL, k + 1, 0, nullptr, nullptr, st);
   hipLaunchKernelGGL(k_finish, dim3(B, (kmax + 1 + 255) / 256), dim3(256), 0, st, bt, B, 0);
   return check_launch();
 }
@@ -279,13 +310,24 @@ hg_status check_ws(void* ws, size_t bytes, size_t need) {
   return HG_OK;
 }
 
-hg_status check_common(const float* target, int ny, int nx, int iters, int L) {
+hg_status check_size(int ny, int nx) {
   if (!pow2_in_range(ny) || !pow2_in_range(nx))
     return fail(HG_ERR_UNSUPPORTED_SIZE, "ny=%d nx=%d: each must be a power of two in [64, 4096]", ny, nx);
+  return HG_OK;
+}
+
+hg_status check_common(const float* target, int ny, int nx, int iters, int L) {
+  hg_status s = check_size(ny, nx);
+  if (s != HG_OK) return s;
   if (!target) return fail(HG_ERR_INVALID_ARG, "target is NULL");
   if (iters < 1) return fail(HG_ERR_INVALID_ARG, "iters=%d must be >= 1", iters);
   if (!(L == 0 || (L >= 2 && L <= 256))) return fail(HG_ERR_INVALID_ARG, "slm_levels=%d: 0 or 2..256", L);
   return HG_OK;
+}
+
+bool optics_ok(double lambda, double pitch, double z) {
+  return !is_fresnel(lambda, pitch, z) ||
+         (lambda > 0.0 && pitch > 0.0 && std::isfinite(lambda) && std::isfinite(pitch));
 }
 
 hg_status gs_common(bool weighted, const float* target, int ny, int nx, int iters, int L, uint64_t seed,
@@ -297,8 +339,7 @@ hg_status gs_common(bool weighted, const float* target, int ny, int nx, int iter
   if (s != HG_OK) return s;
   if (L >= 2 && !levels_out) return fail(HG_ERR_INVALID_ARG, "levels_out is required when slm_levels >= 2");
   if (init_levels && L < 2) return fail(HG_ERR_INVALID_ARG, "init_levels needs slm_levels >= 2");
-  if (is_fresnel(lambda, pitch, z) && !(lambda > 0.0 && pitch > 0.0 && std::isfinite(lambda) && std::isfinite(pitch)))
-    return fail(HG_ERR_INVALID_ARG, "Fresnel needs wavelength_m > 0 and pitch_m > 0");
+  if (!optics_ok(lambda, pitch, z)) return fail(HG_ERR_INVALID_ARG, "Fresnel needs wavelength_m > 0 and pitch_m > 0");
   const int op = weighted ? HG_OP_WGS : HG_OP_GS;
   const Layout Lo = make_layout(op, ny, nx, 1, iters);
   s = check_ws(ws, ws_bytes, Lo.total);
@@ -320,6 +361,21 @@ hg_status gs_common(bool weighted, const float* target, int ny, int nx, int iter
   std::vector<Desc> ds{d};
   std::vector<double> rates{chirp_rate(lambda, pitch, z)};
   return run_gs_class(ny, nx, ds, rates, weighted, ws, Lo, static_cast<hipStream_t>(stream));
+}
+
+// Size classes of a batched call in order of first appearance.
+struct ClassPlan {
+  std::vector<std::pair<int, int>> order;
+  std::map<std::pair<int, int>, std::vector<int>> members;
+};
+ClassPlan plan_classes(const hg_problem* probs, int count) {
+  ClassPlan cp;
+  for (int i = 0; i < count; ++i) {
+    auto key = std::make_pair(probs[i].ny, probs[i].nx);
+    if (!cp.members.count(key)) cp.order.push_back(key);
+    cp.members[key].push_back(i);
+  }
+  return cp;
 }
 
 }  // namespace
@@ -403,17 +459,16 @@ hg_status hg_ospr(const float* target, int ny, int nx, int subframes, int adapti
   d.seed = seed;
   d.L = 2;
   d.iters = subframes;
-  Batch bt = make_batch(workspace, Lo, ny, nx);
-  s = upload_descs(const_cast<Desc*>(bt.desc), {d}, st);
-  if (s != HG_OK) return s;
+  const Cfg cfg = get_cfg(ny, nx, 1);
+  Batch bt = make_batch(workspace, Lo, ny, nx, cfg.C);
+  upload_descs(const_cast<Desc*>(bt.desc), {d}, st);
   launch_twiddles(const_cast<float2*>(bt.tw_x), nx, st);
   if (ny != nx) launch_twiddles(const_cast<float2*>(bt.tw_y), ny, st);
-  else bt.tw_y = bt.tw_x;
-  launch_setup(bt, 1, 0, st);
-  launch_col(bt, 1, COL_OSPR_FIRST, 1, adaptive, nullptr, nullptr, st);
+  launch_setup(bt, cfg.C, 1, 0, st);
+  launch_col(bt, cfg.C, 1, COL_OSPR_FIRST, 1, adaptive, nullptr, nullptr, st);
   for (int n = 1; n <= subframes; ++n) {
-    launch_row(bt, 1, false, ROW_OSPR, n, nullptr, nullptr, st);
-    launch_col(bt, 1, n == subframes ? COL_OSPR_FINAL : COL_OSPR, n + 1, adaptive, nullptr, nullptr, st);
+    launch_row(bt, cfg.RPB, 1, false, LK_BIN, ROW_OSPR, n, nullptr, nullptr, st);
+    launch_col(bt, cfg.C, 1, n == subframes ? COL_OSPR_FINAL : COL_OSPR, n + 1, adaptive, nullptr, nullptr, st);
   }
   hipLaunchKernelGGL(k_finish, dim3(1, (subframes + 255) / 256), dim3(256), 0, st, bt, 1, 1);
   return check_launch();
@@ -423,17 +478,18 @@ hg_status hg_fresnel_propagate(const hg_complex* in, hg_complex* out, int ny, in
                                double pitch_m, double z_m, int direction, void* workspace, size_t workspace_bytes,
                                void* stream) {
   g_err[0] = 0;
-  if (!pow2_in_range(ny) || !pow2_in_range(nx))
-    return fail(HG_ERR_UNSUPPORTED_SIZE, "ny=%d nx=%d: each must be a power of two in [64, 4096]", ny, nx);
+  hg_status s = check_size(ny, nx);
+  if (s != HG_OK) return s;
   if (!in || !out) return fail(HG_ERR_INVALID_ARG, "in and out must be non-NULL");
   if (direction != 1 && direction != -1) return fail(HG_ERR_INVALID_ARG, "direction must be +1 or -1");
-  const bool fres = is_fresnel(wavelength_m, pitch_m, z_m);
-  if (fres && !(wavelength_m > 0.0 && pitch_m > 0.0 && std::isfinite(wavelength_m) && std::isfinite(pitch_m)))
+  if (!optics_ok(wavelength_m, pitch_m, z_m))
     return fail(HG_ERR_INVALID_ARG, "Fresnel needs wavelength_m > 0 and pitch_m > 0");
+  const bool fres = is_fresnel(wavelength_m, pitch_m, z_m);
   const Layout Lo = make_prop_layout(ny, nx);
-  hg_status s = check_ws(workspace, workspace_bytes, Lo.total);
+  s = check_ws(workspace, workspace_bytes, Lo.total);
   if (s != HG_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const Cfg cfg = get_cfg(ny, nx, 1);
   Batch bt{};
   bt.tw_x = at<float2>(workspace, Lo.twx);
   bt.tw_y = ny != nx ? at<float2>(workspace, Lo.twy) : bt.tw_x;
@@ -446,43 +502,39 @@ hg_status hg_fresnel_propagate(const hg_complex* in, hg_complex* out, int ny, in
   const float2* fin = reinterpret_cast<const float2*>(in);
   float2* fout = reinterpret_cast<float2*>(out);
   if (direction > 0) {
-    launch_row(bt, 1, fres, ROW_PROP_FWD, 0, fin, fout, st);
-    launch_col(bt, 1, COL_PROP_FWD, 0, 0, fout, fout, st);
+    launch_row(bt, cfg.RPB, 1, fres, LK_ANY, ROW_PROP_FWD, 0, fin, fout, st);
+    launch_col(bt, cfg.C, 1, COL_PROP_FWD, 0, 0, fout, fout, st);
   } else {
-    launch_col(bt, 1, COL_PROP_BWD, 0, 0, fin, fout, st);
-    launch_row(bt, 1, fres, ROW_PROP_BWD, 0, fout, fout, st);
+    launch_col(bt, cfg.C, 1, COL_PROP_BWD, 0, 0, fin, fout, st);
+    launch_row(bt, cfg.RPB, 1, fres, LK_ANY, ROW_PROP_BWD, 0, fout, fout, st);
   }
   return check_launch();
 }
 
-hg_status hg_random_phase(uint64_t seed, uint32_t item, uint32_t tag, int ny, int nx, hg_complex* out,
+hg_status hg_random_phase(uint64_t seed, uint32_t item, uint32_t tag, int axis, int ny, int nx, hg_complex* out,
                           void* stream) {
   g_err[0] = 0;
-  if (!pow2_in_range(ny) || !pow2_in_range(nx))
-    return fail(HG_ERR_UNSUPPORTED_SIZE, "ny=%d nx=%d: each must be a power of two in [64, 4096]", ny, nx);
+  hg_status s = check_size(ny, nx);
+  if (s != HG_OK) return s;
   if (!out) return fail(HG_ERR_INVALID_ARG, "out is NULL");
-  const int npix = ny * nx;
-  hipLaunchKernelGGL(k_random_phase, dim3((npix + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
-                     reinterpret_cast<float2*>(out), seed, item, tag, npix);
+  if (axis != 0 && axis != 1) return fail(HG_ERR_INVALID_ARG, "axis must be 0 (column lines) or 1 (row lines)");
+  const int nthreads = ny * nx / 4;
+  hipLaunchKernelGGL(k_random_phase, dim3((nthreads + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     reinterpret_cast<float2*>(out), seed, item, tag, ny, nx, axis);
   return check_launch();
 }
 
 size_t hg_gs_batched_workspace_size(const hg_problem* probs, int count) {
   if (!probs || count < 1) return 0;
-  std::vector<std::pair<int, int>> order;
-  std::map<std::pair<int, int>, std::pair<int, int>> cls;  // (ny,nx) -> (count, kmax)
-  for (int i = 0; i < count; ++i) {
-    const hg_problem& p = probs[i];
-    if (!pow2_in_range(p.ny) || !pow2_in_range(p.nx) || p.iters < 1) return 0;
-    auto key = std::make_pair(p.ny, p.nx);
-    auto it = cls.find(key);
-    if (it == cls.end()) { cls[key] = {1, p.iters}; order.push_back(key); }
-    else { it->second.first++; it->second.second = std::max(it->second.second, p.iters); }
-  }
+  for (int i = 0; i < count; ++i)
+    if (!pow2_in_range(probs[i].ny) || !pow2_in_range(probs[i].nx) || probs[i].iters < 1) return 0;
+  const ClassPlan cp = plan_classes(probs, count);
   size_t total = 0;
-  for (auto& k : order) {
+  for (auto& key : cp.order) {
+    int kmax = 0;
+    for (int i : cp.members.at(key)) kmax = std::max(kmax, probs[i].iters);
     // the weighted layout is the larger one; one query serves both modes
-    total += make_layout(HG_OP_WGS, k.first, k.second, cls[k].first, cls[k].second).total;
+    total += make_layout(HG_OP_WGS, key.first, key.second, (int)cp.members.at(key).size(), kmax).total;
   }
   return total;
 }
@@ -494,26 +546,22 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
   for (int i = 0; i < count; ++i) {
     const hg_problem& p = probs[i];
     hg_status s = check_common(p.target, p.ny, p.nx, p.iters, p.slm_levels);
-    if (s != HG_OK) return fail(s, "problem %d: %s", i, g_err);
+    if (s != HG_OK) {
+      std::string msg = g_err;
+      return fail(s, "problem %d: %s", i, msg.c_str());
+    }
     if (p.slm_levels >= 2 && !p.levels_out) return fail(HG_ERR_INVALID_ARG, "problem %d: levels_out required", i);
-    if (is_fresnel(p.wavelength_m, p.pitch_m, p.z_m) &&
-        !(p.wavelength_m > 0.0 && p.pitch_m > 0.0 && std::isfinite(p.wavelength_m) && std::isfinite(p.pitch_m)))
+    if (!optics_ok(p.wavelength_m, p.pitch_m, p.z_m))
       return fail(HG_ERR_INVALID_ARG, "problem %d: Fresnel needs wavelength_m > 0 and pitch_m > 0", i);
   }
   const size_t need = hg_gs_batched_workspace_size(probs, count);
   hg_status s = check_ws(workspace, workspace_bytes, need);
   if (s != HG_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  std::vector<std::pair<int, int>> order;
-  std::map<std::pair<int, int>, std::vector<int>> members;
-  for (int i = 0; i < count; ++i) {
-    auto key = std::make_pair(probs[i].ny, probs[i].nx);
-    if (!members.count(key)) order.push_back(key);
-    members[key].push_back(i);
-  }
+  const ClassPlan cp = plan_classes(probs, count);
   size_t off = 0;
-  for (auto& key : order) {
-    const std::vector<int>& idx = members[key];
+  for (auto& key : cp.order) {
+    const std::vector<int>& idx = cp.members.at(key);
     std::vector<Desc> ds;
     std::vector<double> rates;
     int kmax = 0;
@@ -536,6 +584,117 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
     if (s != HG_OK) return s;
     off += Lo.total;
   }
+  return HG_OK;
+}
+
+size_t hg_autotune_workspace_size(int ny, int nx, int batch) {
+  if (!pow2_in_range(ny) || !pow2_in_range(nx) || batch < 1) return 0;
+  const size_t px = (size_t)ny * nx * batch;
+  return make_layout(HG_OP_WGS, ny, nx, batch, 4).total + align256(px * sizeof(float)) + align256(px);
+}
+
+hg_status hg_autotune(int ny, int nx, int batch, int* col_tile, int* rows_per_group, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+  g_err[0] = 0;
+  hg_status s = check_size(ny, nx);
+  if (s != HG_OK) return s;
+  if (batch < 1) return fail(HG_ERR_INVALID_ARG, "batch must be >= 1");
+  s = check_ws(workspace, workspace_bytes, hg_autotune_workspace_size(ny, nx, batch));
+  if (s != HG_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout Lo = make_layout(HG_OP_WGS, ny, nx, batch, 4);
+  const size_t px = (size_t)ny * nx * batch;
+  float* target = at<float>(workspace, Lo.total);
+  uint8_t* levels = at<uint8_t>(workspace, Lo.total + align256(px * sizeof(float)));
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((px + 255) / 256)), dim3(256), 0, st, target, px, 1.0f);
+  std::vector<Desc> ds(batch);
+  for (int b = 0; b < batch; ++b) {
+    ds[b] = Desc{};
+    ds[b].target = target + (size_t)b * ny * nx;
+    ds[b].levels_out = levels + (size_t)b * ny * nx;
+    ds[b].seed = 1;
+    ds[b].item = (uint32_t)b;
+    ds[b].L = 2;
+    ds[b].iters = 1 << 20;  // never the last iteration: no level writes
+  }
+  const bool was_on = g_timing.on;
+  g_timing.on = false;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(HG_ERR_HIP, "hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(HG_ERR_HIP, "hipEventCreate failed");
+  }
+  auto time_ms = [&](auto&& body) {
+    body();  // warm-up
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < 3; ++r) body();
+    (void)hipEventRecord(e1, st);
+    float ms = 0.f;
+    (void)hipEventSynchronize(e1);
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return ms;
+  };
+  const Cfg def = default_cfg(ny, nx, batch);
+  Cfg best = def;
+  float best_col = 1e30f, best_row = 1e30f;
+  for (int C : {2, 4, 8, 16}) {
+    if (!col_ok(ny, C) || C > nx) continue;
+    Batch bt = make_batch(workspace, Lo, ny, nx, C);
+    upload_descs(const_cast<Desc*>(bt.desc), ds, st);
+    launch_twiddles(const_cast<float2*>(bt.tw_x), nx, st);
+    if (ny != nx) launch_twiddles(const_cast<float2*>(bt.tw_y), ny, st);
+    launch_setup(bt, C, batch, 1, st);
+    launch_row(bt, def.RPB, batch, false, LK_BIN, ROW_INIT, 0, nullptr, nullptr, st);
+    const float ms = time_ms([&] { launch_col(bt, C, batch, COL_WGS, 1, 0, nullptr, nullptr, st); });
+    if (ms < best_col) { best_col = ms; best.C = C; }
+  }
+  for (int R : {1, 2, 4, 8, 16, 32, 64}) {
+    if (!rpb_ok(nx, R) || R > ny) continue;
+    Batch bt = make_batch(workspace, Lo, ny, nx, best.C);
+    const float ms = time_ms([&] { launch_row(bt, R, batch, false, LK_BIN, ROW_ITER, 1, nullptr, nullptr, st); });
+    if (ms < best_row) { best_row = ms; best.RPB = R; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g_timing.on = was_on;
+  s = check_launch();
+  if (s != HG_OK) return s;
+  {
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    g_tuned[std::make_tuple(ny, nx, batch_class(batch))] = best;
+  }
+  if (col_tile) *col_tile = best.C;
+  if (rows_per_group) *rows_per_group = best.RPB;
+  return HG_OK;
+}
+
+hg_status hg_set_launch_config(int ny, int nx, int batch, int col_tile, int rows_per_group) {
+  g_err[0] = 0;
+  hg_status s = check_size(ny, nx);
+  if (s != HG_OK) return s;
+  if (batch < 1) return fail(HG_ERR_INVALID_ARG, "batch must be >= 1");
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  const auto key = std::make_tuple(ny, nx, batch_class(batch));
+  if (col_tile == 0 && rows_per_group == 0) {
+    g_tuned.erase(key);
+    return HG_OK;
+  }
+  if (!col_ok(ny, col_tile) || col_tile > nx)
+    return fail(HG_ERR_INVALID_ARG, "column tile %d not compiled for ny=%d", col_tile, ny);
+  if (!rpb_ok(nx, rows_per_group) || rows_per_group > ny)
+    return fail(HG_ERR_INVALID_ARG, "rows per group %d not compiled for nx=%d", rows_per_group, nx);
+  g_tuned[key] = Cfg{col_tile, rows_per_group};
+  return HG_OK;
+}
+
+hg_status hg_get_launch_config(int ny, int nx, int batch, int* col_tile, int* rows_per_group) {
+  g_err[0] = 0;
+  hg_status s = check_size(ny, nx);
+  if (s != HG_OK) return s;
+  const Cfg c = get_cfg(ny, nx, std::max(batch, 1));
+  if (col_tile) *col_tile = c.C;
+  if (rows_per_group) *rows_per_group = c.RPB;
   return HG_OK;
 }
 

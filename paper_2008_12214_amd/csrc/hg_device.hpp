@@ -7,6 +7,20 @@
 
 namespace hg {
 
+// Global-memory pointer.  Pointers that reach a kernel inside a struct are
+// generic; marking them global lets the compiler emit global_load/store
+// instead of flat instructions, whose completion is tracked together with
+// LDS traffic.
+// (The host pass of HIP compilation only builds kernel stubs and sees plain
+// pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T> using gptr = __attribute__((address_space(1))) T*;
+#else
+template <class T> using gptr = T*;
+#endif
+template <class T> __device__ __forceinline__ gptr<T> to_global(T* p) { return (gptr<T>)p; }
+template <class T> __device__ __forceinline__ gptr<const T> to_global(const T* p) { return (gptr<const T>)p; }
+
 // ---------------------------------------------------------------------------
 // complex float helpers (interleaved float2)
 // ---------------------------------------------------------------------------
@@ -125,14 +139,30 @@ template <int N, int E> struct Plan {
   __host__ __device__ static constexpr int stride(int s) { return s == 0 ? 1 : stride(s - 1) * radix(s - 1); }
 };
 
-// Twiddle multiply: forward uses w, inverse conj(w); tw[m] = exp(-2 pi i m / N).
+// Per-stage twiddle table layout.  Stage s >= 1 (stride p, radix R) stores
+// W_{pR}^{r k} for k < p, r = 1..R-1 at offset twoff(s) + k (R - 1) + r - 1,
+// so one butterfly reads R - 1 consecutive entries.
+template <int N, int E> struct TwLayout {
+  using P = Plan<N, E>;
+  __host__ __device__ static constexpr int size_of(int s) { return s == 0 ? 0 : P::stride(s) * (P::radix(s) - 1); }
+  __host__ __device__ static constexpr int twoff(int s) { return s <= 1 ? 0 : twoff(s - 1) + size_of(s - 1); }
+  __host__ __device__ static constexpr int total() { return twoff(P::ns - 1) + size_of(P::ns - 1); }
+};
+
+// Twiddle multiply: forward uses w, inverse conj(w); tables hold exp(-2 pi i m / n).
 template <int DIR> __device__ __forceinline__ float2 twmul(float2 a, float2 w) {
   return DIR < 0 ? cmul(a, w) : cmulc(a, w);
 }
 
+// LDS element padding: one float2 of padding per 16 elements.  Stage
+// strides in the plans used here are 1 (first radix-16 stage) or multiples
+// of 16, so padded addresses stay affine in the butterfly index r and the
+// compiler can use immediate offsets.
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+
 // One Stockham stage S and, recursively, the following ones.
-//   Ex: LDS exchange policy with read(idx), write(idx, v), before_read(),
-//       before_write().
+//   Ex: LDS exchange policy with before_read(), before_write(), and
+//       ld(e) / st(e, v) on padded element index e.
 template <int N, int E, int DIR, int S, class Ex>
 __device__ __forceinline__ void fft_stage(float2 (&v)[E], int t, const float2* __restrict__ tw, Ex& ex) {
   using P = Plan<N, E>;
@@ -140,8 +170,14 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], int t, const float2* _
   constexpr bool last = (S == P::ns - 1);
   if constexpr (S > 0) {
     ex.before_read();
+    if constexpr (T % 16 == 0) {
+      const int rb = lds_pad(t);
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = ex.read(t + T * j);
+      for (int j = 0; j < E; ++j) v[j] = ex.ld(rb + j * (T + T / 16));
+    } else {
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = ex.ld(lds_pad(t + T * j));
+    }
   }
 #pragma unroll
   for (int m = 0; m < M; ++m) {
@@ -151,9 +187,10 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], int t, const float2* _
 #pragma unroll
     for (int r = 0; r < R; ++r) a[r] = v[m + r * M];
     if constexpr (p > 1) {
-      constexpr int step = N / (p * R);
+      constexpr int kTwOff = TwLayout<N, E>::twoff(S);
+      const float2* w = tw + kTwOff + k * (R - 1);
 #pragma unroll
-      for (int r = 1; r < R; ++r) a[r] = twmul<DIR>(a[r], tw[r * k * step]);
+      for (int r = 1; r < R; ++r) a[r] = twmul<DIR>(a[r], w[r - 1]);
     }
     Dft<R, DIR>::run(a);
 #pragma unroll
@@ -165,17 +202,36 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], int t, const float2* _
     for (int m = 0; m < M; ++m) {
       const int i = t + T * m;
       const int k = i & (p - 1);
+      const int o = (i - k) * R + k;  // output index of r = 0
+      if constexpr (p % 16 == 0) {
+        const int wb = lds_pad(o);
 #pragma unroll
-      for (int r = 0; r < R; ++r) ex.write((i - k) * R + k + r * p, v[m + r * M]);
+        for (int r = 0; r < R; ++r) ex.st(wb + r * (p + p / 16), v[m + r * M]);
+      } else if constexpr (p == 1 && R == 16) {
+        const int wb = lds_pad(o);
+#pragma unroll
+        for (int r = 0; r < R; ++r) ex.st(wb + r, v[m + r * M]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) ex.st(lds_pad(o + r * p), v[m + r * M]);
+      }
     }
     fft_stage<N, E, DIR, S + 1>(v, t, tw, ex);
   }
 }
 
+// Hide a pointer's value from the optimiser.  Used so that table loads are
+// issued where they are consumed instead of being hoisted (and kept live in
+// registers) across whole transforms, which would cap occupancy.
+template <class T> __device__ __forceinline__ T* launder(T* p) {
+  asm volatile("" : "+v"(p));
+  return p;
+}
+
 // Unscaled length-N transform of the data held by this thread group.
 template <int N, int E, int DIR, class Ex>
 __device__ __forceinline__ void fft(float2 (&v)[E], int t, const float2* __restrict__ tw, Ex& ex) {
-  fft_stage<N, E, DIR, 0>(v, t, tw, ex);
+  fft_stage<N, E, DIR, 0>(v, t, launder(tw), ex);
 }
 
 // ---------------------------------------------------------------------------
@@ -197,10 +253,16 @@ __device__ __forceinline__ U64x4 philox4x64_10(U64x4 x, uint64_t k0, uint64_t k1
   return x;
 }
 
-// 64-bit word for pixel p of the stream (seed, item, tag).
-__device__ __forceinline__ uint64_t philox_pixel_word(uint64_t seed, uint32_t item, uint32_t tag, uint64_t p) {
-  const U64x4 o = philox4x64_10(U64x4{p >> 2, 0, 0, 0}, seed, ((uint64_t)item << 32) | tag);
-  const uint32_t w = (uint32_t)(p & 3);
+// Random words of a plane split into lines of length n: element i of line l
+// takes word (i div n/4) of the block at counter (i mod n/4, l, 0, 0) under
+// key (seed, (item << 32) | tag).  One block serves the four quarter-line
+// elements i, i + n/4, i + n/2, i + 3n/4, which a thread of a length-n
+// transform holding elements t + T j (E divisible by 4) owns together.
+__device__ __forceinline__ U64x4 philox_line_block(uint64_t seed, uint32_t item, uint32_t tag, uint32_t i,
+                                                   uint32_t line) {
+  return philox4x64_10(U64x4{i, line, 0, 0}, seed, ((uint64_t)item << 32) | tag);
+}
+__device__ __forceinline__ uint64_t u64x4_word(const U64x4& o, int w) {
   return w == 0 ? o.a : w == 1 ? o.b : w == 2 ? o.c : o.d;
 }
 

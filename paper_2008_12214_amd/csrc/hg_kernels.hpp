@@ -17,6 +17,7 @@
 namespace hg {
 
 constexpr int kMaxWaves = 16;
+constexpr int kE = 16;  // elements per thread in every transform
 
 // Per-problem descriptor (device memory).  Replay-plane arrays are centred.
 struct Desc {
@@ -44,8 +45,8 @@ struct Batch {
   float* tprep;         // [B][ny][nx] prepared target
   float* wbuf;          // [B][ny][nx] workspace weights (if not user-owned)
   float* accum;         // [B][ny][nx] OSPR accumulator
-  const float2* tw_x;   // nx twiddles exp(-2 pi i m / nx)
-  const float2* tw_y;   // ny twiddles
+  const float2* tw_x;   // staged twiddle table for length nx
+  const float2* tw_y;   // staged twiddle table for length ny
   const float2* chirp;  // [B][nx + ny]: cx[x] (-1)^x, then cy[y] (-1)^y
   double* part;         // [B][slots][nblk][4] partial sums
   int ny, nx;
@@ -59,35 +60,80 @@ __device__ __forceinline__ double* part_ptr(const Batch& bt, int b, int slot, in
   return bt.part + (((size_t)b * bt.slots + slot) * bt.nblk + blk) * 4;
 }
 
-// ---------------------------------------------------------------------------
-// LDS exchange policies
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+// Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Give each XCD a contiguous run of column tiles so neighbouring tiles, which
+// share 128-byte lines when a tile is narrower than 16 columns, meet in the
+// same L2.
+__device__ __forceinline__ int xcd_tile(int bx, int nb) {
+  return (nb & 7) ? bx : (bx & 7) * (nb >> 3) + (bx >> 3);
+}
 
-// Row transforms: private LDS region per row, ping-pong buffers so each
-// exchange needs one barrier.
-struct RowEx {
+// ---------------------------------------------------------------------------
+// LDS exchange policies (padded element index e, see lds_pad)
+// ---------------------------------------------------------------------------
+// Ordering point for LDS traffic of a single wave: a wave's LDS operations
+// execute in program order, so only the compiler must be kept from moving
+// them across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Row transforms: private LDS region per row.  A row held by one wave
+// (T <= 64 threads) exchanges through one buffer with wave-level ordering
+// only; a row spread over several waves uses ping-pong buffers and one
+// workgroup barrier per exchange.
+template <bool WAVE> struct RowEx {
   float2* b[2];
   int w, rd;
-  __device__ void before_read() { __syncthreads(); rd = w; w ^= 1; }
-  __device__ void before_write() {}
-  __device__ float2 read(int i) const { return b[rd][lds_pad(i)]; }
-  __device__ void write(int i, float2 v) { b[w][lds_pad(i)] = v; }
+  __device__ void before_read() {
+    if constexpr (WAVE) {
+      wave_lds_sync();
+    } else {
+      __syncthreads();
+      rd = w;
+      w ^= 1;
+    }
+  }
+  __device__ void before_write() {
+    if constexpr (WAVE) wave_lds_sync();
+  }
+  __device__ float2 ld(int e) const { return WAVE ? b[0][e] : b[rd][e]; }
+  __device__ void st(int e, float2 v) {
+    if constexpr (WAVE) b[0][e] = v;
+    else b[w][e] = v;
+  }
 };
 
-// Column tile: C interleaved columns, element (i, c) at pad(i) * C + c.
-// Single buffer (the tile is large): barrier before reads and before writes.
-template <int C> struct ColEx {
-  float2* s;
-  int c;
-  __device__ void before_read() { __syncthreads(); }
-  __device__ void before_write() { __syncthreads(); }
-  __device__ float2 read(int i) const { return s[lds_pad(i) * C + c]; }
-  __device__ void write(int i, float2 v) { s[lds_pad(i) * C + c] = v; }
+// Column tile: C interleaved columns, element (e, c) at e * C + c.  With two
+// tile buffers (PP) each exchange needs one barrier; with one, a barrier
+// before the reads and another before the writes.
+template <int C, bool PP> struct ColEx {
+  float2* s;  // tile base + c
+  int w = 0, rd = 0;
+  int stride;                     // elements between the two buffers
+  __device__ void before_read() {
+    __syncthreads();
+    if constexpr (PP) { rd = w; w ^= 1; }
+  }
+  __device__ void before_write() {
+    if constexpr (!PP) __syncthreads();
+  }
+  __device__ float2 ld(int e) const { return PP ? s[rd * stride + e * C] : s[e * C]; }
+  __device__ void st(int e, float2 v) {
+    if constexpr (PP) s[w * stride + e * C] = v;
+    else s[e * C] = v;
+  }
 };
+
+// Two column tiles fit in LDS (with room for the reductions) when small enough.
+// (Measured: a second buffer costs more occupancy than the barrier it saves,
+// so it is off for every compiled tile.)
+__host__ __device__ constexpr bool col_pingpong(int NY, int C) { return false && 2 * (NY + NY / 16) * C * 8 <= 150 * 1024; }
 
 // ---------------------------------------------------------------------------
-// deterministic block reduction of 4 float sums into FP64
+// deterministic block reductions into FP64
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -95,6 +141,8 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sums of four per-thread float values over the block, in a fixed order;
+// results in tot[0..3] (valid for every thread on return).
 template <int NT>
 __device__ __forceinline__ void block_sum4(float a0, float a1, float a2, float a3, double (&red)[kMaxWaves][4],
                                            double (&tot)[4]) {
@@ -113,9 +161,8 @@ __device__ __forceinline__ void block_sum4(float a0, float a1, float a2, float a
   __syncthreads();
 }
 
-// Sum field `f` of slot `slot` over all nblk blocks of problem b, in a fixed
+// Sum field `f` of slot `slot` over all nblk tiles of problem b, in a fixed
 // order (every block computes the identical value).
-template <int NT>
 __device__ __forceinline__ double slot_total(const Batch& bt, int b, int slot, int f, double* bcast) {
   __syncthreads();
   if (threadIdx.x < 64) {
@@ -131,19 +178,38 @@ __device__ __forceinline__ double slot_total(const Batch& bt, int b, int slot, i
 // ---------------------------------------------------------------------------
 // table kernels (FP64 arithmetic, stored as complex64)
 // ---------------------------------------------------------------------------
-__global__ void k_twiddles(float2* tw, int n) {
+// Staged twiddles of a length-N transform: stage s, butterfly class k,
+// r = 1..R-1 -> exp(-2 pi i r k / (p R)).  Stages are walked at compile time.
+template <int N, int S>
+__device__ __forceinline__ void twiddle_entry(float2* tw, int m) {
+  using P = Plan<N, kE>;
+  if constexpr (S < P::ns) {
+    constexpr int R = P::radix(S), p = P::stride(S);
+    constexpr int off = TwLayout<N, kE>::twoff(S), sz = TwLayout<N, kE>::size_of(S);
+    if (m >= off && m < off + sz) {
+      const int k = (m - off) / (R - 1), r = (m - off) % (R - 1) + 1;
+      double sn, cs;
+      sincospi(2.0 * (double)(r * k) / (double)(p * R), &sn, &cs);
+      tw[m] = make_float2((float)cs, (float)-sn);
+      return;
+    }
+    twiddle_entry<N, S + 1>(tw, m);
+  }
+}
+
+template <int N>
+__global__ void k_twiddles(float2* tw) {
+  constexpr int total = TwLayout<N, kE>::total();
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n) return;
-  double s, c;
-  sincospi(2.0 * (double)m / (double)n, &s, &c);
-  tw[m] = make_float2((float)c, (float)-s);
+  if (m >= total) return;
+  twiddle_entry<N, 1>(tw, m);
 }
 
 // cx[x] = exp(i pi p^2 (x - nx/2)^2 / (lambda z)) (-1)^x, then cy likewise.
 // a = p^2 / (lambda z) (0 for Fourier); phase in half-turns = a d^2, reduced
 // exactly mod 2 before the FP64 sincospi.
 struct ChirpArgs { double a[32]; int count; };
-__global__ void k_chirps(float2* chirp, int ny, int nx, ChirpArgs ca, int first) {
+static __global__ void k_chirps(float2* chirp, int ny, int nx, ChirpArgs ca, int first) {
   const int b = blockIdx.y;
   if (b >= ca.count) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -159,47 +225,62 @@ __global__ void k_chirps(float2* chirp, int ny, int nx, ChirpArgs ca, int first)
   chirp[(size_t)(first + b) * (nx + ny) + i] = make_float2((float)c, (float)s);
 }
 
+// The phase field of stream (seed, item, tag): axis 1 = row lines, 0 = column lines.
+static __global__ void k_random_phase(float2* out, uint64_t seed, uint32_t item, uint32_t tag, int ny, int nx, int axis) {
+  const int n = axis ? nx : ny, nl = axis ? ny : nx, q = n / 4;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= q * nl) return;
+  const int i = id % q, l = id / q;
+  const U64x4 o = philox_line_block(seed, item, tag, (uint32_t)i, (uint32_t)l);
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const int e = i + w * q;
+    const size_t idx = axis ? (size_t)l * nx + e : (size_t)e * nx + l;
+    out[idx] = philox_phasor(u64x4_word(o, w));
+  }
+}
+
 // ---------------------------------------------------------------------------
-// set-up: target energy, prepared target, weights
+// set-up: target energy, prepared target, weights.  These share the column
+// pass's tiling so their partials line up with its slots.
 // ---------------------------------------------------------------------------
-// Column-tile elementwise kernels share the column pass's tiling so their
-// block partials line up with its slots.
-template <int NY, int E, int C>
-__global__ __launch_bounds__(C * (NY / E)) void k_energy(Batch bt) {
-  constexpr int T = NY / E, NT = C * T;
+template <int NY, int C>
+__global__ __launch_bounds__(C * (NY / kE)) void k_energy(Batch bt) {
+  constexpr int T = NY / kE, NT = C * T;
   __shared__ double red[kMaxWaves][4];
-  const int b = blockIdx.y, blk = blockIdx.x;
+  __shared__ double tot[4];
+  const int b = blockIdx.y, blk = xcd_tile(blockIdx.x, gridDim.x);
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int u = blk * C + c;
   const float* tg = bt.desc[b].target;
   float e = 0.0f;
 #pragma unroll
-  for (int j = 0; j < E; ++j) {
+  for (int j = 0; j < kE; ++j) {
     const float v = tg[(size_t)(t + T * j) * bt.nx + u];
     e += v * v;
   }
-  __shared__ double tot[4];
   block_sum4<NT>(e, 0.f, 0.f, 0.f, red, tot);
   if (threadIdx.x == 0) part_ptr(bt, b, bt.slots - 1, blk)[0] = tot[0];
 }
 
-template <int NY, int E, int C>
-__global__ __launch_bounds__(C * (NY / E)) void k_prepare(Batch bt, int weighted) {
-  constexpr int T = NY / E, NT = C * T;
+template <int NY, int C>
+__global__ __launch_bounds__(C * (NY / kE)) void k_prepare(Batch bt, int weighted) {
+  constexpr int T = NY / kE, NT = C * T;
   __shared__ double red[kMaxWaves][4];
+  __shared__ double tot[4];
   __shared__ double bc;
-  const int b = blockIdx.y, blk = blockIdx.x;
+  const int b = blockIdx.y, blk = xcd_tile(blockIdx.x, gridDim.x);
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int u = blk * C + c;
   const Desc& d = bt.desc[b];
-  const double e = slot_total<NT>(bt, b, bt.slots - 1, 0, &bc);
+  const double e = slot_total(bt, b, bt.slots - 1, 0, &bc);
   const float scale = (float)sqrt((double)bt.nx * (double)bt.ny / e);
   const size_t off = (size_t)b * bt.ny * bt.nx;
   float* w = d.user_weights ? d.weights : bt.wbuf + off;
   float om = 0.f, ws = 0.f;
   const int um = (bt.nx - u) & (bt.nx - 1);
 #pragma unroll
-  for (int j = 0; j < E; ++j) {
+  for (int j = 0; j < kE; ++j) {
     const int v = t + T * j;
     const size_t idx = (size_t)v * bt.nx + u;
     float tv = d.target[idx];
@@ -218,11 +299,10 @@ __global__ __launch_bounds__(C * (NY / E)) void k_prepare(Batch bt, int weighted
   }
   if (weighted) {
     // slot slots-1 field 1: |Omega|; slot 0 field 3: sum of w_0 over Omega
-    __shared__ double tmp[4];
-    block_sum4<NT>(om, ws, 0.f, 0.f, red, tmp);
+    block_sum4<NT>(om, ws, 0.f, 0.f, red, tot);
     if (threadIdx.x == 0) {
-      part_ptr(bt, b, bt.slots - 1, blk)[1] = tmp[0];
-      part_ptr(bt, b, 0, blk)[3] = tmp[1];
+      part_ptr(bt, b, bt.slots - 1, blk)[1] = tot[0];
+      part_ptr(bt, b, 0, blk)[3] = tot[1];
     }
   }
 }
@@ -231,6 +311,7 @@ __global__ __launch_bounds__(C * (NY / E)) void k_prepare(Batch bt, int weighted
 // row pass
 // ---------------------------------------------------------------------------
 enum RowMode { ROW_INIT = 0, ROW_ITER = 1, ROW_OSPR = 2, ROW_PROP_FWD = 3, ROW_PROP_BWD = 4 };
+enum LevelKind { LK_ANY = 0, LK_BIN = 1 };  // LK_BIN: every problem of the launch has L = 2
 
 // Modulation m[y][x] applied before the forward row FFT and conjugated after
 // the inverse one: (-1)^(x+y) for Fourier, chirp * (-1)^(x+y) for Fresnel.
@@ -244,38 +325,41 @@ __device__ __forceinline__ float2 modulate(float2 v, int x, int y, const float2*
   }
 }
 
-// mode      ROW_INIT: build f0, forward FFT.  ROW_ITER: inverse FFT, project,
-//           forward FFT (iteration k = arg).  ROW_OSPR: same with L = 2 and
-//           the levels of subframe arg written.  ROW_PROP_*: propagation.
-template <int NX, int E, int RPB, bool FRESNEL>
-__global__ __launch_bounds__(RPB * (NX / E)) void k_row(Batch bt, int mode, int arg, const float2* pin, float2* pout) {
+// MODE  ROW_INIT: build f0 (Philox, levels or field), forward FFT.
+//       ROW_ITER: inverse FFT, project, forward FFT (iteration k = arg).
+//       ROW_OSPR: as ROW_ITER with L = 2, writing subframe arg's levels.
+//       ROW_PROP_FWD / _BWD: scaled propagation between pin and pout.
+template <int NX, int RPB, bool FRESNEL, int MODE, int LK>
+__global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, const float2* pin, float2* pout) {
+  constexpr int E = kE;
   using P = Plan<NX, E>;
   constexpr int T = P::T;
-  constexpr int NT = RPB * T;
   constexpr int LW = NX + NX / 16;
   constexpr bool XCH = P::ns > 1;
-  __shared__ float2 lds[XCH ? RPB * 2 * LW : 1];
+  constexpr bool WAVE = T <= 64;  // each row inside one wave
+  constexpr int NBUF = WAVE ? 1 : 2;
+  __shared__ float2 lds[XCH ? RPB * NBUF * LW : 1];
   const int b = blockIdx.y;
   const int r = threadIdx.x / T, t = threadIdx.x % T;
   const int y = blockIdx.x * RPB + r;
   const size_t off = (size_t)b * bt.ny * NX;
-  float2* row = bt.field + off + (size_t)y * NX;
+  gptr<float2> row = to_global(bt.field + off + (size_t)y * NX);
   const float2* cx = bt.chirp + (size_t)b * (NX + bt.ny);
   const float2 cyv = FRESNEL ? cx[NX + y] : make_float2(1.f, 0.f);
-  RowEx ex;
-  ex.b[0] = lds + (XCH ? r * 2 * LW : 0);
-  ex.b[1] = ex.b[0] + (XCH ? LW : 0);
+  RowEx<WAVE> ex;
+  ex.b[0] = lds + (XCH ? r * NBUF * LW : 0);
+  ex.b[1] = ex.b[0] + (XCH && !WAVE ? LW : 0);
   ex.w = 0;
   ex.rd = 0;
   float2 v[E];
 
-  if (mode == ROW_PROP_FWD || mode == ROW_PROP_BWD) {
-    const float2* src = pin + off + (size_t)y * NX;
-    float2* dst = pout + off + (size_t)y * NX;
+  if constexpr (MODE == ROW_PROP_FWD || MODE == ROW_PROP_BWD) {
+    gptr<const float2> src = to_global(pin + off + (size_t)y * NX);
+    gptr<float2> dst = to_global(pout + off + (size_t)y * NX);
     const float s = rsqrtf((float)NX);
 #pragma unroll
     for (int j = 0; j < E; ++j) v[j] = src[t + T * j];
-    if (mode == ROW_PROP_FWD) {
+    if constexpr (MODE == ROW_PROP_FWD) {
 #pragma unroll
       for (int j = 0; j < E; ++j) v[j] = cscale(modulate<FRESNEL>(v[j], t + T * j, y, cx, cyv, false), s);
       fft<NX, E, -1>(v, t, bt.tw_x, ex);
@@ -286,49 +370,55 @@ __global__ __launch_bounds__(RPB * (NX / E)) void k_row(Batch bt, int mode, int 
     }
 #pragma unroll
     for (int j = 0; j < E; ++j) dst[t + T * j] = v[j];
-    return;
-  }
-
-  const Desc& d = bt.desc[b];
-  if (mode == ROW_ITER && arg > d.iters) return;  // uniform per block
-  if (mode == ROW_INIT) {
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int x = t + T * j;
-      const size_t idx = (size_t)y * NX + x;
-      float2 f;
-      if (d.init_field) f = d.init_field[idx];
-      else if (d.init_levels) f = level_phasor(d.init_levels[idx], d.L);
-      else f = philox_phasor(philox_pixel_word(d.seed, d.item, 1u, idx));
-      v[j] = modulate<FRESNEL>(f, x, y, cx, cyv, false);
-    }
   } else {
-    const int L = (mode == ROW_OSPR) ? 2 : d.L;
-    const bool last = (mode == ROW_OSPR) || (arg == d.iters);
-    uint8_t* lev = d.levels_out;
-    if (mode == ROW_OSPR) lev += (size_t)(arg - 1) * bt.ny * NX;
+    const Desc& d = bt.desc[b];
+    if constexpr (MODE == ROW_INIT) {
+      if (d.init_field || d.init_levels) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = row[t + T * j];
-    fft<NX, E, +1>(v, t, bt.tw_x, ex);
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int x = t + T * j;
-      const float2 g = modulate<FRESNEL>(v[j], x, y, cx, cyv, true);
-      float2 f;
-      if (L == 0) {
-        f = unit_phase(g);
+        for (int j = 0; j < E; ++j) {
+          const size_t idx = (size_t)y * NX + t + T * j;
+          v[j] = d.init_field ? d.init_field[idx] : level_phasor(d.init_levels[idx], d.L);
+        }
       } else {
-        const int k = level_index(g, L);
-        f = level_phasor(k, L);
-        if (last && lev) lev[(size_t)y * NX + x] = (uint8_t)k;
-      }
-      if (last && d.field_out && mode != ROW_OSPR) d.field_out[(size_t)y * NX + x] = f;
-      v[j] = modulate<FRESNEL>(f, x, y, cx, cyv, false);
-    }
-  }
-  fft<NX, E, -1>(v, t, bt.tw_x, ex);
+        // initial phase: Philox words over row lines; element j = g + (E/4) w
 #pragma unroll
-  for (int j = 0; j < E; ++j) row[t + T * j] = v[j];
+        for (int g = 0; g < E / 4; ++g) {
+          const U64x4 o = philox_line_block(d.seed, d.item, 1u, (uint32_t)(t + T * g), (uint32_t)y);
+#pragma unroll
+          for (int w = 0; w < 4; ++w) v[g + (E / 4) * w] = philox_phasor(u64x4_word(o, w));
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = modulate<FRESNEL>(v[j], t + T * j, y, cx, cyv, false);
+    } else {
+      if (MODE == ROW_ITER && arg > d.iters) return;  // uniform per block
+      const int L = (MODE == ROW_OSPR || LK == LK_BIN) ? 2 : d.L;
+      const bool last = (MODE == ROW_OSPR) || (arg == d.iters);
+      gptr<uint8_t> lev = to_global(d.levels_out);
+      if (MODE == ROW_OSPR) lev += (size_t)(arg - 1) * bt.ny * NX;
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = row[t + T * j];
+      fft<NX, E, +1>(v, t, bt.tw_x, ex);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int x = t + T * j;
+        const float2 g = modulate<FRESNEL>(v[j], x, y, cx, cyv, true);
+        float2 f;
+        if (L == 0) {
+          f = unit_phase(g);
+        } else {
+          const int k = level_index(g, L);
+          f = level_phasor(k, L);
+          if (last && lev) lev[(size_t)y * NX + x] = (uint8_t)k;
+        }
+        if (MODE == ROW_ITER && last && d.field_out) to_global(d.field_out)[(size_t)y * NX + x] = f;
+        v[j] = modulate<FRESNEL>(f, x, y, cx, cyv, false);
+      }
+    }
+    fft<NX, E, -1>(v, t, bt.tw_x, ex);
+#pragma unroll
+    for (int j = 0; j < E; ++j) row[t + T * j] = v[j];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -340,6 +430,7 @@ enum ColMode {
   COL_OSPR_FIRST = 3,  // T e^{i phi_1} -> inverse FFT
   COL_OSPR = 4,        // subframe arg >= 2: finish subframe arg-1, start arg
   COL_OSPR_FINAL = 5,  // finish the last subframe
+  COL_FINAL = 8,       // GS/WGS pass K + 1: NMSE partials of the final field, replay out
   COL_PROP_FWD = 6,
   COL_PROP_BWD = 7
 };
@@ -347,155 +438,166 @@ enum ColMode {
 // weighted GS: amplitude floor (unit-rms units), leak exponent, clamp
 constexpr float kWgsEps = 0.1f, kWgsGamma = 0.7f, kWMin = 1e-6f, kWMax = 1e6f;
 
-template <int NY, int E, int C>
-__global__ __launch_bounds__(C * (NY / E)) void k_col(Batch bt, int mode, int arg, int adaptive,
-                                                      const float2* pin, float2* pout) {
+template <int NY, int C, int MODE>
+__global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int adaptive, const float2* pin,
+                                                       float2* pout) {
+  constexpr int E = kE;
   using P = Plan<NY, E>;
   constexpr int T = P::T, NT = C * T;
-  __shared__ float2 lds[(NY + NY / 16) * C];
+  constexpr bool PP = col_pingpong(NY, C);
+  constexpr int TILE = (NY + NY / 16) * C;
+  __shared__ float2 lds[(PP ? 2 : 1) * TILE];
   __shared__ double red[kMaxWaves][4];
+  __shared__ double tot[4];
   __shared__ double bc;
-  const int b = blockIdx.y, blk = blockIdx.x;
+  const int b = blockIdx.y, blk = xcd_tile(blockIdx.x, gridDim.x);
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int u = blk * C + c;
   const int NX = bt.nx;
   const size_t off = (size_t)b * NY * NX;
-  float2* fld = bt.field + off;
-  ColEx<C> ex{lds, c};
+  gptr<float2> fld = to_global(bt.field + off);
+  ColEx<C, PP> ex;
+  ex.s = lds + c;
+  ex.stride = TILE;
   float2 v[E];
 
-  if (mode == COL_PROP_FWD || mode == COL_PROP_BWD) {
-    const float2* src = pin + off;
-    float2* dst = pout + off;
+  if constexpr (MODE == COL_PROP_FWD || MODE == COL_PROP_BWD) {
+    gptr<const float2> src = to_global(pin + off);
+    gptr<float2> dst = to_global(pout + off);
     const float s = rsqrtf((float)NY);
 #pragma unroll
     for (int j = 0; j < E; ++j) v[j] = src[(size_t)(t + T * j) * NX + u];
-    if (mode == COL_PROP_FWD) fft<NY, E, -1>(v, t, bt.tw_y, ex);
+    if constexpr (MODE == COL_PROP_FWD) fft<NY, E, -1>(v, t, bt.tw_y, ex);
     else fft<NY, E, +1>(v, t, bt.tw_y, ex);
 #pragma unroll
     for (int j = 0; j < E; ++j) dst[(size_t)(t + T * j) * NX + u] = cscale(v[j], s);
-    return;
-  }
-
-  const Desc& d = bt.desc[b];
-  const float* tp = bt.tprep + off;
-  __shared__ double tot[4];
-  float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f, s_w = 0.f;
-
-  if (mode == COL_GS || mode == COL_WGS) {
-    // column pass k of a problem with K iterations: k <= K iterates, k = K + 1
-    // only measures the final field (NMSE, replay out), k > K + 1 is idle.
+  } else if constexpr (MODE == COL_GS || MODE == COL_WGS || MODE == COL_FINAL) {
+    const Desc& d = bt.desc[b];
+    gptr<const float> tp = to_global(bt.tprep + off);
+    // column pass k of a problem with K iterations: k <= K iterates (GS/WGS
+    // launches), k = K + 1 only measures the final field (FINAL launch); a
+    // problem whose K does not match the launch is idle in it.
     const int k = arg;
-    if (k > d.iters + 1) return;  // uniform per block
-    const bool fin = (k == d.iters + 1);
-    float m_prev = 1.0f;
-    float* w = nullptr;
-    if (mode == COL_WGS && !fin) {
-      const double om = slot_total<NT>(bt, b, bt.slots - 1, 1, &bc);
-      const double wsum = slot_total<NT>(bt, b, k - 1, 3, &bc);
-      m_prev = (float)(wsum / (om > 0.0 ? om : 1.0));
-      w = d.user_weights ? d.weights : bt.wbuf + off;
+    if constexpr (MODE == COL_FINAL) {
+      if (k != d.iters + 1) return;  // uniform per block
+    } else {
+      if (k > d.iters) return;
+    }
+    float inv_m = 1.0f;
+    gptr<float> w = nullptr;
+    if constexpr (MODE == COL_WGS) {
+      const double om = slot_total(bt, b, bt.slots - 1, 1, &bc);
+      const double wsum = slot_total(bt, b, k - 1, 3, &bc);
+      inv_m = (float)((om > 0.0 ? om : 1.0) / wsum);
+      w = to_global(d.user_weights ? d.weights : bt.wbuf + off);
     }
 #pragma unroll
     for (int j = 0; j < E; ++j) v[j] = fld[(size_t)(t + T * j) * NX + u];
     fft<NY, E, -1>(v, t, bt.tw_y, ex);
+    float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f, s_w = 0.f;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const size_t idx = (size_t)(t + T * j) * NX + u;
       const float2 Rr = v[j];  // unscaled replay, centred index (t + T j, u)
       const float a2 = Rr.x * Rr.x + Rr.y * Rr.y;
-      const float inv = a2 > 0.f ? rsqrtf(a2) : 0.f;
+      const float inv = a2 > 0.f ? __builtin_amdgcn_rsqf(a2) : 0.f;
       const float A = a2 * inv * bt.fwd_scale;  // |R| of the unitary transform
       const float Tv = tp[idx];
       s_ta += Tv * A;
       s_aa += A * A;
       s_tt += Tv * Tv;
-      if (fin) {
-        if (d.replay_out) d.replay_out[idx] = cscale(Rr, bt.fwd_scale);
-        continue;
+      if constexpr (MODE == COL_FINAL) {
+        if (d.replay_out) to_global(d.replay_out)[idx] = cscale(Rr, bt.fwd_scale);
+      } else {
+        float amp = Tv;
+        if constexpr (MODE == COL_WGS) {
+          if (Tv > 0.f) {
+            const float ratio = fmaxf(Tv, kWgsEps) * __builtin_amdgcn_rcpf(fmaxf(A, kWgsEps));
+            const float wc = fminf(fmaxf(w[idx] * ratio * inv_m, kWMin), kWMax);
+            const float wn = __builtin_amdgcn_exp2f(kWgsGamma * __builtin_amdgcn_logf(wc));
+            w[idx] = wn;
+            s_w += wn;
+            amp = wn * Tv;
+          }
+        }
+        v[j] = a2 > 0.f ? cscale(Rr, amp * inv) : make_float2(amp, 0.f);
       }
-      float amp = Tv;
-      if (mode == COL_WGS && Tv > 0.f) {
-        const float ratio = fmaxf(Tv, kWgsEps) / fmaxf(A, kWgsEps);
-        const float wn = powf(fminf(fmaxf(w[idx] * ratio / m_prev, kWMin), kWMax), kWgsGamma);
-        w[idx] = wn;
-        s_w += wn;
-        amp = wn * Tv;
-      }
-      v[j] = a2 > 0.f ? cscale(Rr, amp * inv) : make_float2(amp, 0.f);
     }
     block_sum4<NT>(s_ta, s_aa, s_tt, s_w, red, tot);
     if (threadIdx.x == 0) {
       double* pp = part_ptr(bt, b, k - 1, blk);
       pp[0] = tot[0]; pp[1] = tot[1]; pp[2] = tot[2];
-      if (mode == COL_WGS && !fin) part_ptr(bt, b, k, blk)[3] = tot[3];
+      if (MODE == COL_WGS) part_ptr(bt, b, k, blk)[3] = tot[3];
     }
-    if (fin) return;
-    fft<NY, E, +1>(v, t, bt.tw_y, ex);
+    if constexpr (MODE != COL_FINAL) {
+      fft<NY, E, +1>(v, t, bt.tw_y, ex);
 #pragma unroll
-    for (int j = 0; j < E; ++j) fld[(size_t)(t + T * j) * NX + u] = v[j];
-    return;
-  }
-
-  // OSPR.  Subframe n's column work: finish subframe n-1 (forward FFT,
-  // accumulate, NMSE partials, feedback), then start subframe n (random
-  // replay phase, inverse FFT).
-  const int n = arg;
-  const int N = d.iters;
-  float* acc = bt.accum + off;
-  if (mode != COL_OSPR_FIRST) {
+      for (int j = 0; j < E; ++j) fld[(size_t)(t + T * j) * NX + u] = v[j];
+    }
+  } else {
+    // OSPR.  Subframe n's column work: finish subframe n-1 (forward FFT,
+    // accumulate, NMSE partials, feedback), then start subframe n (random
+    // replay phase, inverse FFT).
+    const Desc& d = bt.desc[b];
+    gptr<const float> tp = to_global(bt.tprep + off);
+    const int n = arg;
+    gptr<float> acc = to_global(bt.accum + off);
+    if constexpr (MODE != COL_OSPR_FIRST) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = fld[(size_t)(t + T * j) * NX + u];
-    fft<NY, E, -1>(v, t, bt.tw_y, ex);
-  }
-  const float inv_prev = 1.0f / (float)(n - 1);
+      for (int j = 0; j < E; ++j) v[j] = fld[(size_t)(t + T * j) * NX + u];
+      fft<NY, E, -1>(v, t, bt.tw_y, ex);
+    }
+    const float inv_prev = 1.0f / (float)(n - 1);
+    float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f;
 #pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int row = t + T * j;
-    const size_t idx = (size_t)row * NX + u;
-    const float Tv = tp[idx];
-    float Tn = Tv;
-    if (mode != COL_OSPR_FIRST) {
-      const float2 R = cscale(v[j], bt.fwd_scale);
-      const float a = (n == 2 ? 0.f : acc[idx]) + (R.x * R.x + R.y * R.y);  // A_{n-1}
-      if (mode == COL_OSPR_FINAL) {
-        if (d.accum_out) d.accum_out[idx] = a;
-      } else {
-        acc[idx] = a;
+    for (int j = 0; j < E; ++j) {
+      const size_t idx = (size_t)(t + T * j) * NX + u;
+      const float Tv = tp[idx];
+      float Tn = Tv;
+      if constexpr (MODE != COL_OSPR_FIRST) {
+        const float2 R = cscale(v[j], bt.fwd_scale);
+        const float a = (n == 2 ? 0.f : acc[idx]) + (R.x * R.x + R.y * R.y);  // A_{n-1}
+        if constexpr (MODE == COL_OSPR_FINAL) {
+          if (d.accum_out) to_global(d.accum_out)[idx] = a;
+        } else {
+          acc[idx] = a;
+        }
+        const float avg = a * inv_prev;
+        s_ta += Tv * __builtin_amdgcn_sqrtf(avg);
+        s_aa += avg;
+        s_tt += Tv * Tv;
+        if (adaptive) Tn = __builtin_amdgcn_sqrtf(fmaxf(0.f, (float)n * Tv * Tv - a));
       }
-      const float avg = a * inv_prev;
-      s_ta += Tv * sqrtf(avg);
-      s_aa += avg;
-      s_tt += Tv * Tv;
-      if (adaptive) Tn = sqrtf(fmaxf(0.f, (float)n * Tv * Tv - a));
+      v[j] = make_float2(Tn, 0.f);  // amplitude of subframe n's replay target
     }
-    if (mode != COL_OSPR_FINAL) {
-      const float2 ph = philox_phasor(philox_pixel_word(d.seed, d.item, 0x100u + (uint32_t)n, idx));
-      v[j] = cscale(ph, Tn);
+    if constexpr (MODE != COL_OSPR_FIRST) {
+      block_sum4<NT>(s_ta, s_aa, s_tt, 0.f, red, tot);
+      if (threadIdx.x == 0) {
+        double* pp = part_ptr(bt, b, n - 2, blk);
+        pp[0] = tot[0]; pp[1] = tot[1]; pp[2] = tot[2];
+      }
     }
-  }
-  if (mode != COL_OSPR_FIRST) {
-    block_sum4<NT>(s_ta, s_aa, s_tt, 0.f, red, tot);
-    if (threadIdx.x == 0) {
-      double* pp = part_ptr(bt, b, n - 2, blk);
-      pp[0] = tot[0]; pp[1] = tot[1]; pp[2] = tot[2];
-    }
-  }
-  if (mode == COL_OSPR_FINAL) return;
-  fft<NY, E, +1>(v, t, bt.tw_y, ex);
+    if constexpr (MODE != COL_OSPR_FINAL) {
+      // replay phase of subframe n: Philox words over column lines
 #pragma unroll
-  for (int j = 0; j < E; ++j) fld[(size_t)(t + T * j) * NX + u] = v[j];
-}
-
-__global__ void k_random_phase(float2* out, uint64_t seed, uint32_t item, uint32_t tag, int npix) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npix) return;
-  out[p] = philox_phasor(philox_pixel_word(seed, item, tag, (uint64_t)p));
+      for (int g = 0; g < E / 4; ++g) {
+        const U64x4 o = philox_line_block(d.seed, d.item, 0x100u + (uint32_t)n, (uint32_t)(t + T * g), (uint32_t)u);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const int j = g + (E / 4) * w;
+          v[j] = cscale(philox_phasor(u64x4_word(o, w)), v[j].x);
+        }
+      }
+      fft<NY, E, +1>(v, t, bt.tw_y, ex);
+#pragma unroll
+      for (int j = 0; j < E; ++j) fld[(size_t)(t + T * j) * NX + u] = v[j];
+    }
+  }
 }
 
 // nmse[k] = 1 - sta^2 / (stt saa) from the block partials of slot k; a GS
 // problem has iters + 1 values, an OSPR problem `iters` (= subframes).
-__global__ void k_finish(Batch bt, int count, int ospr) {
+static __global__ void k_finish(Batch bt, int count, int ospr) {
   const int b = blockIdx.x;
   const int k = threadIdx.x + blockIdx.y * blockDim.x;
   if (b >= count) return;

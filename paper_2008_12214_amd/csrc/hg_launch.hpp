@@ -1,0 +1,37 @@
+// Launch layer: the kernel configurations compiled for each transform length
+// and the launchers that pick one at run time.  Each length lives in its own
+// translation unit (hg_n<N>.hip) so the kernels build in parallel.
+#pragma once
+#include "hg_kernels.hpp"
+
+namespace hg {
+
+// Column-tile widths C compiled for a column length N (threads per tile
+// C * N / 16 between 64 and 1024).
+__host__ __device__ constexpr bool col_ok(int N, int C) {
+  switch (N) {
+    case 64: return C == 16;
+    case 128: return C == 8 || C == 16;
+    case 256: return C == 4 || C == 8 || C == 16;
+    case 512: return C == 4 || C == 8 || C == 16;
+    case 1024: return C == 4 || C == 8 || C == 16;
+    case 2048: return C == 2 || C == 4 || C == 8;
+    case 4096: return C == 2 || C == 4;
+    default: return false;
+  }
+}
+// Rows per row-pass workgroup compiled for a row length N (128 or 256 threads).
+__host__ __device__ constexpr bool rpb_ok(int N, int RPB) {
+  const int T = N / kE;
+  return (RPB * T == 128 || RPB * T == 256) || (T >= 256 && RPB == 1);
+}
+
+template <int N> void launch_col_t(int C, const Batch& bt, int B, int mode, int arg, int adaptive,
+                                   const float2* pin, float2* pout, hipStream_t st);
+template <int N> void launch_setup_t(int C, const Batch& bt, int B, int weighted, hipStream_t st);
+template <int N> void launch_row_t(int RPB, bool fresnel, int lk, const Batch& bt, int B, int mode, int arg,
+                                   const float2* pin, float2* pout, hipStream_t st);
+template <int N> void launch_twiddles_t(float2* tw, hipStream_t st);
+template <int N> constexpr int twiddle_count() { return TwLayout<N, kE>::total(); }
+
+}  // namespace hg

@@ -73,7 +73,8 @@ def test_wgs_ospr_propagate_batched_validation():
     assert L.hg_ospr(FAKE, 64, 64, 4, 1, 1, FAKE, None, None, FAKE, 16, None) == hg.HG_ERR_WORKSPACE
     assert L.hg_fresnel_propagate(FAKE, FAKE, 64, 64, 0.0, 0.0, 0.0, 0, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG
     assert L.hg_fresnel_propagate(None, FAKE, 64, 64, 0.0, 0.0, 0.0, 1, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG
-    assert L.hg_random_phase(1, 0, 1, 48, 64, FAKE, None) == hg.HG_ERR_UNSUPPORTED_SIZE
+    assert L.hg_random_phase(1, 0, 1, 1, 48, 64, FAKE, None) == hg.HG_ERR_UNSUPPORTED_SIZE
+    assert L.hg_random_phase(1, 0, 1, 2, 64, 64, FAKE, None) == hg.HG_ERR_INVALID_ARG
     assert L.hg_gs_batched(None, 0, 0, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG
     probs = (hg._binding.hg_problem * 2)()
     probs[0] = hg._binding.hg_problem(64, 64, 8, 3, 1, 0, 0, 0, 0x10000, 0x10000, None)

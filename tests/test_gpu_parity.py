@@ -68,14 +68,15 @@ def level_check(gpu_lev, ref_lev, g_ref, L):
 # ---------------------------------------------------------------------------
 # Philox and propagation
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("seed,item,tag", [(1, 0, 1), (0xDEADBEEF12345678, 7, 0x100 + 3)])
-def test_philox_phases_bit_exact(seed, item, tag):
-    say("philox", seed, item, tag)
+@pytest.mark.parametrize("seed,item,tag,axis", [(1, 0, 1, 1), (0xDEADBEEF12345678, 7, 0x100 + 3, 0),
+                                                 (5, 2, 0x100 + 24, 1)])
+def test_philox_phases_bit_exact(seed, item, tag, axis):
+    say("philox", seed, item, tag, axis)
     ny, nx = 64, 256
-    z = host(hg.hg_random_phase(seed, item, tag, ny, nx, device=DEV)).astype(np.complex128)
+    z = host(hg.hg_random_phase(seed, item, tag, axis, ny, nx, device=DEV)).astype(np.complex128)
     u_gpu = np.round(np.mod(np.angle(z) / (2 * np.pi), 1.0) * 2 ** 24).astype(np.int64) % (1 << 24)
-    words = philox.pixel_words(seed, tag, ny * nx, batch_item=item)
-    u_ref = (words >> np.uint64(40)).astype(np.int64).reshape(ny, nx)
+    words = philox.line_words(seed, tag, ny, nx, axis, batch_item=item)
+    u_ref = (words >> np.uint64(40)).astype(np.int64)
     np.testing.assert_array_equal(u_gpu, u_ref)
     np.testing.assert_allclose(np.abs(z), 1.0, atol=1e-6)
 

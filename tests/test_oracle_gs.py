@@ -78,7 +78,7 @@ def test_binary_replay_is_centrosymmetric():
 def test_weighted_binary_weights_stay_symmetric():
     T = synth.gaussian_target(32, seed=6)
     # from a binary start every replay is centro-symmetric, so are the weights
-    init = (philox.u24(philox.pixel_words(3, 1, 32 * 32)) < 0.5).astype(np.int64).reshape(32, 32)
+    init = (philox.u24(philox.line_words(3, 1, 32, 32, 1)) < 0.5).astype(np.int64)
     out = hologram.gs(T, 8, 2, init_levels=init, weighted=True)
     np.testing.assert_allclose(out["weights"], hologram.mirror(out["weights"]), rtol=1e-9)
     assert out["m"] > 0
@@ -160,7 +160,7 @@ def test_brute_force_bounds_gs_and_ds_on_4x4(L):
 
 def test_direct_search_on_8x8_reaches_local_minimum():
     T = hologram.prepare_target(synth.gaussian_target(8, seed=3), 2)
-    init = (philox.u24(philox.pixel_words(5, 1, 64)) < 0.5).astype(np.int64).reshape(8, 8)
+    init = (philox.u24(philox.line_words(5, 1, 8, 8, 1)) < 0.5).astype(np.int64)
     lev, e, sweeps = search.direct_search(T, 2, init)
     assert e <= search.replay_error(init, T, 2)
     for p in range(64):

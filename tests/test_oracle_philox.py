@@ -1,5 +1,6 @@
 """Pins for the oracle's Philox4x64-10 (published generator, Salmon et al. SC'11)."""
 import numpy as np
+import pytest
 
 from oracle import philox
 from conftest import golden
@@ -10,8 +11,8 @@ M64 = (1 << 64) - 1
 def _np_words(counter, key, n=4):
     # numpy's Philox increments its 256-bit counter before each block
     c = (sum(int(w) << (64 * i) for i, w in enumerate(counter)) - 1) % (1 << 256)
-    g = np.random.Philox(key=[int(key[0]), int(key[1])],
-                         counter=[(c >> (64 * i)) & M64 for i in range(4)])
+    g = np.random.Philox(key=np.array([int(key[0]), int(key[1])], dtype=np.uint64),
+                         counter=np.array([(c >> (64 * i)) & M64 for i in range(4)], dtype=np.uint64))
     return [int(v) for v in g.random_raw(n)]
 
 
@@ -34,13 +35,17 @@ def test_matches_numpy_philox_random_blocks():
         assert [int(g[0]) for g in got] == _np_words(ctr, key)
 
 
-def test_pixel_word_mapping_against_numpy():
-    seed, tag, b, n = 0x1234ABCD5678, 0x105, 3, 37
-    words = philox.pixel_words(seed, tag, n, batch_item=b)
+@pytest.mark.parametrize("axis", [0, 1])
+def test_line_word_mapping_against_numpy(axis):
+    seed, tag, b, ny, nx = 0x1234ABCD5678, 0x105, 3, 8, 16
+    words = philox.line_words(seed, tag, ny, nx, axis, batch_item=b)
     key = [seed, (b << 32) | tag]
-    for p in [0, 1, 2, 3, 4, 17, 36]:
-        blk = _np_words([p >> 2, 0, 0, 0], key)
-        assert int(words[p]) == blk[p & 3]
+    n = nx if axis == 1 else ny
+    for y in range(ny):
+        for x in range(nx):
+            i, l = (x, y) if axis == 1 else (y, x)
+            blk = _np_words([i % (n // 4), l, 0, 0], key)
+            assert int(words[y, x]) == blk[i // (n // 4)]
 
 
 def test_u24_exact_and_in_range():
@@ -51,5 +56,5 @@ def test_u24_exact_and_in_range():
     ph = philox.phase_field(5, philox.TAG_INIT, 16, 16)
     assert ph.min() >= 0 and ph.max() < 2 * np.pi
     # uniformity sanity on a larger draw
-    big = philox.u24(philox.pixel_words(9, 1, 1 << 16))
+    big = philox.u24(philox.line_words(9, 1, 256, 256, 1))
     assert abs(big.mean() - 0.5) < 0.01 and abs(big.var() - 1 / 12) < 0.005
