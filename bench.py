@@ -28,10 +28,49 @@ HBM_PEAK_GBS = 8000.0
 N = 1024
 LEVELS = 2
 # algorithmic HBM bytes per pixel: weighted column pass = field r+w (16) +
-# target r (4) + weights r+w (8); its final launch (NMSE only) = field r (8)
-# + target r (4); row pass = field r+w (16), + levels w (1) on the last.
-COL_BYTES, COL_FINAL_BYTES, ROW_BYTES = 28, 12, 16
+# target r (4) + weights r+w (8) on the target support only (weights
+# elsewhere are never used), i.e. 20 + 8 * support fraction; its final
+# launch (NMSE only) = field r (8) + target r (4); row pass = field r+w (16),
+# + levels w (1) on the last.
+COL_FIXED_BYTES, COL_WEIGHT_BYTES, COL_FINAL_BYTES, ROW_BYTES = 20, 8, 12, 16
 ITERS = 100
+
+
+def kernel_source_hash():
+    """sha256 of the HIP sources: ties a committed traffic measurement to the kernels it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2008_12214_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".inc")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(batch):
+    """HBM bytes per column-pass launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources and this batch; else None."""
+    path = os.path.join(ROOT, "profiles", "wgs1024_colpass_traffic.json")
+    try:
+        t = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("batch") != batch:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def copy_calibration(nbytes=1 << 30, reps=5):
+    """A plain device copy of known size, for calibrating the FETCH_SIZE/WRITE_SIZE counters."""
+    import torch
+    dev = torch.device("cuda:0")
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize(dev)
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
 
 
 def log(*a):
@@ -71,7 +110,12 @@ def main():
     ap.add_argument("--no-b1", action="store_true")
     ap.add_argument("--iters", type=int, default=100,
                     help="iterations per hologram (100 is the workload; fewer only for short profiles)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     global ITERS
     ITERS = args.iters
     if args.gpus != 1:
@@ -86,6 +130,16 @@ def main():
 
     dev = torch.device("cuda:0")
     lib = hg.lib()
+
+    def support_fraction(B):
+        """Fraction of pixels on the binary-symmetrised target support, over the batch."""
+        import numpy as np
+        tot = 0.0
+        for b in range(B):
+            T = synth.gaussian_target(N, seed=2, batch_item=b)
+            mir = T[(-np.arange(N)) % N][:, (-np.arange(N)) % N]
+            tot += float(np.mean((T > 0) | (mir > 0)))
+        return tot / B
 
     def setup(B):
         targets = [torch.from_numpy(synth.gaussian_target(N, seed=2, batch_item=b)).to(dev) for b in range(B)]
@@ -131,14 +185,16 @@ def main():
     kt = hg.hg_timing_read()
     hg.hg_timing_enable(False)
     px = N * N * B
-    col_bytes = args.steps * (ITERS * COL_BYTES + COL_FINAL_BYTES) * px
+    omega = support_fraction(B)
+    col_px_bytes = COL_FIXED_BYTES + COL_WEIGHT_BYTES * omega
+    col_bytes = args.steps * (ITERS * col_px_bytes + COL_FINAL_BYTES) * px
     # row launches: one initial pass (writes the field, 8 B/px) + ITERS passes
     row_bytes = args.steps * (8 + ITERS * ROW_BYTES + 1) * px
     col_avg_ms = kt["col_ms"] / kt["col_launches"]
     row_avg_ms = kt["row_ms"] / kt["row_launches"]
     col_gbs = col_bytes / (kt["col_ms"] * 1e-3) / 1e9
     row_gbs = row_bytes / (kt["row_ms"] * 1e-3) / 1e9
-    iter_gbs = (ITERS * (COL_BYTES + ROW_BYTES)) * px * args.steps / dt / 1e9
+    iter_gbs = (ITERS * (col_px_bytes + ROW_BYTES)) * px * args.steps / dt / 1e9
     log(f"column pass avg {col_avg_ms * 1e3:.1f} us ({col_gbs:.0f} GB/s), row pass avg {row_avg_ms * 1e3:.1f} us "
         f"({row_gbs:.0f} GB/s)")
     del step, keep
@@ -152,7 +208,7 @@ def main():
         k1 = max(args.steps, 10)
         dt1 = timed(step1, k1)
         b1 = {"iter_per_s": ITERS * k1 / dt1, "us_per_iteration": dt1 / (k1 * ITERS) * 1e6,
-              "algorithmic_GBs": (COL_BYTES + ROW_BYTES) * N * N * ITERS * k1 / dt1 / 1e9}
+              "algorithmic_GBs": (col_px_bytes + ROW_BYTES) * N * N * ITERS * k1 / dt1 / 1e9}
         log(f"B=1: {b1['iter_per_s']:.0f} iter/s, {b1['us_per_iteration']:.1f} us/iteration")
         del step1, keep1
 
@@ -169,9 +225,10 @@ def main():
         "config": {"workload": f"wgs_binary_{N}x{N}_{ITERS}it", "batch": B, "grid": [N, N], "iters": ITERS,
                    "slm_levels": LEVELS, "target": "gaussian sum, 32 blobs, central window"},
         "roofline": {"bound": "hbm", "achieved": round(col_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(col_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(col_gbs / HBM_PEAK_GBS, 4), "traffic": committed_traffic(B),
                      "kernel": "column pass k_col<1024,C,COL_WGS> (weighted GS)",
                      "bytes_per_launch": int(col_bytes / kt["col_launches"]),
+                     "bytes_per_px": round(col_px_bytes, 3), "support_fraction": round(omega, 4),
                      "avg_launch_us": round(col_avg_ms * 1e3, 2)},
         "cpu_baseline": cpu,
         "extra": {"row_pass": {"avg_launch_us": round(row_avg_ms * 1e3, 2), "achieved_GBs": round(row_gbs, 1)},
