@@ -227,6 +227,12 @@ template <class T> __device__ __forceinline__ T* launder(T* p) {
   asm volatile("" : "+v"(p));
   return p;
 }
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T> __device__ __forceinline__ gptr<T> launder(gptr<T> p) {
+  asm volatile("" : "+v"(p));
+  return p;
+}
+#endif
 
 // Unscaled length-N transform of the data held by this thread group.
 template <int N, int E, int DIR, class Ex>

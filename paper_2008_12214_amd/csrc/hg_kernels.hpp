@@ -595,6 +595,198 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
   }
 }
 
+// ---------------------------------------------------------------------------
+// column pass with wave-local transforms (NY <= 1024: the NY/16 threads of a
+// column fit in one wave).  Phases:
+//   A  coalesced tile load, thread (c, r) reads rows r + T i of column c,
+//      into a column-major LDS tile;
+//   B  each wave transforms its column(s) in LDS with wave-level ordering
+//      only (no workgroup barrier inside the transform);
+//   C  element-wise constraint back in the coalesced mapping, so target and
+//      weight traffic is coalesced too; NMSE partials;
+//   D  inverse transforms, wave-local again;
+//   E  coalesced store.
+// Four workgroup barriers in all.
+// ---------------------------------------------------------------------------
+template <int NY, int C>
+__host__ __device__ constexpr int colw_stride() {
+  // padded column length, chosen so that C columns x (64/C) rows of a wave
+  // in the coalesced mapping hit distinct bank pairs
+  return NY + NY / 16 + (((64 / C) - (NY + NY / 16)) % 32 + 32) % 32;
+}
+
+// LDS exchange inside one column region, ordered within the wave.
+struct WaveColEx {
+  float2* s;
+  __device__ void before_read() { wave_lds_sync(); }
+  __device__ void before_write() { wave_lds_sync(); }
+  __device__ float2 ld(int e) const { return s[e]; }
+  __device__ void st(int e, float2 v) { s[e] = v; }
+};
+
+template <int NY, int C, int MODE>
+__global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int adaptive, const float2* pin,
+                                                        float2* pout) {
+  constexpr int E = kE, T = NY / E, NT = C * T;
+  static_assert(T <= 64 && 64 % T == 0, "a column must fit in one wave");
+  constexpr int RS = colw_stride<NY, C>();
+  __shared__ float2 tile[C * RS];
+  __shared__ double red[kMaxWaves][4];
+  __shared__ double tot[4];
+  __shared__ double bc;
+  const int b = blockIdx.y, blk = xcd_tile(blockIdx.x, gridDim.x);
+  const int cc = threadIdx.x % C, r0 = threadIdx.x / C;  // coalesced mapping
+  const int cw = threadIdx.x / T, tw = threadIdx.x % T;  // wave mapping
+  const int u = blk * C + cc;
+  const int NX = bt.nx;
+  const size_t off = (size_t)b * NY * NX;
+  gptr<float2> fld = to_global(bt.field + off);
+  float2* mine = tile + cc * RS;  // column cc, coalesced mapping
+  WaveColEx ex{tile + cw * RS};   // column cw, wave mapping
+  const Desc& d = bt.desc[b];
+  gptr<const float> tp = to_global(bt.tprep + off);
+  constexpr bool GSK = (MODE == COL_GS || MODE == COL_WGS || MODE == COL_FINAL);
+  const int k = arg;  // GS: column pass of iteration k; OSPR: subframe n = arg
+  if constexpr (MODE == COL_FINAL) {
+    if (k != d.iters + 1) return;  // uniform per block
+  } else if constexpr (MODE == COL_GS || MODE == COL_WGS) {
+    if (k > d.iters) return;
+  }
+  float inv_m = 1.0f;
+  gptr<float> w = nullptr;
+  if constexpr (MODE == COL_WGS) {
+    const double om = slot_total(bt, b, bt.slots - 1, 1, &bc);
+    const double wsum = slot_total(bt, b, k - 1, 3, &bc);
+    inv_m = (float)((om > 0.0 ? om : 1.0) / wsum);
+    w = to_global(d.user_weights ? d.weights : bt.wbuf + off);
+  }
+  float2 v[E];
+
+  // A + B: forward column transform of the field
+  if constexpr (MODE != COL_OSPR_FIRST) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = fld[(size_t)(r0 + T * i) * NX + u];
+#pragma unroll
+    for (int i = 0; i < E; ++i) mine[lds_pad(r0 + T * i)] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = ex.s[lds_pad(tw + T * j)];
+    fft<NY, E, -1>(v, tw, bt.tw_y, ex);
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < E; ++j) ex.s[lds_pad(tw + T * j)] = v[j];
+    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);  // keep phase C's loads out of the transform
+  }
+
+  // C: element-wise, coalesced mapping (rows r0 + T i of column u).  The
+  // table pointers are re-derived here so their loads are not hoisted above
+  // the transform, where they would hold registers through it.
+  tp = launder(tp);
+  if constexpr (MODE == COL_WGS) w = launder(w);
+  float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f, s_w = 0.f;
+  if constexpr (GSK) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int row = r0 + T * i;
+      const size_t idx = (size_t)row * NX + u;
+      const float2 Rr = mine[lds_pad(row)];  // unscaled replay at centred index (row, u)
+      const float a2 = Rr.x * Rr.x + Rr.y * Rr.y;
+      const float inv = a2 > 0.f ? __builtin_amdgcn_rsqf(a2) : 0.f;
+      const float A = a2 * inv * bt.fwd_scale;  // |R| of the unitary transform
+      const float Tv = tp[idx];
+      s_ta += Tv * A;
+      s_aa += A * A;
+      s_tt += Tv * Tv;
+      if constexpr (MODE == COL_FINAL) {
+        if (d.replay_out) to_global(d.replay_out)[idx] = cscale(Rr, bt.fwd_scale);
+      } else {
+        float amp = Tv;
+        if constexpr (MODE == COL_WGS) {
+          if (Tv > 0.f) {
+            const float ratio = fmaxf(Tv, kWgsEps) * __builtin_amdgcn_rcpf(fmaxf(A, kWgsEps));
+            const float wc = fminf(fmaxf(w[idx] * ratio * inv_m, kWMin), kWMax);
+            const float wn = __builtin_amdgcn_exp2f(kWgsGamma * __builtin_amdgcn_logf(wc));
+            w[idx] = wn;
+            s_w += wn;
+            amp = wn * Tv;
+          }
+        }
+        mine[lds_pad(row)] = a2 > 0.f ? cscale(Rr, amp * inv) : make_float2(amp, 0.f);
+      }
+    }
+    block_sum4<NT>(s_ta, s_aa, s_tt, s_w, red, tot);  // ends with a barrier
+    if (threadIdx.x == 0) {
+      double* pp = part_ptr(bt, b, k - 1, blk);
+      pp[0] = tot[0]; pp[1] = tot[1]; pp[2] = tot[2];
+      if (MODE == COL_WGS) part_ptr(bt, b, k, blk)[3] = tot[3];
+    }
+  } else {
+    // OSPR: finish subframe n-1 (accumulate, NMSE partials, feedback), start
+    // subframe n (random replay phase).  Element i = g + 4 w' of this thread
+    // shares a Philox block with its quarter-column siblings.
+    const int n = arg;
+    gptr<float> acc = to_global(bt.accum + off);
+    const float inv_prev = 1.0f / (float)(n - 1);
+    float amp[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int row = r0 + T * i;
+      const size_t idx = (size_t)row * NX + u;
+      const float Tv = tp[idx];
+      float Tn = Tv;
+      if constexpr (MODE != COL_OSPR_FIRST) {
+        const float2 R = cscale(mine[lds_pad(row)], bt.fwd_scale);
+        const float a = (n == 2 ? 0.f : acc[idx]) + (R.x * R.x + R.y * R.y);  // A_{n-1}
+        if constexpr (MODE == COL_OSPR_FINAL) {
+          if (d.accum_out) to_global(d.accum_out)[idx] = a;
+        } else {
+          acc[idx] = a;
+        }
+        const float avg = a * inv_prev;
+        s_ta += Tv * __builtin_amdgcn_sqrtf(avg);
+        s_aa += avg;
+        s_tt += Tv * Tv;
+        if (adaptive) Tn = __builtin_amdgcn_sqrtf(fmaxf(0.f, (float)n * Tv * Tv - a));
+      }
+      amp[i] = Tn;
+    }
+    if constexpr (MODE != COL_OSPR_FINAL) {
+#pragma unroll
+      for (int g = 0; g < E / 4; ++g) {
+        const U64x4 o = philox_line_block(d.seed, d.item, 0x100u + (uint32_t)n, (uint32_t)(r0 + T * g), (uint32_t)u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = g + (E / 4) * q;
+          mine[lds_pad(r0 + T * i)] = cscale(philox_phasor(u64x4_word(o, q)), amp[i]);
+        }
+      }
+    }
+    if constexpr (MODE != COL_OSPR_FIRST) {
+      block_sum4<NT>(s_ta, s_aa, s_tt, 0.f, red, tot);  // ends with a barrier
+      if (threadIdx.x == 0) {
+        double* pp = part_ptr(bt, b, n - 2, blk);
+        pp[0] = tot[0]; pp[1] = tot[1]; pp[2] = tot[2];
+      }
+    } else {
+      __syncthreads();
+    }
+  }
+  if constexpr (MODE == COL_FINAL || MODE == COL_OSPR_FINAL) return;
+  __builtin_amdgcn_sched_barrier(0);
+
+  // D + E: inverse column transform, coalesced store
+#pragma unroll
+  for (int j = 0; j < E; ++j) v[j] = ex.s[lds_pad(tw + T * j)];
+  fft<NY, E, +1>(v, tw, bt.tw_y, ex);
+  wave_lds_sync();
+#pragma unroll
+  for (int j = 0; j < E; ++j) ex.s[lds_pad(tw + T * j)] = v[j];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < E; ++i) fld[(size_t)(r0 + T * i) * NX + u] = mine[lds_pad(r0 + T * i)];
+}
+
 // nmse[k] = 1 - sta^2 / (stt saa) from the block partials of slot k; a GS
 // problem has iters + 1 values, an OSPR problem `iters` (= subframes).
 static __global__ void k_finish(Batch bt, int count, int ospr) {
