@@ -17,10 +17,14 @@ Network reading (U-Net encoder-decoder):
            phase is arg(a + i b).
 Weights are OHWI: w[co][ky][kx][ci]; conv(x)[n,y,x,co] =
   bias[co] + sum_{ky,kx,ci} x[n, y+ky-1, x+kx-1, ci] w[co,ky,kx,ci].
-Loss (global-phase invariant): 1 - |sum_p a_p z_p conj(e^{i psi_p})| / sum_p a_p
-with z_p = (a + i b)/|a + i b| and a_p the target amplitude.
+Loss (global-phase invariant, per image): 1 - |sum_p a_p z_p conj(e^{i psi_p})| /
+sum_p a_p with z_p = (a + i b)/|a + i b| and a_p the target amplitude,
+averaged over the images of a batch.
 """
 import numpy as np
+
+from . import hologram as _holo
+from . import slm as _slm
 
 ENC = (16, 32, 64, 128)
 
@@ -160,23 +164,33 @@ def forward(p, x, enc=ENC, round_bf16=False):
 
 
 def phase_loss(out, psi, amp):
-    """Global-phase-invariant loss and its gradient with respect to out."""
+    """Global-phase-invariant loss and its gradient with respect to out.
+
+    Each image n has its own free global phase, so its loss is
+    l_n = 1 - |S_n| / W_n with S_n = sum_p amp z conj(e^{i psi}) and
+    W_n = sum_p amp over that image; the batch loss is the mean of l_n.
+    Arrays carry the batch as their leading axis.
+    """
     a, b = out[..., 0], out[..., 1]
+    nb = a.shape[0]
+    axes = tuple(range(1, a.ndim))
     r = np.sqrt(a * a + b * b) + 1e-12
     z = (a + 1j * b) / r
     y = np.exp(1j * psi)
-    S = np.sum(amp * z * np.conj(y))
-    W = np.sum(amp)
-    loss = 1.0 - np.abs(S) / W
-    # d|S|/dz* contribution: d loss/d z = -(1/W) * amp * conj(y) * S*/(2|S|) ... use real form
-    s_hat = S / (np.abs(S) + 1e-300)
-    # loss = 1 - Re(conj(s_hat) S)/W locally; d/d(a,b) of Re(conj(s_hat) amp z conj(y))
-    c = amp * np.conj(s_hat) * np.conj(y)  # coefficient multiplying z
-    # z = (a + ib)/r; dz/da = (1/r) - a(a+ib)/r^3, dz/db = i/r - b(a+ib)/r^3
+    S = np.sum(amp * z * np.conj(y), axis=axes)
+    W = np.sum(amp, axis=axes)
+    loss = float(np.mean(1.0 - np.abs(S) / W))
+    # Near the current point |S_n| = Re(conj(s_hat_n) S_n) with s_hat_n = S_n/|S_n|,
+    # so d l_n/d(a, b) = -Re(conj(s_hat_n) amp conj(y) dz/d(a, b)) / W_n.
+    shp = (nb,) + (1,) * (a.ndim - 1)
+    s_hat = (S / (np.abs(S) + 1e-300)).reshape(shp)
+    c = amp * np.conj(s_hat) * np.conj(y)
+    # z = (a + ib)/r: dz/da = 1/r - a(a+ib)/r^3, dz/db = i/r - b(a+ib)/r^3
     dz_da = 1.0 / r - a * (a + 1j * b) / r ** 3
     dz_db = 1j / r - b * (a + 1j * b) / r ** 3
-    ga = -np.real(c * dz_da) / W
-    gb = -np.real(c * dz_db) / W
+    scale = (W * nb).reshape(shp)
+    ga = -np.real(c * dz_da) / scale
+    gb = -np.real(c * dz_db) / scale
     return loss, np.stack([ga, gb], axis=-1)
 
 
@@ -217,3 +231,34 @@ def adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         mh = m[k] / (1 - b1 ** t)
         vh = v[k] / (1 - b2 ** t)
         p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
+
+
+def normalise_input(T):
+    """Network input: each target image scaled to unit rms, sum T^2 = H W
+    (the same automatic scaling the hologram loops apply); shape [n, h, w, 1]."""
+    T = np.asarray(T, np.float64)
+    n = T.shape[0]
+    hw = T[0].size
+    s = np.sqrt(hw / np.sum(T.reshape(n, -1) ** 2, axis=1))
+    return (T * s.reshape((n,) + (1,) * (T.ndim - 1)))[..., None]
+
+
+def quadratic_phase(ny, nx):
+    """Deterministic replay-plane start phase for label generation:
+    psi0[v][u] = 2 pi ((u - nx/2)^2 / nx + (v - ny/2)^2 / ny), centred indices."""
+    u = np.arange(nx) - nx // 2
+    v = np.arange(ny) - ny // 2
+    return 2.0 * np.pi * ((u[None, :] ** 2 % nx) / nx + (v[:, None] ** 2 % ny) / ny)
+
+
+def replay_phase_levels(T, phasor, L):
+    """SLM start levels from a replay-plane phase: P_L(IDFT(T e^{i arg phasor})).
+
+    phasor is a complex centred array (a zero entry counts as phase 0).
+    Returns (levels, g) with g the field before projection."""
+    y = np.asarray(phasor, np.complex128)
+    mag = np.abs(y)
+    unit = np.where(mag > 0, y / np.where(mag > 0, mag, 1.0), 1.0 + 0j)
+    g = _holo.backward(np.asarray(T, np.float64) * unit)
+    _, levels = _slm.project(g, L)
+    return levels, g

@@ -65,13 +65,29 @@ def test_loss_invariant_to_global_phase_and_zero_when_exact():
     assert abs(loss) < 1e-12
 
 
+def test_batch_loss_is_mean_of_image_losses():
+    rng = np.random.default_rng(7)
+    out = rng.standard_normal((2, 5, 6, 2))
+    psi = rng.uniform(-np.pi, np.pi, (2, 5, 6))
+    amp = rng.random((2, 5, 6))
+    lb, gb = nn.phase_loss(out, psi, amp)
+    l0, g0 = nn.phase_loss(out[:1], psi[:1], amp[:1])
+    l1, g1 = nn.phase_loss(out[1:], psi[1:], amp[1:])
+    assert lb == pytest.approx(0.5 * (l0 + l1), rel=1e-14)
+    np.testing.assert_allclose(gb, 0.5 * np.concatenate([g0, g1]), rtol=1e-13, atol=1e-16)
+    # a separate global phase per image leaves the loss at zero
+    ph = np.array([0.3, -2.0])[:, None, None]
+    exact = np.stack([np.cos(psi + ph), np.sin(psi + ph)], axis=-1) * 2.0
+    assert abs(nn.phase_loss(exact, psi, amp)[0]) < 1e-12
+
+
 def test_network_gradient_finite_differences():
     rng = np.random.default_rng(5)
     enc = (3, 4, 5)
     p = nn.init_params(rng, enc)
-    x = rng.random((1, 8, 8, 1))
-    psi = rng.uniform(-np.pi, np.pi, (1, 8, 8))
-    amp = rng.random((1, 8, 8)) + 0.1
+    x = rng.random((2, 8, 8, 1))
+    psi = rng.uniform(-np.pi, np.pi, (2, 8, 8))
+    amp = rng.random((2, 8, 8)) + 0.1
     out, cache = nn.forward(p, x, enc)
     loss, dout = nn.phase_loss(out, psi, amp)
     g = nn.backward(p, cache, dout, enc)
@@ -104,3 +120,34 @@ def test_adam_matches_torch():
         pt.grad = _t(g)
         opt.step()
     np.testing.assert_allclose(p["a"], pt.detach().numpy(), rtol=1e-12, atol=1e-12)
+
+
+def test_normalise_input_unit_rms():
+    rng = np.random.default_rng(8)
+    T = rng.random((3, 6, 10)) * np.array([1.0, 5.0, 0.01])[:, None, None]
+    x = nn.normalise_input(T)
+    assert x.shape == (3, 6, 10, 1)
+    np.testing.assert_allclose(np.mean(x[..., 0] ** 2, axis=(1, 2)), 1.0, rtol=1e-13)
+    np.testing.assert_allclose(x[1, ..., 0] / x[1, 0, 0, 0], T[1] / T[1, 0, 0], rtol=1e-13)
+
+
+def test_quadratic_phase_values():
+    ny, nx = 8, 16
+    psi = nn.quadratic_phase(ny, nx)
+    for v, u in [(0, 0), (4, 8), (7, 3), (1, 15)]:
+        ref = 2 * np.pi * ((u - 8) ** 2 / 16 + (v - 4) ** 2 / 8)
+        assert np.exp(1j * psi[v, u]) == pytest.approx(np.exp(1j * ref), abs=1e-12)
+    assert psi[4, 8] == 0.0
+
+
+def test_replay_phase_levels_recovers_consistent_hologram():
+    # If the replay phase is that of a quantised hologram whose replay
+    # amplitude is the target, the inverse transform returns that hologram.
+    from oracle import hologram, slm
+    rng = np.random.default_rng(9)
+    L = 8
+    lev = rng.integers(0, L, (16, 16))
+    R = hologram.forward(slm.level_phasor(lev, L))
+    got, g = nn.replay_phase_levels(np.abs(R), R * 3.7, L)
+    np.testing.assert_array_equal(got, lev)
+    np.testing.assert_allclose(g, slm.level_phasor(lev, L), atol=1e-12)
