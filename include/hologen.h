@@ -153,14 +153,17 @@ hg_status hg_random_phase(uint64_t seed, uint32_t item, uint32_t tag, int axis, 
  * many independent GS problems of possibly different sizes in one call.
  * Problems are grouped by (ny, nx); each group runs as one batched launch
  * per pass.  Per-problem fields mirror hg_gs (Philox item = index in the
- * array, so problem b draws key (seed, (b << 32) | 1)).                      */
+ * array, so problem b draws key (seed, (b << 32) | 1) unless init_levels
+ * is given).                                                                 */
 typedef struct hg_problem {
   int ny, nx, slm_levels, iters;
   uint64_t seed;
   double wavelength_m, pitch_m, z_m;
   const float* target;
-  uint8_t* levels_out;   /* required when slm_levels >= 2 */
-  double* nmse_out;      /* nullable, iters+1 */
+  uint8_t* levels_out;          /* required when slm_levels >= 2 */
+  double* nmse_out;             /* nullable, iters+1 */
+  const uint8_t* init_levels;   /* nullable start levels (slm_levels >= 2) */
+  hg_complex* replay_out;       /* nullable centred replay of the final field */
 } hg_problem;
 
 size_t hg_gs_batched_workspace_size(const hg_problem* problems, int count);

@@ -1,7 +1,7 @@
 """MI355X-native hologram generation (HoloGen's iterative Fourier transform hot path).
 
 The compute path is the HIP library ``libhologen.so`` (C ABI in
-``include/hologen.h``).  This package is a thin ctypes binding with the same
+``include/hologen.h`` and ``include/hologen_nn.h``).  This package is a thin ctypes binding with the same
 entry-point names: it checks tensor placement, allocates outputs and the
 workspace through PyTorch, and passes raw device pointers and the current
 stream.  Every step of the path runs in the library's kernels; there is no
@@ -14,4 +14,8 @@ from ._binding import (  # noqa: F401
     hg_workspace_size, hg_gs, hg_wgs, hg_ospr, hg_fresnel_propagate,
     hg_gs_batched, hg_gs_batched_workspace_size, hg_random_phase, hg_status_string, hg_last_error,
     hg_timing_enable, hg_timing_read, hg_autotune, hg_set_launch_config, hg_get_launch_config,
+    hg_nn_param_count, hg_nn_workspace_size, hg_nn_workspace, hg_nn_forward, hg_nn_backward, hg_nn_adam,
+    hg_replay_phase_init, hg_nn_pack_weights, hg_nn_conv3x3, hg_nn_conv3x3_wgrad, hg_nn_avgpool2,
+    hg_nn_avgpool2_backward, hg_nn_upsample_concat, hg_nn_upsample_concat_backward, hg_nn_head,
+    hg_nn_head_backward, hg_nn_phase_loss,
 )

@@ -1,4 +1,4 @@
-"""ctypes binding of include/hologen.h (argument marshalling only).
+"""ctypes binding of include/hologen.h and include/hologen_nn.h (argument marshalling only).
 
 Each ``hg_*`` function here has the name and meaning of the C entry point.
 Tensors must live on the GPU the library runs on; outputs and the
@@ -36,7 +36,8 @@ class hg_kernel_times(ctypes.Structure):
 class hg_problem(ctypes.Structure):
     _fields_ = [("ny", _i), ("nx", _i), ("slm_levels", _i), ("iters", _i), ("seed", _u64),
                 ("wavelength_m", _d), ("pitch_m", _d), ("z_m", _d),
-                ("target", _vp), ("levels_out", _vp), ("nmse_out", _vp)]
+                ("target", _vp), ("levels_out", _vp), ("nmse_out", _vp),
+                ("init_levels", _vp), ("replay_out", _vp)]
 
 
 _LIB = None
@@ -91,6 +92,7 @@ def lib():
         L.hg_status_string.argtypes = [_i]
         L.hg_last_error.restype = ctypes.c_char_p
         L.hg_last_error.argtypes = []
+        _declare_nn(L)
         _LIB = L
     return _LIB
 
@@ -263,7 +265,9 @@ def _problem_array(problems):
                             p.get("wavelength_m", 0.0), p.get("pitch_m", 0.0), p.get("z_m", 0.0),
                             p["target"].data_ptr() if p.get("target") is not None else None,
                             p["levels_out"].data_ptr() if p.get("levels_out") is not None else None,
-                            p["nmse_out"].data_ptr() if p.get("nmse_out") is not None else None)
+                            p["nmse_out"].data_ptr() if p.get("nmse_out") is not None else None,
+                            p["init_levels"].data_ptr() if p.get("init_levels") is not None else None,
+                            p["replay_out"].data_ptr() if p.get("replay_out") is not None else None)
     return arr
 
 
@@ -272,29 +276,275 @@ def hg_gs_batched_workspace_size(problems):
     return int(lib().hg_gs_batched_workspace_size(arr, len(problems)))
 
 
-def hg_gs_batched(targets, iters, slm_levels, seeds=None, optics=None, weighted=False, stream=None,
-                  workspace=None):
+def hg_gs_batched(targets, iters, slm_levels, seeds=None, optics=None, weighted=False, init_levels=None,
+                  want_replay=False, stream=None, workspace=None):
     """Many GS problems (possibly of different sizes) in one call.
 
     targets: list of float32 CUDA tensors; optics: optional list of
-    (wavelength_m, pitch_m, z_m) per problem.  Returns (levels, nmse) lists.
+    (wavelength_m, pitch_m, z_m) per problem; init_levels: optional list of
+    uint8 start levels (entries may be None).  Returns (levels, nmse) lists,
+    plus the list of final centred replays when want_replay.
     """
     torch = _torch()
     dev = targets[0].device
-    probs, levels, nmses = [], [], []
+    probs, levels, nmses, replays = [], [], [], []
     for i, t in enumerate(targets):
         ny, nx = t.shape
         _dev_tensor(t, torch.float32, (ny, nx), f"targets[{i}]")
         lv = torch.empty((ny, nx), dtype=torch.uint8, device=dev) if slm_levels >= 2 else None
         nm = torch.empty(iters + 1, dtype=torch.float64, device=dev)
+        rp = torch.empty((ny, nx), dtype=torch.complex64, device=dev) if want_replay else None
+        il = init_levels[i] if init_levels is not None else None
+        if il is not None:
+            _dev_tensor(il, torch.uint8, (ny, nx), f"init_levels[{i}]")
         lam, pit, z = optics[i] if optics is not None else (0.0, 0.0, 0.0)
         probs.append(dict(ny=ny, nx=nx, slm_levels=slm_levels, iters=iters,
                           seed=(seeds[i] if seeds is not None else 0), wavelength_m=lam, pitch_m=pit, z_m=z,
-                          target=t, levels_out=lv, nmse_out=nm))
+                          target=t, levels_out=lv, nmse_out=nm, init_levels=il, replay_out=rp))
         levels.append(lv)
         nmses.append(nm)
+        replays.append(rp)
     arr = _problem_array(probs)
     nbytes = int(lib().hg_gs_batched_workspace_size(arr, len(probs)))
     ws = _workspace(nbytes, dev, workspace)
     _check(lib().hg_gs_batched(arr, len(probs), int(bool(weighted)), _ptr(ws), ws.numel(), _stream(dev, stream)))
-    return levels, nmses
+    return (levels, nmses, replays) if want_replay else (levels, nmses)
+
+
+# ---------------------------------------------------------------------------
+# learned initialisation (include/hologen_nn.h)
+# ---------------------------------------------------------------------------
+_l = ctypes.c_long
+
+
+def _declare_nn(L):
+    sig = {
+        "hg_nn_param_count": (_l, []),
+        "hg_nn_workspace_size": (_sz, [_i, _i, _i]),
+        "hg_nn_forward": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp, _sz, _vp]),
+        "hg_nn_backward": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _sz, _vp]),
+        "hg_nn_adam": (_i, [_vp, _vp, _vp, _vp, _l, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                            ctypes.c_float, _i, _vp]),
+        "hg_replay_phase_init_workspace_size": (_sz, [_i, _i, _i]),
+        "hg_replay_phase_init": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _sz, _vp]),
+        "hg_nn_kpad": (_i, [_i]),
+        "hg_nn_pack_weights": (_i, [_vp, _vp, _i, _i, _i, _vp]),
+        "hg_nn_conv3x3": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _vp]),
+        "hg_nn_wgrad_workspace_size": (_sz, [_i, _i, _i, _i, _i]),
+        "hg_nn_conv3x3_wgrad": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _sz, _vp]),
+        "hg_nn_avgpool2": (_i, [_vp, _vp, _i, _i, _i, _i, _vp]),
+        "hg_nn_avgpool2_backward": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _vp]),
+        "hg_nn_upsample_concat": (_i, [_vp, _vp, _vp, _i, _i, _i, _i, _i, _vp]),
+        "hg_nn_upsample_concat_backward": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp]),
+        "hg_nn_head": (_i, [_vp, _vp, _vp, _vp, _l, _i, _vp]),
+        "hg_nn_head_workspace_size": (_sz, [_i]),
+        "hg_nn_head_backward": (_i, [_vp, _vp, _vp, _vp, _vp, _l, _i, _vp, _sz, _vp]),
+        "hg_nn_loss_workspace_size": (_sz, [_i]),
+        "hg_nn_phase_loss": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _l, _vp, _sz, _vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def _need(t, dtype, name, ndim=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous() or (ndim is not None and t.dim() != ndim):
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor" + (f" with {ndim} dims" if ndim else ""))
+    return t
+
+
+def hg_nn_param_count():
+    return int(lib().hg_nn_param_count())
+
+
+def hg_nn_workspace_size(batch, h, w):
+    return int(lib().hg_nn_workspace_size(batch, h, w))
+
+
+def hg_nn_workspace(batch, h, w, device="cuda"):
+    """A workspace tensor for hg_nn_forward / hg_nn_backward at this shape."""
+    torch = _torch()
+    n = hg_nn_workspace_size(batch, h, w)
+    if n == 0:
+        raise HologenError(HG_ERR_UNSUPPORTED_SIZE, "network shape unsupported (h, w multiples of 8)")
+    return torch.empty(n, dtype=torch.uint8, device=torch.device(device))
+
+
+def hg_nn_forward(params, target, workspace, out=None, stream=None):
+    """Head output [B, H, W, 2] float32 for targets [B, H, W]; activations stay in `workspace`."""
+    torch = _torch()
+    _need(params, torch.float32, "params", 1)
+    _need(target, torch.float32, "target", 3)
+    b, h, w = target.shape
+    dev = target.device
+    if out is None:
+        out = torch.empty((b, h, w, 2), dtype=torch.float32, device=dev)
+    _need(out, torch.float32, "out", 4)
+    _check(lib().hg_nn_forward(_ptr(params), _ptr(target), b, h, w, _ptr(out), _ptr(workspace), workspace.numel(),
+                               _stream(dev, stream)))
+    return out
+
+
+def hg_nn_backward(params, out, label, amp, workspace, grads=None, stream=None):
+    """(grads, per-image loss) of the phase loss; follows hg_nn_forward on the same workspace."""
+    torch = _torch()
+    _need(params, torch.float32, "params", 1)
+    _need(out, torch.float32, "out", 4)
+    _need(label, torch.complex64, "label", 3)
+    _need(amp, torch.float32, "amp", 3)
+    b, h, w = amp.shape
+    dev = amp.device
+    if grads is None:
+        grads = torch.empty_like(params)
+    loss = torch.empty(b, dtype=torch.float32, device=dev)
+    _check(lib().hg_nn_backward(_ptr(params), _ptr(out), _ptr(label), _ptr(amp), b, h, w, _ptr(grads), _ptr(loss),
+                                _ptr(workspace), workspace.numel(), _stream(dev, stream)))
+    return grads, loss
+
+
+def hg_nn_adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    torch = _torch()
+    for t, n in ((params, "params"), (grads, "grads"), (m, "m"), (v, "v")):
+        _need(t, torch.float32, n)
+    _check(lib().hg_nn_adam(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.numel(), lr, beta1, beta2, eps,
+                            int(step), _stream(params.device, stream)))
+
+
+def hg_replay_phase_init(target, slm_levels, phasor=None, stream=None):
+    """SLM start levels P_L(IDFT(T e^{i arg phasor})) for targets [B, ny, nx] (phasor None: quadratic)."""
+    torch = _torch()
+    _need(target, torch.float32, "target", 3)
+    b, ny, nx = target.shape
+    dev = target.device
+    if phasor is not None:
+        if phasor.dtype == torch.float32 and phasor.dim() == 4 and phasor.shape[-1] == 2:
+            phasor = phasor.contiguous()
+        else:
+            _need(phasor, torch.complex64, "phasor", 3)
+    levels = torch.empty((b, ny, nx), dtype=torch.uint8, device=dev)
+    n = int(lib().hg_replay_phase_init_workspace_size(b, ny, nx))
+    ws = _workspace(n, dev, None)
+    _check(lib().hg_replay_phase_init(_ptr(phasor), _ptr(target), b, ny, nx, slm_levels, _ptr(levels), _ptr(ws),
+                                      ws.numel(), _stream(dev, stream)))
+    return levels
+
+
+def hg_nn_pack_weights(w, flip=False, stream=None):
+    """bf16 GEMM operand from OHWI float32 weights [cout, 3, 3, cin]."""
+    torch = _torch()
+    _need(w, torch.float32, "w", 4)
+    cout, _, _, cin = w.shape
+    rows, k = (cin, 9 * cout) if flip else (cout, 9 * cin)
+    wg = torch.empty((rows, int(lib().hg_nn_kpad(k))), dtype=torch.bfloat16, device=w.device)
+    _check(lib().hg_nn_pack_weights(_ptr(w), _ptr(wg), cout, cin, int(bool(flip)), _stream(w.device, stream)))
+    return wg
+
+
+def hg_nn_conv3x3(x, wg, cout, bias=None, mask=None, relu=False, stream=None):
+    torch = _torch()
+    _need(x, torch.bfloat16, "x", 4)
+    n, h, w, cin = x.shape
+    y = torch.empty((n, h, w, cout), dtype=torch.bfloat16, device=x.device)
+    _check(lib().hg_nn_conv3x3(_ptr(x), _ptr(wg), _ptr(bias), _ptr(mask), _ptr(y), n, h, w, cin, cout,
+                               int(bool(relu)), _stream(x.device, stream)))
+    return y
+
+
+def hg_nn_conv3x3_wgrad(x, dy, stream=None):
+    torch = _torch()
+    _need(x, torch.bfloat16, "x", 4)
+    _need(dy, torch.bfloat16, "dy", 4)
+    n, h, w, cin = x.shape
+    cout = dy.shape[3]
+    dw = torch.empty((cout, 3, 3, cin), dtype=torch.float32, device=x.device)
+    db = torch.empty(cout, dtype=torch.float32, device=x.device)
+    ws = _workspace(int(lib().hg_nn_wgrad_workspace_size(n, h, w, cin, cout)), x.device, None)
+    _check(lib().hg_nn_conv3x3_wgrad(_ptr(x), _ptr(dy), _ptr(dw), _ptr(db), n, h, w, cin, cout, _ptr(ws),
+                                     ws.numel(), _stream(x.device, stream)))
+    return dw, db
+
+
+def hg_nn_avgpool2(x, stream=None):
+    torch = _torch()
+    _need(x, torch.bfloat16, "x", 4)
+    n, h, w, c = x.shape
+    y = torch.empty((n, h // 2, w // 2, c), dtype=torch.bfloat16, device=x.device)
+    _check(lib().hg_nn_avgpool2(_ptr(x), _ptr(y), n, h, w, c, _stream(x.device, stream)))
+    return y
+
+
+def hg_nn_avgpool2_backward(dy, dskip=None, mask=None, stream=None):
+    torch = _torch()
+    _need(dy, torch.bfloat16, "dy", 4)
+    n, h2, w2, c = dy.shape
+    dx = torch.empty((n, 2 * h2, 2 * w2, c), dtype=torch.bfloat16, device=dy.device)
+    _check(lib().hg_nn_avgpool2_backward(_ptr(dy), _ptr(dskip), _ptr(mask), _ptr(dx), n, 2 * h2, 2 * w2, c,
+                                         _stream(dy.device, stream)))
+    return dx
+
+
+def hg_nn_upsample_concat(lo, skip, stream=None):
+    torch = _torch()
+    _need(lo, torch.bfloat16, "lo", 4)
+    _need(skip, torch.bfloat16, "skip", 4)
+    n, h, w, c2 = skip.shape
+    c1 = lo.shape[3]
+    out = torch.empty((n, h, w, c1 + c2), dtype=torch.bfloat16, device=lo.device)
+    _check(lib().hg_nn_upsample_concat(_ptr(lo), _ptr(skip), _ptr(out), n, h, w, c1, c2, _stream(lo.device, stream)))
+    return out
+
+
+def hg_nn_upsample_concat_backward(dout, c1, mask_lo=None, stream=None):
+    torch = _torch()
+    _need(dout, torch.bfloat16, "dout", 4)
+    n, h, w, c = dout.shape
+    c2 = c - c1
+    dlo = torch.empty((n, h // 2, w // 2, c1), dtype=torch.bfloat16, device=dout.device)
+    dskip = torch.empty((n, h, w, c2), dtype=torch.bfloat16, device=dout.device)
+    _check(lib().hg_nn_upsample_concat_backward(_ptr(dout), _ptr(mask_lo), _ptr(dlo), _ptr(dskip), n, h, w, c1, c2,
+                                                _stream(dout.device, stream)))
+    return dlo, dskip
+
+
+def hg_nn_head(x, w, b, stream=None):
+    torch = _torch()
+    _need(x, torch.bfloat16, "x")
+    c = x.shape[-1]
+    pixels = x.numel() // c
+    out = torch.empty(tuple(x.shape[:-1]) + (2,), dtype=torch.float32, device=x.device)
+    _check(lib().hg_nn_head(_ptr(x), _ptr(w), _ptr(b), _ptr(out), pixels, c, _stream(x.device, stream)))
+    return out
+
+
+def hg_nn_head_backward(dout, w, x, stream=None):
+    """(dx, dwb): dwb = weight gradient [2, c] flattened, then bias gradient [2]."""
+    torch = _torch()
+    _need(x, torch.bfloat16, "x")
+    c = x.shape[-1]
+    pixels = x.numel() // c
+    dx = torch.empty_like(x)
+    dwb = torch.empty(2 * c + 2, dtype=torch.float32, device=x.device)
+    ws = _workspace(int(lib().hg_nn_head_workspace_size(c)), x.device, None)
+    _check(lib().hg_nn_head_backward(_ptr(dout), _ptr(w), _ptr(x), _ptr(dx), _ptr(dwb), pixels, c, _ptr(ws),
+                                     ws.numel(), _stream(x.device, stream)))
+    return dx, dwb
+
+
+def hg_nn_phase_loss(out, label, amp, stream=None):
+    """(dout, per-image loss) of the phase loss for head output out [B, ..., 2]."""
+    torch = _torch()
+    _need(out, torch.float32, "out")
+    _need(label, torch.complex64, "label")
+    _need(amp, torch.float32, "amp")
+    b = amp.shape[0]
+    hw = amp.numel() // b
+    dout = torch.empty_like(out)
+    loss = torch.empty(b, dtype=torch.float32, device=out.device)
+    ws = _workspace(int(lib().hg_nn_loss_workspace_size(b)), out.device, None)
+    _check(lib().hg_nn_phase_loss(_ptr(out), _ptr(label), _ptr(amp), _ptr(dout), _ptr(loss), b, hw, _ptr(ws),
+                                  ws.numel(), _stream(out.device, stream)))
+    return dout, loss

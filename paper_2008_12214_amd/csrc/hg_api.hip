@@ -380,6 +380,12 @@ ClassPlan plan_classes(const hg_problem* probs, int count) {
 
 }  // namespace
 
+// Error text shared with the network translation unit (same thread-local
+// buffer that hg_last_error returns).
+namespace hg_internal {
+void set_error(const char* msg) { snprintf(g_err, sizeof(g_err), "%s", msg); }
+}  // namespace hg_internal
+
 extern "C" {
 
 const char* hg_status_string(hg_status s) {
@@ -553,6 +559,8 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
     if (p.slm_levels >= 2 && !p.levels_out) return fail(HG_ERR_INVALID_ARG, "problem %d: levels_out required", i);
     if (!optics_ok(p.wavelength_m, p.pitch_m, p.z_m))
       return fail(HG_ERR_INVALID_ARG, "problem %d: Fresnel needs wavelength_m > 0 and pitch_m > 0", i);
+    if (p.init_levels && p.slm_levels < 2)
+      return fail(HG_ERR_INVALID_ARG, "problem %d: init_levels needs slm_levels >= 2", i);
   }
   const size_t need = hg_gs_batched_workspace_size(probs, count);
   hg_status s = check_ws(workspace, workspace_bytes, need);
@@ -571,6 +579,8 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
       d.target = p.target;
       d.levels_out = p.levels_out;
       d.nmse_out = p.nmse_out;
+      d.init_levels = p.init_levels;
+      d.replay_out = reinterpret_cast<float2*>(p.replay_out);
       d.seed = p.seed;
       d.item = (uint32_t)i;
       d.L = p.slm_levels;

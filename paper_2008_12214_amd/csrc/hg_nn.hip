@@ -1,0 +1,1063 @@
+// Learned initialisation network on gfx950: BF16 MFMA convolutions (forward,
+// backward-data, backward-weight) accumulating in FP32, the small layers
+// around them, and the whole-network forward / backward / Adam sequence.
+// Activations are NHWC bfloat16; parameters, their gradients and the
+// optimiser state are FP32.
+//
+// A 3x3 convolution is an implicit GEMM: Y[p][co] = sum_k A[p][k] B[k][co],
+// k = (ky * 3 + kx) * Cin + ci, A gathered from the input on the fly, B the
+// packed weights [co][k] (k padded with zeros to a multiple of 32).  One wave
+// computes 16 pixels x 16 NB output channels with v_mfma_f32_16x16x32_bf16:
+//   A operand: lane l holds row (l & 15), k = 8 (l >> 4) .. + 7
+//   B operand: lane l holds column (l & 15), k = 8 (l >> 4) .. + 7
+//   result:    lane l holds column (l & 15), rows 4 (l >> 4) .. + 3
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include <algorithm>
+
+#include "hg_device.hpp"
+#include "hologen_nn.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16;
+
+__host__ __device__ inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+__device__ __forceinline__ u16 f2bf(float f) {  // round to nearest, ties to even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (u16)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 load8(const u16* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution, zero padding 1.  X [P][Cin] (P = N H W pixels, NHWC),
+// Wg [Cout][Kpad] bf16, Y [P][Cout].  Epilogue: + bias (nullable), ReLU
+// (relu != 0), times (mask > 0) where mask (nullable) has Y's layout, then
+// bf16.  grid.x = ceil(P / 64) (4 waves x 16 pixels), grid.y = Cout / (16 NB).
+// ---------------------------------------------------------------------------
+template <int NB, bool VEC>
+__global__ __launch_bounds__(256) void k_conv3x3(const u16* __restrict__ X, const u16* __restrict__ Wg,
+                                                 const float* __restrict__ bias, const u16* __restrict__ mask,
+                                                 u16* __restrict__ Y, long P, int H, int W, int Cin, int Cout,
+                                                 int Kpad, int relu) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long pbase = ((long)blockIdx.x * 4 + wave) * 16;
+  if (pbase >= P) return;  // whole wave
+  const int m = lane & 15, kb = lane >> 4;
+  const long pa = pbase + m;
+  const bool pvalid = pa < P;
+  const long HW = (long)H * W;
+  int y = 0, x = 0;
+  const u16* xn = X;
+  if (pvalid) {
+    const long n = pa / HW;
+    const int r = (int)(pa - n * HW);
+    y = r / W;
+    x = r - y * W;
+    xn = X + (size_t)n * HW * Cin;
+  }
+  const int co0 = blockIdx.y * 16 * NB;
+  const int K = 9 * Cin;
+  f32x4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int kc = 0; kc < Kpad; kc += 32) {
+    const int k = kc + kb * 8;
+    bf16x8 a = zero8();
+    if constexpr (VEC) {  // Cin % 8 == 0: the 8 k values are 8 channels of one tap
+      if (pvalid && k < K) {
+        const int tap = k / Cin, ci = k - tap * Cin;
+        const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W) a = load8(xn + ((size_t)yy * W + xx) * Cin + ci);
+      }
+    } else {
+      u16 tmp[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int kk = k + e;
+        u16 v = 0;
+        if (pvalid && kk < K) {
+          const int tap = kk / Cin, ci = kk - tap * Cin;
+          const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+          if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = xn[((size_t)yy * W + xx) * Cin + ci];
+        }
+        tmp[e] = v;
+      }
+      a = __builtin_bit_cast(bf16x8, tmp);
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const bf16x8 b = load8(Wg + (size_t)(co0 + nb * 16 + m) * Kpad + k);
+      acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int co = co0 + nb * 16 + m;
+    const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const long p = pbase + 4 * kb + i;
+      if (p < P) {
+        const size_t o = (size_t)p * Cout + co;
+        float v = acc[nb][i] + bv;
+        if (relu) v = fmaxf(v, 0.f);
+        if (mask && !(bf2f(mask[o]) > 0.f)) v = 0.f;
+        Y[o] = f2bf(v);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: part[pb][co][k] = sum over pixel block pb of
+// dY[p][co] A[p][k] (A = implicit im2col of X), i.e. dY^T A with pixels as
+// the MFMA reduction dimension:
+//   A operand (16 co x 32 px): lane l -> co (l & 15), pixels 8 (l >> 4) .. + 7
+//   B operand (32 px x 16 k):  lane l -> k  (l & 15), pixels 8 (l >> 4) .. + 7
+// grid.x = pixel blocks of pb_len pixels (a multiple of 32), grid.y = Cout/16,
+// grid.z = ceil(Kpad / 64) (4 waves x 16 k).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_conv3x3_wgrad(const u16* __restrict__ X, const u16* __restrict__ dY,
+                                                       float* __restrict__ part, long P, int H, int W, int Cin,
+                                                       int Cout, int Kpad, long pb_len) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kb = lane >> 4;
+  const int co = blockIdx.y * 16 + (lane & 15);
+  const int kcol = (blockIdx.z * 4 + wave) * 16 + (lane & 15);
+  const long HW = (long)H * W;
+  const int K = 9 * Cin;
+  const bool kvalid = kcol < K;
+  int ci = 0, dyy = 0, dxx = 0;
+  if (kvalid) {
+    const int tap = kcol / Cin;
+    ci = kcol - tap * Cin;
+    dyy = tap / 3 - 1;
+    dxx = tap % 3 - 1;
+  }
+  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  const long p_begin = (long)blockIdx.x * pb_len;
+  const long p_end = std::min(p_begin + pb_len, P);
+  for (long pc = p_begin; pc < p_end; pc += 32) {
+    u16 av[8], bv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const long p = pc + kb * 8 + e;
+      u16 ga = 0, gb = 0;
+      if (p < p_end) {
+        ga = dY[(size_t)p * Cout + co];
+        if (kvalid) {
+          const long n = p / HW;
+          const int r = (int)(p - n * HW);
+          const int yy = r / W + dyy, xx = r % W + dxx;
+          if (yy >= 0 && yy < H && xx >= 0 && xx < W) gb = X[(((size_t)n * H + yy) * W + xx) * Cin + ci];
+        }
+      }
+      av[e] = ga;
+      bv[e] = gb;
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
+                                                  acc, 0, 0, 0);
+  }
+  if (kcol < Kpad) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int cor = blockIdx.y * 16 + 4 * kb + i;
+      part[((size_t)blockIdx.x * Cout + cor) * Kpad + kcol] = acc[i];
+    }
+  }
+}
+
+// dw[co][k] (OHWI) = sum over the pixel blocks of part, in block order.
+__global__ void k_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dw, int npb, int Cout, int Kpad,
+                               int K) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Cout * K) return;
+  const int co = i / K, k = i - co * K;
+  float s = 0.f;
+  for (int b = 0; b < npb; ++b) s += part[((size_t)b * Cout + co) * Kpad + k];
+  dw[i] = s;
+}
+
+// Column sums of a [P][C] bf16 array, C <= 256: part[blk][c] is the sum over
+// block blk's pixel range (threads of one channel add in a fixed order).
+__global__ __launch_bounds__(256) void k_colsum_part(const u16* __restrict__ dY, float* __restrict__ part, long P,
+                                                     int C, long chunk) {
+  __shared__ float red[256];
+  const int c = threadIdx.x % C, sub = threadIdx.x / C, nsub = 256 / C;
+  const long p0 = (long)blockIdx.x * chunk;
+  const long p1 = std::min(p0 + chunk, P);
+  float s = 0.f;
+  if (sub < nsub)
+    for (long p = p0 + sub; p < p1; p += nsub) s += bf2f(dY[(size_t)p * C + c]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < C) {
+    float t = 0.f;
+    for (int j = 0; j < nsub; ++j) t += red[j * C + threadIdx.x];
+    part[(size_t)blockIdx.x * C + threadIdx.x] = t;
+  }
+}
+
+// out[j] = sum_b part[b][j], b in order
+__global__ void k_sum_parts(const float* __restrict__ part, float* __restrict__ out, int nparts, int ncol) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncol) return;
+  float s = 0.f;
+  for (int b = 0; b < nparts; ++b) s += part[(size_t)b * ncol + j];
+  out[j] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Weight packing.  Forward: wg[co][k] = w[co][ky][kx][ci] (k = tap Cin + ci).
+// Backward-data (the adjoint is a 3x3 convolution of dY with the spatially
+// flipped, channel-transposed kernel): wg[ci][k'] = w[co][2-ky][2-kx][ci]
+// with k' = tap Cout + co.
+// ---------------------------------------------------------------------------
+__global__ void k_pack_weights(const float* __restrict__ w, u16* __restrict__ wg, int Cout, int Cin, int Kpad,
+                               int flip) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int rows = flip ? Cin : Cout, cols = flip ? 9 * Cout : 9 * Cin;
+  if (i >= rows * Kpad) return;
+  const int r = i / Kpad, k = i - r * Kpad;
+  float v = 0.f;
+  if (k < cols) {
+    if (!flip) {
+      v = w[(size_t)r * 9 * Cin + k];
+    } else {
+      const int tap = k / Cout, co = k - tap * Cout;
+      const int ky = 2 - tap / 3, kx = 2 - tap % 3;
+      v = w[(((size_t)co * 3 + ky) * 3 + kx) * Cin + r];
+    }
+  }
+  wg[i] = f2bf(v);
+}
+
+// network input: per-image sum of T^2 (block partials, FP64) ...
+__global__ __launch_bounds__(256) void k_sumsq_part(const float* __restrict__ t, double* __restrict__ part, long HW) {
+  __shared__ double red[256];
+  const long base = (long)blockIdx.y * HW;
+  double s = 0.0;
+  for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < HW; p += (long)gridDim.x * 256) {
+    const double v = t[base + p];
+    s += v * v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+// ... then x = bf16(T sqrt(HW / sum T^2))
+__global__ void k_input(const float* __restrict__ t, const double* __restrict__ part, int nparts, u16* __restrict__ x,
+                        long HW) {
+  const long base = (long)blockIdx.y * HW;
+  double s = 0.0;
+  for (int i = 0; i < nparts; ++i) s += part[(size_t)blockIdx.y * nparts + i];
+  const float scale = s > 0.0 ? (float)sqrt((double)HW / s) : 0.f;
+  for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += (long)gridDim.x * blockDim.x)
+    x[base + p] = f2bf(t[base + p] * scale);
+}
+
+// 2x2 average pool, NHWC bf16
+__global__ void k_avgpool2(const u16* __restrict__ x, u16* __restrict__ y, int N, int H, int W, int C) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int Ho = H / 2, Wo = W / 2;
+  if (i >= (long)N * Ho * Wo * C) return;
+  const int c = (int)(i % C);
+  long r = i / C;
+  const int xo = (int)(r % Wo);
+  r /= Wo;
+  const int yo = (int)(r % Ho);
+  const long n = r / Ho;
+  const size_t b = (((size_t)n * H + 2 * yo) * W + 2 * xo) * C + c;
+  const size_t rs = (size_t)W * C;
+  const float s = (bf2f(x[b]) + bf2f(x[b + C])) + (bf2f(x[b + rs]) + bf2f(x[b + rs + C]));
+  y[i] = f2bf(0.25f * s);
+}
+
+// dx = (0.25 dy[pooled pixel] + dskip) rounded to bf16, zeroed where
+// mask <= 0 (dskip and mask nullable)
+__global__ void k_avgpool2_bwd(const u16* __restrict__ dy, const u16* __restrict__ dskip, const u16* __restrict__ mask,
+                               u16* __restrict__ dx, int N, int H, int W, int C) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)N * H * W * C) return;
+  const int c = (int)(i % C);
+  long r = i / C;
+  const int x = (int)(r % W);
+  r /= W;
+  const int yv = (int)(r % H);
+  const long n = r / H;
+  float g = 0.25f * bf2f(dy[(((size_t)n * (H / 2) + yv / 2) * (W / 2) + x / 2) * C + c]);
+  if (dskip) g += bf2f(dskip[i]);
+  if (mask && !(bf2f(mask[i]) > 0.f)) g = 0.f;
+  dx[i] = f2bf(g);
+}
+
+// out[..., :C1] = nearest 2x upsampling of lo (C1 channels), out[..., C1:] = skip (C2)
+__global__ void k_upcat(const u16* __restrict__ lo, const u16* __restrict__ skip, u16* __restrict__ out, int N, int H,
+                        int W, int C1, int C2) {
+  const int C = C1 + C2;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)N * H * W * C) return;
+  const int c = (int)(i % C);
+  const long p = i / C;
+  if (c < C1) {
+    const int x = (int)(p % W);
+    const long r = p / W;
+    const int yv = (int)(r % H);
+    const long n = r / H;
+    out[i] = lo[(((size_t)n * (H / 2) + yv / 2) * (W / 2) + x / 2) * C1 + c];
+  } else {
+    out[i] = skip[(size_t)p * C2 + (c - C1)];
+  }
+}
+
+// backward of k_upcat: dlo = bf16(sum of the 4 copies) zeroed where
+// mask_lo <= 0 (nullable), dskip = the skip channels
+__global__ void k_upcat_bwd(const u16* __restrict__ dout, const u16* __restrict__ mask_lo, u16* __restrict__ dlo,
+                            u16* __restrict__ dskip, int N, int H, int W, int C1, int C2) {
+  const int C = C1 + C2;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nlo = (long)N * (H / 2) * (W / 2) * C1;
+  const long nsk = (long)N * H * W * C2;
+  if (i < nlo) {
+    const int c = (int)(i % C1);
+    long r = i / C1;
+    const int xo = (int)(r % (W / 2));
+    r /= (W / 2);
+    const int yo = (int)(r % (H / 2));
+    const long n = r / (H / 2);
+    const size_t b = (((size_t)n * H + 2 * yo) * W + 2 * xo) * C + c;
+    const size_t rs = (size_t)W * C;
+    float s = (bf2f(dout[b]) + bf2f(dout[b + C])) + (bf2f(dout[b + rs]) + bf2f(dout[b + rs + C]));
+    if (mask_lo && !(bf2f(mask_lo[i]) > 0.f)) s = 0.f;
+    dlo[i] = f2bf(s);
+  } else if (i < nlo + nsk) {
+    const long j = i - nlo;
+    dskip[j] = dout[(size_t)(j / C2) * C + C1 + (j % C2)];
+  }
+}
+
+// 1x1 head: out[p] = (sum_c x[p][c] w[0][c] + b[0], sum_c x[p][c] w[1][c] + b[1]),
+// weights rounded to bf16, FP32 output (interleaved pairs, a complex64 layout)
+__global__ void k_head(const u16* __restrict__ x, const float* __restrict__ w, const float* __restrict__ b,
+                       float* __restrict__ out, long P, int C) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  float a0 = 0.f, a1 = 0.f;
+  for (int c = 0; c < C; ++c) {
+    const float v = bf2f(x[(size_t)p * C + c]);
+    a0 += v * bf2f(f2bf(w[c]));
+    a1 += v * bf2f(f2bf(w[C + c]));
+  }
+  out[2 * p] = a0 + b[0];
+  out[2 * p + 1] = a1 + b[1];
+}
+
+// Phase loss of image blockIdx.y against the label phasor y = lab/|lab|
+// (lab = 0 counts as phase 0) weighted by amp.  Pass 1: block partials of
+// S = sum amp z conj(y) (re, im) and of sum amp, z = out/|out|.
+__global__ __launch_bounds__(256) void k_loss_part(const float* __restrict__ out, const float2* __restrict__ lab,
+                                                   const float* __restrict__ amp, double* __restrict__ part,
+                                                   long HW) {
+  __shared__ double red[3][256];
+  const long base = (long)blockIdx.y * HW;
+  double sr = 0, si = 0, sw = 0;
+  for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < HW; p += (long)gridDim.x * 256) {
+    const float a = out[2 * (base + p)], b = out[2 * (base + p) + 1];
+    const float r = sqrtf(a * a + b * b) + 1e-12f;
+    const float2 l = lab[base + p];
+    const float lm = sqrtf(l.x * l.x + l.y * l.y);
+    const float c = lm > 0.f ? l.x / lm : 1.f, s = lm > 0.f ? l.y / lm : 0.f;
+    const float am = amp[base + p];
+    sr += am * (a * c + b * s) / r;  // Re(z conj(y))
+    si += am * (b * c - a * s) / r;  // Im(z conj(y))
+    sw += am;
+  }
+  red[0][threadIdx.x] = sr;
+  red[1][threadIdx.x] = si;
+  red[2][threadIdx.x] = sw;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 3 + q] = red[q][0];
+}
+
+// Pass 2: l_n = 1 - |S_n| / W_n and d(mean_n l_n)/d out.  With s = S/|S| the
+// gradient of l_n is -Re(conj(s) amp conj(y) dz/d(a, b)) / W_n, where
+// dz/da = 1/r - a (a + ib)/r^3 and dz/db = i/r - b (a + ib)/r^3.
+__global__ __launch_bounds__(256) void k_loss_grad(const float* __restrict__ out, const float2* __restrict__ lab,
+                                                   const float* __restrict__ amp, const double* __restrict__ part,
+                                                   int nparts, float* __restrict__ dout, float* __restrict__ loss,
+                                                   long HW, int batch) {
+  const int n = blockIdx.y;
+  double S_re = 0, S_im = 0, Wt = 0;
+  for (int i = 0; i < nparts; ++i) {
+    S_re += part[((size_t)n * nparts + i) * 3 + 0];
+    S_im += part[((size_t)n * nparts + i) * 3 + 1];
+    Wt += part[((size_t)n * nparts + i) * 3 + 2];
+  }
+  const double Sabs = sqrt(S_re * S_re + S_im * S_im);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && loss) loss[n] = Wt > 0 ? (float)(1.0 - Sabs / Wt) : 0.f;
+  const float hr = Sabs > 0 ? (float)(S_re / Sabs) : 1.f, hi = Sabs > 0 ? (float)(S_im / Sabs) : 0.f;
+  const float scale = Wt > 0 ? (float)(1.0 / (Wt * batch)) : 0.f;
+  const long base = (long)n * HW;
+  for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < HW; p += (long)gridDim.x * 256) {
+    const float a = out[2 * (base + p)], b = out[2 * (base + p) + 1];
+    const float r = sqrtf(a * a + b * b) + 1e-12f;
+    const float2 l = lab[base + p];
+    const float lm = sqrtf(l.x * l.x + l.y * l.y);
+    const float c = lm > 0.f ? l.x / lm : 1.f, s = lm > 0.f ? l.y / lm : 0.f;
+    const float am = amp[base + p];
+    // coefficient of z: amp conj(s_hat) conj(y) = am (hr - i hi)(c - i s)
+    const float cr = am * (hr * c - hi * s), cim = -am * (hr * s + hi * c);
+    const float ir = 1.f / r, ir3 = ir * ir * ir;
+    const float da_r = ir - a * a * ir3, da_i = -a * b * ir3;
+    const float db_r = -b * a * ir3, db_i = ir - b * b * ir3;
+    dout[2 * (base + p)] = -(cr * da_r - cim * da_i) * scale;
+    dout[2 * (base + p) + 1] = -(cr * db_r - cim * db_i) * scale;
+  }
+}
+
+// head backward-data: dx[p][c] = bf16(sum_o dout[p][o] bf16(w[o][c])), zeroed
+// where x[p][c] <= 0 (x is the ReLU output feeding the head)
+__global__ void k_head_bwd_data(const float* __restrict__ dout, const float* __restrict__ w,
+                                const u16* __restrict__ x, u16* __restrict__ dx, long P, int C) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P * C) return;
+  const long p = i / C;
+  const int c = (int)(i - p * C);
+  float g = dout[2 * p] * bf2f(f2bf(w[c])) + dout[2 * p + 1] * bf2f(f2bf(w[C + c]));
+  if (!(bf2f(x[i]) > 0.f)) g = 0.f;
+  dx[i] = f2bf(g);
+}
+
+// head parameter-gradient partials over pixel chunks: columns o C + c
+// (weights), then 2 C + o (bias)
+__global__ void k_head_wgrad(const float* __restrict__ dout, const u16* __restrict__ x, float* __restrict__ part,
+                             long P, int C, long chunk) {
+  const int j = threadIdx.x;
+  const int ncol = 2 * C + 2;
+  if (j >= ncol) return;
+  const long p0 = (long)blockIdx.x * chunk;
+  const long p1 = std::min(p0 + chunk, P);
+  float s = 0.f;
+  if (j < 2 * C) {
+    const int o = j / C, c = j - o * C;
+    for (long p = p0; p < p1; ++p) s += dout[2 * p + o] * bf2f(x[(size_t)p * C + c]);
+  } else {
+    const int o = j - 2 * C;
+    for (long p = p0; p < p1; ++p) s += dout[2 * p + o];
+  }
+  part[(size_t)blockIdx.x * ncol + j] = s;
+}
+
+// Adam (Kingma and Ba): m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
+// p -= lr (m / c1) / (sqrt(v / c2) + eps), c1 = 1 - b1^t, c2 = 1 - b2^t
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       long n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// replay-plane start field: field = T y / |y| (y = 0 counts as phase 0);
+// y = NULL selects the quadratic phase 2 pi ((u - nx/2)^2 / nx + (v - ny/2)^2 / ny),
+// evaluated exactly through the integer residues of the squares.
+__global__ void k_replay_start(const float* __restrict__ t, const float2* __restrict__ y, float2* __restrict__ field,
+                               int ny, int nx, long total) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const float tv = t[i];
+  float c, s;
+  if (y) {
+    const float2 q = y[i];
+    const float mg = sqrtf(q.x * q.x + q.y * q.y);
+    c = mg > 0.f ? q.x / mg : 1.f;
+    s = mg > 0.f ? q.y / mg : 0.f;
+  } else {
+    const long pix = i % ((long)ny * nx);
+    const long u = pix % nx - nx / 2, v = pix / nx - ny / 2;
+    const double frac = (double)((u * u) % nx) / nx + (double)((v * v) % ny) / ny;
+    double sd, cd;
+    sincospi(2.0 * frac, &sd, &cd);
+    c = (float)cd;
+    s = (float)sd;
+  }
+  field[i] = make_float2(tv * c, tv * s);
+}
+
+__global__ void k_project_levels(const float2* __restrict__ g, uint8_t* __restrict__ levels, int L, long total) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  levels[i] = (uint8_t)hg::level_index(g[i], L);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+}  // namespace
+
+namespace hg_internal {
+void set_error(const char* msg);  // the buffer hg_last_error returns
+}
+
+namespace {
+
+hg_status nn_fail(hg_status s, const char* msg) {
+  hg_internal::set_error(msg);
+  return s;
+}
+void clear_error() { hg_internal::set_error(""); }
+hg_status nn_launch_status() {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "HIP launch failed: %s", hipGetErrorString(e));
+    hg_internal::set_error(buf);
+    return HG_ERR_HIP;
+  }
+  return HG_OK;
+}
+inline unsigned nblk(long n, int t) { return (unsigned)((n + t - 1) / t); }
+inline int kpad_of(int K) { return (K + 31) / 32 * 32; }
+
+// ---- layer launchers (arguments validated by the callers) ----
+void conv_launch(const u16* X, const u16* Wg, const float* bias, const u16* mask, u16* Y, long P, int H, int W,
+                 int Cin, int Cout, int relu, hipStream_t st) {
+  const int nb16 = Cout / 16;
+  const int NB = nb16 % 4 == 0 ? 4 : nb16 % 3 == 0 ? 3 : nb16 % 2 == 0 ? 2 : 1;
+  const dim3 grid(nblk(P, 64), nb16 / NB);
+  const bool vec = (Cin % 8) == 0;
+  const int Kp = kpad_of(9 * Cin);
+#define HG_CONV(NBV)                                                                                               \
+  if (vec)                                                                                                         \
+    hipLaunchKernelGGL((k_conv3x3<NBV, true>), grid, dim3(256), 0, st, X, Wg, bias, mask, Y, P, H, W, Cin, Cout,   \
+                       Kp, relu);                                                                                  \
+  else                                                                                                             \
+    hipLaunchKernelGGL((k_conv3x3<NBV, false>), grid, dim3(256), 0, st, X, Wg, bias, mask, Y, P, H, W, Cin, Cout, \
+                       Kp, relu);
+  switch (NB) {
+    case 4: HG_CONV(4) break;
+    case 3: HG_CONV(3) break;
+    case 2: HG_CONV(2) break;
+    default: HG_CONV(1) break;
+  }
+#undef HG_CONV
+}
+
+struct WgradPlan {
+  long pb_len;
+  int npb;
+};
+WgradPlan wgrad_plan(long P, int Cin, int Cout) {
+  const int Kp = kpad_of(9 * Cin);
+  const long tiles = (long)(Cout / 16) * ((Kp + 63) / 64);
+  const long want = std::max(1L, 2048 / tiles);  // about 2048 workgroups in all
+  long pb = (P + want - 1) / want;
+  pb = std::max(256L, (pb + 31) / 32 * 32);
+  return {pb, (int)((P + pb - 1) / pb)};
+}
+constexpr int kColsumParts = 64;
+size_t wgrad_ws_bytes(long P, int Cin, int Cout) {
+  const WgradPlan w = wgrad_plan(P, Cin, Cout);
+  return al256((size_t)w.npb * Cout * kpad_of(9 * Cin) * sizeof(float)) +
+         al256((size_t)kColsumParts * Cout * sizeof(float));
+}
+void wgrad_launch(const u16* X, const u16* dY, float* dw, float* db, long P, int H, int W, int Cin, int Cout,
+                  char* ws, hipStream_t st) {
+  const WgradPlan wp = wgrad_plan(P, Cin, Cout);
+  const int Kp = kpad_of(9 * Cin);
+  float* part = reinterpret_cast<float*>(ws);
+  hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(wp.npb, Cout / 16, (Kp + 63) / 64), dim3(256), 0, st, X, dY, part, P, H, W,
+                     Cin, Cout, Kp, wp.pb_len);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk((long)Cout * 9 * Cin, 256)), dim3(256), 0, st, part, dw, wp.npb, Cout,
+                     Kp, 9 * Cin);
+  if (db) {
+    float* bpart = reinterpret_cast<float*>(ws + al256((size_t)wp.npb * Cout * Kp * sizeof(float)));
+    const long chunk = (P + kColsumParts - 1) / kColsumParts;
+    hipLaunchKernelGGL(k_colsum_part, dim3(kColsumParts), dim3(256), 0, st, dY, bpart, P, Cout, chunk);
+    hipLaunchKernelGGL(k_sum_parts, dim3(nblk(Cout, 256)), dim3(256), 0, st, bpart, db, kColsumParts, Cout);
+  }
+}
+
+constexpr int kLossParts = 64;
+constexpr int kHeadParts = 256;
+
+// ---- the fixed network: encoder 16/32/64/128, decoder back to 16, head 2 ----
+constexpr int kLevels = 4;
+constexpr int kEnc[kLevels] = {16, 32, 64, 128};
+enum { E0A, E0B, E1A, E1B, E2A, E2B, E3A, E3B, D2A, D2B, D1A, D1B, D0A, D0B, HEAD, NLAYER };
+
+struct Layer {
+  int cin, cout, level;
+  size_t w, b;  // float offsets into the parameter vector
+};
+
+struct Net {
+  Layer L[NLAYER];
+  size_t nparams;
+  Net() {
+    int k = 0;
+    int cin = 1;
+    for (int l = 0; l < kLevels; ++l) {
+      L[k++] = {cin, kEnc[l], l, 0, 0};
+      L[k++] = {kEnc[l], kEnc[l], l, 0, 0};
+      cin = kEnc[l];
+    }
+    for (int l = kLevels - 2; l >= 0; --l) {
+      L[k++] = {cin + kEnc[l], kEnc[l], l, 0, 0};
+      L[k++] = {kEnc[l], kEnc[l], l, 0, 0};
+      cin = kEnc[l];
+    }
+    L[k++] = {cin, 2, 0, 0, 0};
+    size_t off = 0;
+    for (int i = 0; i < NLAYER; ++i) {
+      L[i].w = off;
+      off += (size_t)L[i].cout * (i == HEAD ? 1 : 9) * L[i].cin;
+      L[i].b = off;
+      off += L[i].cout;
+    }
+    nparams = off;
+  }
+};
+const Net& net() {
+  static const Net n;
+  return n;
+}
+// decoder layer pair at level l: D{l}A, D{l}B
+inline int dec_a(int l) { return D2A + 2 * (kLevels - 2 - l); }
+
+// Workspace plan for a batch of B images of H x W (byte offsets).
+struct Plan {
+  long P[kLevels];  // pixels per level
+  size_t wg_f[NLAYER], wg_b[NLAYER];
+  size_t x;                       // input, bf16 [P0]
+  size_t act[NLAYER];             // conv layer outputs
+  size_t pool[kLevels - 1];       // pooled e{l}b outputs (input of e{l+1}a)
+  size_t cat[kLevels - 1];        // decoder concatenations at level l
+  size_t gbuf[3];                 // rotating gradient buffers
+  size_t skipg[kLevels - 1];      // skip-connection gradients
+  size_t dout;                    // fp32 [P0][2]
+  size_t scratch;                 // wgrad partials / reductions
+  size_t total;
+};
+
+Plan make_plan(int B, int H, int W) {
+  const Net& n = net();
+  Plan p{};
+  for (int l = 0; l < kLevels; ++l) p.P[l] = (long)B * (H >> l) * (W >> l);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += al256(bytes);
+    return o;
+  };
+  for (int i = 0; i < HEAD; ++i) {
+    p.wg_f[i] = take((size_t)n.L[i].cout * kpad_of(9 * n.L[i].cin) * 2);
+    p.wg_b[i] = i == E0A ? 0 : take((size_t)n.L[i].cin * kpad_of(9 * n.L[i].cout) * 2);
+  }
+  p.x = take((size_t)p.P[0] * 2);
+  for (int i = 0; i < HEAD; ++i) p.act[i] = take((size_t)p.P[n.L[i].level] * n.L[i].cout * 2);
+  for (int l = 0; l < kLevels - 1; ++l) p.pool[l] = take((size_t)p.P[l + 1] * kEnc[l] * 2);
+  for (int l = 0; l < kLevels - 1; ++l) p.cat[l] = take((size_t)p.P[l] * (kEnc[l + 1] + kEnc[l]) * 2);
+  size_t gb = 0;
+  for (int l = 0; l < kLevels; ++l) {
+    const int cmax = l < kLevels - 1 ? kEnc[l + 1] + kEnc[l] : kEnc[l];
+    gb = std::max(gb, (size_t)p.P[l] * cmax * 2);
+  }
+  for (int j = 0; j < 3; ++j) p.gbuf[j] = take(gb);
+  for (int l = 0; l < kLevels - 1; ++l) p.skipg[l] = take((size_t)p.P[l] * kEnc[l] * 2);
+  p.dout = take((size_t)p.P[0] * 2 * sizeof(float));
+  size_t sc = al256((size_t)B * 64 * sizeof(double));                    // input scaling
+  sc = std::max(sc, al256((size_t)B * kLossParts * 3 * sizeof(double)));  // loss
+  sc = std::max(sc, al256((size_t)kHeadParts * (2 * kEnc[0] + 2) * sizeof(float)));
+  for (int i = 0; i < HEAD; ++i) sc = std::max(sc, wgrad_ws_bytes(p.P[n.L[i].level], n.L[i].cin, n.L[i].cout));
+  p.scratch = take(sc);
+  p.total = off;
+  return p;
+}
+
+hg_status check_net_shape(int B, int H, int W) {
+  if (B < 1 || H < 8 || W < 8 || (H % 8) || (W % 8))
+    return nn_fail(HG_ERR_UNSUPPORTED_SIZE, "network needs batch >= 1 and height, width multiples of 8");
+  if ((long)B * H * W * 48 > (1L << 31)) return nn_fail(HG_ERR_UNSUPPORTED_SIZE, "network batch too large");
+  return HG_OK;
+}
+hg_status check_ws(const void* ws, size_t have, size_t need) {
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return nn_fail(HG_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  if (have < need) return nn_fail(HG_ERR_WORKSPACE, "workspace smaller than the query");
+  return HG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+/* ---------------- layer-level entry points ---------------- */
+
+int hg_nn_kpad(int k) { return k < 1 ? 0 : kpad_of(k); }
+
+hg_status hg_nn_pack_weights(const float* w, void* wg, int cout, int cin, int flip, void* stream) {
+  clear_error();
+  if (!w || !wg || cout < 1 || cin < 1)
+    return nn_fail(HG_ERR_INVALID_ARG, "pack_weights: NULL buffer or channels < 1");
+  const int Kp = flip ? kpad_of(9 * cout) : kpad_of(9 * cin);
+  const long n = (long)(flip ? cin : cout) * Kp;
+  hipLaunchKernelGGL(k_pack_weights, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, w, (u16*)wg, cout, cin,
+                     Kp, flip);
+  return nn_launch_status();
+}
+
+hg_status hg_nn_conv3x3(const void* x, const void* wg, const float* bias, const void* mask, void* y, int n, int h,
+                        int w, int cin, int cout, int relu, void* stream) {
+  clear_error();
+  if (!x || !wg || !y) return nn_fail(HG_ERR_INVALID_ARG, "conv3x3: NULL buffer");
+  if (n < 1 || h < 1 || w < 1 || cin < 1 || cout < 16 || (cout % 16))
+    return nn_fail(HG_ERR_INVALID_ARG, "conv3x3: needs n, h, w, cin >= 1 and cout a multiple of 16");
+  if ((long)n * h * w * std::max(cin, cout) > (1L << 31))
+    return nn_fail(HG_ERR_UNSUPPORTED_SIZE, "conv3x3: tensor too large");
+  conv_launch((const u16*)x, (const u16*)wg, bias, (const u16*)mask, (u16*)y, (long)n * h * w, h, w, cin, cout, relu,
+              (hipStream_t)stream);
+  return nn_launch_status();
+}
+
+size_t hg_nn_wgrad_workspace_size(int n, int h, int w, int cin, int cout) {
+  if (n < 1 || h < 1 || w < 1 || cin < 1 || cout < 16 || (cout % 16) || cout > 256) return 0;
+  return wgrad_ws_bytes((long)n * h * w, cin, cout);
+}
+
+hg_status hg_nn_conv3x3_wgrad(const void* x, const void* dy, float* dw, float* db, int n, int h, int w, int cin,
+                              int cout, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!x || !dy || !dw) return nn_fail(HG_ERR_INVALID_ARG, "wgrad: NULL buffer");
+  if (n < 1 || h < 1 || w < 1 || cin < 1 || cout < 16 || (cout % 16) || cout > 256)
+    return nn_fail(HG_ERR_INVALID_ARG, "wgrad: needs cout a multiple of 16 up to 256");
+  if ((long)n * h * w * std::max(cin, cout) > (1L << 31))
+    return nn_fail(HG_ERR_UNSUPPORTED_SIZE, "wgrad: tensor too large");
+  hg_status s = check_ws(ws, ws_bytes, hg_nn_wgrad_workspace_size(n, h, w, cin, cout));
+  if (s != HG_OK) return s;
+  wgrad_launch((const u16*)x, (const u16*)dy, dw, db, (long)n * h * w, h, w, cin, cout, (char*)ws,
+               (hipStream_t)stream);
+  return nn_launch_status();
+}
+
+hg_status hg_nn_avgpool2(const void* x, void* y, int n, int h, int w, int c, void* stream) {
+  clear_error();
+  if (!x || !y || n < 1 || h < 2 || w < 2 || ((h | w) & 1) || c < 1)
+    return nn_fail(HG_ERR_INVALID_ARG, "avgpool2: NULL buffer or odd/small size");
+  const long cnt = (long)n * (h / 2) * (w / 2) * c;
+  hipLaunchKernelGGL(k_avgpool2, dim3(nblk(cnt, 256)), dim3(256), 0, (hipStream_t)stream, (const u16*)x, (u16*)y, n,
+                     h, w, c);
+  return nn_launch_status();
+}
+
+hg_status hg_nn_avgpool2_backward(const void* dy, const void* dskip, const void* mask, void* dx, int n, int h, int w,
+                                  int c, void* stream) {
+  clear_error();
+  if (!dy || !dx || n < 1 || h < 2 || w < 2 || ((h | w) & 1) || c < 1)
+    return nn_fail(HG_ERR_INVALID_ARG, "avgpool2_backward: NULL buffer or odd/small size");
+  const long cnt = (long)n * h * w * c;
+  hipLaunchKernelGGL(k_avgpool2_bwd, dim3(nblk(cnt, 256)), dim3(256), 0, (hipStream_t)stream, (const u16*)dy,
+                     (const u16*)dskip, (const u16*)mask, (u16*)dx, n, h, w, c);
+  return nn_launch_status();
+}
+
+hg_status hg_nn_upsample_concat(const void* lo, const void* skip, void* out, int n, int h, int w, int c1, int c2,
+                                void* stream) {
+  clear_error();
+  if (!lo || !skip || !out || n < 1 || h < 2 || w < 2 || ((h | w) & 1) || c1 < 1 || c2 < 1)
+    return nn_fail(HG_ERR_INVALID_ARG, "upsample_concat: NULL buffer or bad size");
+  const long cnt = (long)n * h * w * (c1 + c2);
+  hipLaunchKernelGGL(k_upcat, dim3(nblk(cnt, 256)), dim3(256), 0, (hipStream_t)stream, (const u16*)lo,
+                     (const u16*)skip, (u16*)out, n, h, w, c1, c2);
+  return nn_launch_status();
+}
+
+hg_status hg_nn_upsample_concat_backward(const void* dout, const void* mask_lo, void* dlo, void* dskip, int n, int h,
+                                         int w, int c1, int c2, void* stream) {
+  clear_error();
+  if (!dout || !dlo || !dskip || n < 1 || h < 2 || w < 2 || ((h | w) & 1) || c1 < 1 || c2 < 1)
+    return nn_fail(HG_ERR_INVALID_ARG, "upsample_concat_backward: NULL buffer or bad size");
+  const long cnt = (long)n * (h / 2) * (w / 2) * c1 + (long)n * h * w * c2;
+  hipLaunchKernelGGL(k_upcat_bwd, dim3(nblk(cnt, 256)), dim3(256), 0, (hipStream_t)stream, (const u16*)dout,
+                     (const u16*)mask_lo, (u16*)dlo, (u16*)dskip, n, h, w, c1, c2);
+  return nn_launch_status();
+}
+
+hg_status hg_nn_head(const void* x, const float* w, const float* b, float* out, long pixels, int c, void* stream) {
+  clear_error();
+  if (!x || !w || !b || !out || pixels < 1 || c < 1) return nn_fail(HG_ERR_INVALID_ARG, "head: NULL buffer or size");
+  hipLaunchKernelGGL(k_head, dim3(nblk(pixels, 256)), dim3(256), 0, (hipStream_t)stream, (const u16*)x, w, b, out,
+                     pixels, c);
+  return nn_launch_status();
+}
+
+size_t hg_nn_loss_workspace_size(int batch) {
+  return batch < 1 ? 0 : al256((size_t)batch * kLossParts * 3 * sizeof(double));
+}
+
+hg_status hg_nn_phase_loss(const float* out, const hg_complex* label, const float* amp, float* dout, float* loss,
+                           int batch, long hw, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!out || !label || !amp || !dout || batch < 1 || hw < 1)
+    return nn_fail(HG_ERR_INVALID_ARG, "phase_loss: NULL buffer or size");
+  hg_status s = check_ws(ws, ws_bytes, hg_nn_loss_workspace_size(batch));
+  if (s != HG_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const float2* lab = reinterpret_cast<const float2*>(label);
+  hipLaunchKernelGGL(k_loss_part, dim3(kLossParts, batch), dim3(256), 0, st, out, lab, amp, (double*)ws, hw);
+  hipLaunchKernelGGL(k_loss_grad, dim3(kLossParts, batch), dim3(256), 0, st, out, lab, amp, (const double*)ws,
+                     kLossParts, dout, loss, hw, batch);
+  return nn_launch_status();
+}
+
+size_t hg_nn_head_workspace_size(int c) {
+  return c < 1 || 2 * c + 2 > 256 ? 0 : al256((size_t)kHeadParts * (2 * c + 2) * sizeof(float));
+}
+
+hg_status hg_nn_head_backward(const float* dout, const float* w, const void* x, void* dx, float* dwb, long pixels,
+                              int c, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!dout || !w || !x || !dx || !dwb || pixels < 1 || c < 1 || 2 * c + 2 > 256)
+    return nn_fail(HG_ERR_INVALID_ARG, "head_backward: NULL buffer or channels outside 1..127");
+  hg_status s = check_ws(ws, ws_bytes, hg_nn_head_workspace_size(c));
+  if (s != HG_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  float* part = (float*)ws;
+  const long chunk = (pixels + kHeadParts - 1) / kHeadParts;
+  hipLaunchKernelGGL(k_head_bwd_data, dim3(nblk(pixels * c, 256)), dim3(256), 0, st, dout, w, (const u16*)x, (u16*)dx,
+                     pixels, c);
+  hipLaunchKernelGGL(k_head_wgrad, dim3(kHeadParts), dim3(256), 0, st, dout, (const u16*)x, part, pixels, c, chunk);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, part, dwb, kHeadParts, 2 * c + 2);
+  return nn_launch_status();
+}
+
+hg_status hg_nn_adam(float* params, const float* grads, float* m, float* v, long count, float lr, float beta1,
+                     float beta2, float eps, int step, void* stream) {
+  clear_error();
+  if (!params || !grads || !m || !v || count < 1 || step < 1)
+    return nn_fail(HG_ERR_INVALID_ARG, "adam: NULL buffer, count < 1 or step < 1");
+  const float c1 = (float)(1.0 - pow((double)beta1, step)), c2 = (float)(1.0 - pow((double)beta2, step));
+  hipLaunchKernelGGL(k_adam, dim3(nblk(count, 256)), dim3(256), 0, (hipStream_t)stream, params, grads, m, v, count,
+                     lr, beta1, beta2, eps, c1, c2);
+  return nn_launch_status();
+}
+
+/* ---------------- whole network ---------------- */
+
+long hg_nn_param_count(void) { return (long)net().nparams; }
+
+size_t hg_nn_workspace_size(int batch, int h, int w) {
+  if (check_net_shape(batch, h, w) != HG_OK) return 0;
+  return make_plan(batch, h, w).total;
+}
+
+hg_status hg_nn_forward(const float* params, const float* target, int batch, int h, int w, float* out, void* ws,
+                        size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!params || !target || !out) return nn_fail(HG_ERR_INVALID_ARG, "forward: NULL buffer");
+  hg_status s = check_net_shape(batch, h, w);
+  if (s != HG_OK) return s;
+  const Plan p = make_plan(batch, h, w);
+  s = check_ws(ws, ws_bytes, p.total);
+  if (s != HG_OK) return s;
+  const Net& n = net();
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)ws;
+  auto A = [&](size_t off) { return reinterpret_cast<u16*>(base + off); };
+  for (int i = 0; i < HEAD; ++i) {
+    const int Kp = kpad_of(9 * n.L[i].cin);
+    const long cnt = (long)n.L[i].cout * Kp;
+    hipLaunchKernelGGL(k_pack_weights, dim3(nblk(cnt, 256)), dim3(256), 0, st, params + n.L[i].w, A(p.wg_f[i]),
+                       n.L[i].cout, n.L[i].cin, Kp, 0);
+  }
+  const long HW = (long)h * w;
+  double* npart = reinterpret_cast<double*>(base + p.scratch);
+  hipLaunchKernelGGL(k_sumsq_part, dim3(64, batch), dim3(256), 0, st, target, npart, HW);
+  hipLaunchKernelGGL(k_input, dim3(64, batch), dim3(256), 0, st, target, (const double*)npart, 64, A(p.x), HW);
+  auto conv = [&](int i, const u16* in) {
+    const int l = n.L[i].level;
+    conv_launch(in, A(p.wg_f[i]), params + n.L[i].b, nullptr, A(p.act[i]), p.P[l], h >> l, w >> l, n.L[i].cin,
+                n.L[i].cout, 1, st);
+  };
+  const u16* cur = A(p.x);
+  for (int l = 0; l < kLevels; ++l) {
+    conv(2 * l, cur);
+    conv(2 * l + 1, A(p.act[2 * l]));
+    if (l < kLevels - 1) {
+      const long cnt = p.P[l + 1] * kEnc[l];
+      hipLaunchKernelGGL(k_avgpool2, dim3(nblk(cnt, 256)), dim3(256), 0, st, A(p.act[2 * l + 1]), A(p.pool[l]),
+                         batch, h >> l, w >> l, kEnc[l]);
+      cur = A(p.pool[l]);
+    } else {
+      cur = A(p.act[2 * l + 1]);
+    }
+  }
+  for (int l = kLevels - 2; l >= 0; --l) {
+    const int ia = dec_a(l);
+    const int c1 = kEnc[l + 1], c2 = kEnc[l];
+    const long cnt = p.P[l] * (c1 + c2);
+    hipLaunchKernelGGL(k_upcat, dim3(nblk(cnt, 256)), dim3(256), 0, st, cur, A(p.act[2 * l + 1]), A(p.cat[l]), batch,
+                       h >> l, w >> l, c1, c2);
+    conv(ia, A(p.cat[l]));
+    conv(ia + 1, A(p.act[ia]));
+    cur = A(p.act[ia + 1]);
+  }
+  hipLaunchKernelGGL(k_head, dim3(nblk(p.P[0], 256)), dim3(256), 0, st, cur, params + n.L[HEAD].w,
+                     params + n.L[HEAD].b, out, p.P[0], n.L[HEAD].cin);
+  return nn_launch_status();
+}
+
+hg_status hg_nn_backward(const float* params, const float* out, const hg_complex* label, const float* amp, int batch,
+                         int h, int w, float* grads, float* loss_out, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!params || !out || !label || !amp || !grads) return nn_fail(HG_ERR_INVALID_ARG, "backward: NULL buffer");
+  hg_status s = check_net_shape(batch, h, w);
+  if (s != HG_OK) return s;
+  const Plan p = make_plan(batch, h, w);
+  s = check_ws(ws, ws_bytes, p.total);
+  if (s != HG_OK) return s;
+  const Net& n = net();
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)ws;
+  auto A = [&](size_t off) { return reinterpret_cast<u16*>(base + off); };
+  char* scratch = base + p.scratch;
+  for (int i = E0B; i < HEAD; ++i) {
+    const int Kp = kpad_of(9 * n.L[i].cout);
+    const long cnt = (long)n.L[i].cin * Kp;
+    hipLaunchKernelGGL(k_pack_weights, dim3(nblk(cnt, 256)), dim3(256), 0, st, params + n.L[i].w, A(p.wg_b[i]),
+                       n.L[i].cout, n.L[i].cin, Kp, 1);
+  }
+  const long HW = (long)h * w;
+  float* dout = reinterpret_cast<float*>(base + p.dout);
+  const float2* lab = reinterpret_cast<const float2*>(label);
+  hipLaunchKernelGGL(k_loss_part, dim3(kLossParts, batch), dim3(256), 0, st, out, lab, amp, (double*)scratch, HW);
+  hipLaunchKernelGGL(k_loss_grad, dim3(kLossParts, batch), dim3(256), 0, st, out, lab, amp, (const double*)scratch,
+                     kLossParts, dout, loss_out, HW, batch);
+  int gi = 0;  // next rotating gradient buffer
+  auto G = [&]() {
+    u16* b = A(p.gbuf[gi]);
+    gi = (gi + 1) % 3;
+    return b;
+  };
+  // head: the masked gradient of d0b's output, and the head's own gradients
+  // (its weights 2 c0 and bias 2 are adjacent in the parameter vector)
+  const int c0 = n.L[HEAD].cin;
+  u16* dh = G();
+  {
+    float* part = reinterpret_cast<float*>(scratch);
+    const long chunk = (p.P[0] + kHeadParts - 1) / kHeadParts;
+    hipLaunchKernelGGL(k_head_bwd_data, dim3(nblk(p.P[0] * c0, 256)), dim3(256), 0, st, dout, params + n.L[HEAD].w,
+                       A(p.act[D0B]), dh, p.P[0], c0);
+    hipLaunchKernelGGL(k_head_wgrad, dim3(kHeadParts), dim3(256), 0, st, dout, A(p.act[D0B]), part, p.P[0], c0, chunk);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, part, grads + n.L[HEAD].w, kHeadParts, 2 * c0 + 2);
+  }
+  // one conv layer: dz (already masked) -> weight and bias gradients, and the
+  // data gradient into dst, masked with `mask` (nullable); dst NULL skips it
+  auto conv_bwd = [&](int i, const u16* in, const u16* dz, const u16* mask, u16* dst) {
+    const int l = n.L[i].level;
+    wgrad_launch(in, dz, grads + n.L[i].w, grads + n.L[i].b, p.P[l], h >> l, w >> l, n.L[i].cin, n.L[i].cout,
+                 scratch, st);
+    if (dst)
+      conv_launch(dz, A(p.wg_b[i]), nullptr, mask, dst, p.P[l], h >> l, w >> l, n.L[i].cout, n.L[i].cin, 0, st);
+  };
+  // decoder, level 0 up to level kLevels - 2
+  for (int l = 0; l < kLevels - 1; ++l) {
+    const int ia = dec_a(l), ib = ia + 1;
+    u16* dza = G();
+    conv_bwd(ib, A(p.act[ia]), dh, A(p.act[ia]), dza);
+    u16* dcat = G();
+    conv_bwd(ia, A(p.cat[l]), dza, nullptr, dcat);
+    const int c1 = kEnc[l + 1], c2 = kEnc[l];
+    const u16* lower = l + 1 < kLevels - 1 ? A(p.act[dec_a(l + 1) + 1]) : A(p.act[E3B]);
+    u16* dlo = G();
+    const long cnt = p.P[l + 1] * c1 + p.P[l] * c2;
+    hipLaunchKernelGGL(k_upcat_bwd, dim3(nblk(cnt, 256)), dim3(256), 0, st, dcat, lower, dlo, A(p.skipg[l]), batch,
+                       h >> l, w >> l, c1, c2);
+    dh = dlo;
+  }
+  // encoder, deepest level first; dh is the masked gradient of e{l}b's output
+  // (at l < kLevels - 1 after adding the pooled path and the skip gradient)
+  for (int l = kLevels - 1; l >= 0; --l) {
+    if (l < kLevels - 1) {
+      u16* d = G();
+      const long cnt = p.P[l] * kEnc[l];
+      hipLaunchKernelGGL(k_avgpool2_bwd, dim3(nblk(cnt, 256)), dim3(256), 0, st, dh, A(p.skipg[l]),
+                         A(p.act[2 * l + 1]), d, batch, h >> l, w >> l, kEnc[l]);
+      dh = d;
+    }
+    u16* dza = G();
+    conv_bwd(2 * l + 1, A(p.act[2 * l]), dh, A(p.act[2 * l]), dza);
+    const u16* ain = l == 0 ? A(p.x) : A(p.pool[l - 1]);
+    u16* dpool = l == 0 ? nullptr : G();
+    conv_bwd(2 * l, ain, dza, nullptr, dpool);
+    dh = dpool;
+  }
+  return nn_launch_status();
+}
+
+/* ---------------- replay-plane phase -> SLM start levels ---------------- */
+
+size_t hg_replay_phase_init_workspace_size(int batch, int ny, int nx) {
+  if (batch < 1) return 0;
+  const size_t prop = hg_workspace_size(HG_OP_PROPAGATE, ny, nx, 1);
+  if (!prop) return 0;
+  return al256((size_t)batch * ny * nx * sizeof(float2)) + prop;
+}
+
+hg_status hg_replay_phase_init(const hg_complex* phasor, const float* target, int batch, int ny, int nx,
+                               int slm_levels, uint8_t* levels_out, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!target || !levels_out) return nn_fail(HG_ERR_INVALID_ARG, "replay_phase_init: NULL target or levels_out");
+  if (slm_levels < 2 || slm_levels > 256)
+    return nn_fail(HG_ERR_INVALID_ARG, "replay_phase_init: slm_levels must be in 2..256");
+  const size_t need = hg_replay_phase_init_workspace_size(batch, ny, nx);
+  if (!need) return nn_fail(HG_ERR_UNSUPPORTED_SIZE, "replay_phase_init: batch < 1 or unsupported grid");
+  hg_status s = check_ws(ws, ws_bytes, need);
+  if (s != HG_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const long px = (long)ny * nx, total = px * batch;
+  float2* field = reinterpret_cast<float2*>(ws);
+  const size_t fbytes = al256((size_t)total * sizeof(float2));
+  char* pws = (char*)ws + fbytes;
+  hipLaunchKernelGGL(k_replay_start, dim3(nblk(total, 256)), dim3(256), 0, st, target,
+                     reinterpret_cast<const float2*>(phasor), field, ny, nx, total);
+  s = nn_launch_status();
+  if (s != HG_OK) return s;
+  for (int b = 0; b < batch; ++b) {
+    hg_complex* f = reinterpret_cast<hg_complex*>(field + (size_t)b * px);
+    s = hg_fresnel_propagate(f, f, ny, nx, 0.0, 0.0, 0.0, -1, pws, ws_bytes - fbytes, stream);
+    if (s != HG_OK) return s;  // hg_last_error already holds the detail
+  }
+  hipLaunchKernelGGL(k_project_levels, dim3(nblk(total, 256)), dim3(256), 0, st, field, levels_out, slm_levels, total);
+  return nn_launch_status();
+}
+
+}  // extern "C"

@@ -14,9 +14,13 @@ FAKE = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
 
 
 def test_every_declared_symbol_is_exported():
-    hdr = open(os.path.join(ROOT, "include", "hologen.h")).read()
-    names = set(re.findall(r"\b(hg_[a-z_]+)\s*\(", hdr))
-    assert {"hg_gs", "hg_wgs", "hg_ospr", "hg_fresnel_propagate", "hg_gs_batched"} <= names
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            hdr = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"\b(hg_[a-z0-9_]+)\s*\(", hdr))
+    assert {"hg_gs", "hg_wgs", "hg_ospr", "hg_fresnel_propagate", "hg_gs_batched", "hg_nn_forward",
+            "hg_nn_backward", "hg_nn_adam", "hg_replay_phase_init", "hg_nn_conv3x3"} <= names
     for n in names:
         assert hasattr(L, n), n
 
@@ -85,3 +89,46 @@ def test_wgs_ospr_propagate_batched_validation():
     need = L.hg_gs_batched_workspace_size(probs, 2)
     assert need > L.hg_workspace_size(hg.HG_OP_WGS, 64, 64, 3)
     assert L.hg_gs_batched(probs, 2, 0, FAKE, need - 256, None) == hg.HG_ERR_WORKSPACE
+
+
+# ---------------------------------------------------------------------------
+# learned initialisation: shape checks and workspace queries (host only)
+# ---------------------------------------------------------------------------
+def test_nn_param_count_and_workspace_queries():
+    assert hg.hg_nn_param_count() == 487026
+    assert hg.hg_nn_workspace_size(1, 12, 16) == 0       # not a multiple of 8
+    assert hg.hg_nn_workspace_size(0, 64, 64) == 0
+    a = hg.hg_nn_workspace_size(1, 64, 64)
+    b = hg.hg_nn_workspace_size(4, 64, 64)
+    assert a > 64 * 64 * 400 and b - a > 3 * 64 * 64 * 400
+    assert L.hg_nn_wgrad_workspace_size(1, 8, 8, 16, 24) == 0  # cout not a multiple of 16
+    assert L.hg_nn_kpad(9) == 32 and L.hg_nn_kpad(144) == 160 and L.hg_nn_kpad(288) == 288
+    assert L.hg_replay_phase_init_workspace_size(2, 64, 128) >= 2 * 64 * 128 * 8
+    assert L.hg_replay_phase_init_workspace_size(1, 100, 128) == 0
+
+
+@pytest.mark.parametrize("args,status", [
+    (dict(h=12), hg.HG_ERR_UNSUPPORTED_SIZE),
+    (dict(batch=0), hg.HG_ERR_UNSUPPORTED_SIZE),
+    (dict(params=None), hg.HG_ERR_INVALID_ARG),
+    (dict(ws=None), hg.HG_ERR_WORKSPACE),
+    (dict(wsb=1024), hg.HG_ERR_WORKSPACE),
+])
+def test_nn_forward_validation(args, status):
+    a = dict(params=FAKE, target=FAKE, batch=1, h=64, w=64, out=FAKE, ws=FAKE, wsb=1 << 40)
+    a.update(args)
+    st = L.hg_nn_forward(a["params"], a["target"], a["batch"], a["h"], a["w"], a["out"], a["ws"], a["wsb"], None)
+    assert st == status, hg.hg_last_error()
+    assert hg.hg_last_error()
+
+
+def test_nn_layer_validation():
+    assert L.hg_nn_conv3x3(FAKE, FAKE, None, None, FAKE, 1, 8, 8, 16, 24, 0, None) == hg.HG_ERR_INVALID_ARG
+    assert L.hg_nn_conv3x3(None, FAKE, None, None, FAKE, 1, 8, 8, 16, 16, 0, None) == hg.HG_ERR_INVALID_ARG
+    assert L.hg_nn_avgpool2(FAKE, FAKE, 1, 7, 8, 4, None) == hg.HG_ERR_INVALID_ARG
+    assert L.hg_nn_adam(FAKE, FAKE, FAKE, FAKE, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == hg.HG_ERR_INVALID_ARG
+    assert L.hg_replay_phase_init(None, FAKE, 1, 64, 64, 1, FAKE, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG
+    assert L.hg_replay_phase_init(None, FAKE, 1, 64, 48, 8, FAKE, FAKE, 1 << 30, None) == \
+        hg.HG_ERR_UNSUPPORTED_SIZE
+    assert L.hg_nn_conv3x3_wgrad(FAKE, FAKE, FAKE, FAKE, 1, 8, 8, 16, 272, FAKE, 1 << 30, None) == \
+        hg.HG_ERR_INVALID_ARG  # more than 256 output channels
