@@ -83,19 +83,24 @@ hg_status hg_nn_adam(float* params, const float* grads, float* m, float* v, long
                      float beta2, float eps, int step, void* stream);
 
 /* SLM start levels from a replay-plane phase:
- * levels = P_L(IDFT(uncentre(T phasor / |phasor|))), per image.
- *   phasor      nullable [batch][ny][nx] complex, centred (only its phase is
- *               used, 0 = phase 0; hg_nn_forward's `out` qualifies); NULL
- *               selects the quadratic phase
- *               2 pi ((u - nx/2)^2 / nx + (v - ny/2)^2 / ny)
- *   target      [batch][ny][nx] FP32 amplitude (any positive scale)
- *   slm_levels  2..256; levels_out [batch][ny][nx] uint8
+ * levels = P_L(IDFT(uncentre(T e^{i psi}))), per image, with
+ * psi = arg(phasor) + (add_quadratic ? psi0 : 0) and the quadratic phase
+ * psi0 = 2 pi ((u - nx/2)^2 / nx + (v - ny/2)^2 / ny) in centred indices.
+ *   phasor        nullable [batch][ny][nx] complex, centred; only its phase
+ *                 is used (NULL or 0 = phase 0); hg_nn_forward's `out`
+ *                 qualifies
+ *   target        [batch][ny][nx] FP32 amplitude (any positive scale)
+ *   slm_levels    2..256; levels_out [batch][ny][nx] uint8
  * Grid sizes as in hologen.h (Fourier holograms).  The result is a valid
  * init_levels for hg_gs / hg_wgs / hg_problem. */
 size_t hg_replay_phase_init_workspace_size(int batch, int ny, int nx);
 hg_status hg_replay_phase_init(const hg_complex* phasor, const float* target, int batch, int ny, int nx,
-                               int slm_levels, uint8_t* levels_out, void* workspace, size_t workspace_bytes,
-                               void* stream);
+                               int slm_levels, int add_quadratic, uint8_t* levels_out, void* workspace,
+                               size_t workspace_bytes, void* stream);
+
+/* field [batch][ny][nx] (centred) *= e^{sign i psi0}, sign = +1 or -1: moves a
+ * replay-plane phase to or from its residual about the quadratic phase. */
+hg_status hg_quadratic_phase_apply(hg_complex* field, int batch, int ny, int nx, int sign, void* stream);
 
 /* ---- single layers (the steps of the two passes above) ---------------- */
 

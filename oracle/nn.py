@@ -251,14 +251,21 @@ def quadratic_phase(ny, nx):
     return 2.0 * np.pi * ((u[None, :] ** 2 % nx) / nx + (v[:, None] ** 2 % ny) / ny)
 
 
-def replay_phase_levels(T, phasor, L):
-    """SLM start levels from a replay-plane phase: P_L(IDFT(T e^{i arg phasor})).
+def replay_phase_levels(T, phasor, L, add_quadratic=False):
+    """SLM start levels from a replay-plane phase: P_L(IDFT(T e^{i psi})),
+    psi = arg(phasor) (+ quadratic_phase when add_quadratic).
 
-    phasor is a complex centred array (a zero entry counts as phase 0).
-    Returns (levels, g) with g the field before projection."""
-    y = np.asarray(phasor, np.complex128)
-    mag = np.abs(y)
-    unit = np.where(mag > 0, y / np.where(mag > 0, mag, 1.0), 1.0 + 0j)
-    g = _holo.backward(np.asarray(T, np.float64) * unit)
+    phasor is a complex centred array or None (a zero entry, or None, counts
+    as phase 0).  Returns (levels, g) with g the field before projection."""
+    T = np.asarray(T, np.float64)
+    if phasor is None:
+        unit = np.ones(T.shape, np.complex128)
+    else:
+        y = np.asarray(phasor, np.complex128)
+        mag = np.abs(y)
+        unit = np.where(mag > 0, y / np.where(mag > 0, mag, 1.0), 1.0 + 0j)
+    if add_quadratic:
+        unit = unit * np.exp(1j * quadratic_phase(*T.shape))
+    g = _holo.backward(T * unit)
     _, levels = _slm.project(g, L)
     return levels, g

@@ -326,7 +326,8 @@ def _declare_nn(L):
         "hg_nn_adam": (_i, [_vp, _vp, _vp, _vp, _l, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                             ctypes.c_float, _i, _vp]),
         "hg_replay_phase_init_workspace_size": (_sz, [_i, _i, _i]),
-        "hg_replay_phase_init": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _sz, _vp]),
+        "hg_replay_phase_init": (_i, [_vp, _vp, _i, _i, _i, _i, _i, _vp, _vp, _sz, _vp]),
+        "hg_quadratic_phase_apply": (_i, [_vp, _i, _i, _i, _i, _vp]),
         "hg_nn_kpad": (_i, [_i]),
         "hg_nn_pack_weights": (_i, [_vp, _vp, _i, _i, _i, _vp]),
         "hg_nn_conv3x3": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _vp]),
@@ -414,23 +415,37 @@ def hg_nn_adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1
                             int(step), _stream(params.device, stream)))
 
 
-def hg_replay_phase_init(target, slm_levels, phasor=None, stream=None):
-    """SLM start levels P_L(IDFT(T e^{i arg phasor})) for targets [B, ny, nx] (phasor None: quadratic)."""
+def hg_replay_phase_init(target, slm_levels, phasor=None, add_quadratic=None, stream=None):
+    """SLM start levels P_L(IDFT(T e^{i psi})) for targets [B, ny, nx].
+
+    psi = arg(phasor) (+ the quadratic phase when add_quadratic); phasor None
+    with add_quadratic left unset selects the quadratic phase alone."""
     torch = _torch()
     _need(target, torch.float32, "target", 3)
     b, ny, nx = target.shape
     dev = target.device
+    if add_quadratic is None:
+        add_quadratic = phasor is None
     if phasor is not None:
         if phasor.dtype == torch.float32 and phasor.dim() == 4 and phasor.shape[-1] == 2:
-            phasor = phasor.contiguous()
+            _need(phasor, torch.float32, "phasor", 4)
         else:
             _need(phasor, torch.complex64, "phasor", 3)
     levels = torch.empty((b, ny, nx), dtype=torch.uint8, device=dev)
     n = int(lib().hg_replay_phase_init_workspace_size(b, ny, nx))
     ws = _workspace(n, dev, None)
-    _check(lib().hg_replay_phase_init(_ptr(phasor), _ptr(target), b, ny, nx, slm_levels, _ptr(levels), _ptr(ws),
-                                      ws.numel(), _stream(dev, stream)))
+    _check(lib().hg_replay_phase_init(_ptr(phasor), _ptr(target), b, ny, nx, slm_levels, int(bool(add_quadratic)),
+                                      _ptr(levels), _ptr(ws), ws.numel(), _stream(dev, stream)))
     return levels
+
+
+def hg_quadratic_phase_apply(field, sign, stream=None):
+    """In place: field [B, ny, nx] complex64 (centred) *= exp(sign i psi0)."""
+    torch = _torch()
+    _need(field, torch.complex64, "field", 3)
+    b, ny, nx = field.shape
+    _check(lib().hg_quadratic_phase_apply(_ptr(field), b, ny, nx, int(sign), _stream(field.device, stream)))
+    return field
 
 
 def hg_nn_pack_weights(w, flip=False, stream=None):

@@ -131,8 +131,8 @@ __global__ __launch_bounds__(256) void k_conv3x3(const u16* __restrict__ X, cons
 // grid.z = ceil(Kpad / 64) (4 waves x 16 k).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const u16* __restrict__ X, const u16* __restrict__ dY,
-                                                       float* __restrict__ part, long P, int H, int W, int Cin,
-                                                       int Cout, int Kpad, long pb_len) {
+                                                       float* __restrict__ part, float* __restrict__ bpart, long P,
+                                                       int H, int W, int Cin, int Cout, int Kpad, long pb_len) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kb = lane >> 4;
   const int co = blockIdx.y * 16 + (lane & 15);
@@ -148,6 +148,9 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const u16* __restrict__ X
     dxx = tap % 3 - 1;
   }
   f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  // the bias gradient (column sums of dY) rides along in one wave per pixel block
+  const bool bias_wave = bpart && blockIdx.z == 0 && wave == 0;
+  float bsum = 0.f;
   const long p_begin = (long)blockIdx.x * pb_len;
   const long p_end = std::min(p_begin + pb_len, P);
   for (long pc = p_begin; pc < p_end; pc += 32) {
@@ -168,6 +171,10 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const u16* __restrict__ X
       av[e] = ga;
       bv[e] = gb;
     }
+    if (bias_wave) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bsum += bf2f(av[e]);
+    }
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
                                                   acc, 0, 0, 0);
   }
@@ -177,6 +184,11 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const u16* __restrict__ X
       const int cor = blockIdx.y * 16 + 4 * kb + i;
       part[((size_t)blockIdx.x * Cout + cor) * Kpad + kcol] = acc[i];
     }
+  }
+  if (bias_wave) {  // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the same channel
+    bsum += __shfl_xor(bsum, 16);
+    bsum += __shfl_xor(bsum, 32);
+    if (lane < 16) bpart[(size_t)blockIdx.x * Cout + co] = bsum;
   }
 }
 
@@ -189,26 +201,6 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, float* __restrict
   float s = 0.f;
   for (int b = 0; b < npb; ++b) s += part[((size_t)b * Cout + co) * Kpad + k];
   dw[i] = s;
-}
-
-// Column sums of a [P][C] bf16 array, C <= 256: part[blk][c] is the sum over
-// block blk's pixel range (threads of one channel add in a fixed order).
-__global__ __launch_bounds__(256) void k_colsum_part(const u16* __restrict__ dY, float* __restrict__ part, long P,
-                                                     int C, long chunk) {
-  __shared__ float red[256];
-  const int c = threadIdx.x % C, sub = threadIdx.x / C, nsub = 256 / C;
-  const long p0 = (long)blockIdx.x * chunk;
-  const long p1 = std::min(p0 + chunk, P);
-  float s = 0.f;
-  if (sub < nsub)
-    for (long p = p0 + sub; p < p1; p += nsub) s += bf2f(dY[(size_t)p * C + c]);
-  red[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x < C) {
-    float t = 0.f;
-    for (int j = 0; j < nsub; ++j) t += red[j * C + threadIdx.x];
-    part[(size_t)blockIdx.x * C + threadIdx.x] = t;
-  }
 }
 
 // out[j] = sum_b part[b][j], b in order
@@ -453,9 +445,47 @@ __global__ void k_head_bwd_data(const float* __restrict__ dout, const float* __r
 }
 
 // head parameter-gradient partials over pixel chunks: columns o C + c
-// (weights), then 2 C + o (bias)
-__global__ void k_head_wgrad(const float* __restrict__ dout, const u16* __restrict__ x, float* __restrict__ part,
-                             long P, int C, long chunk) {
+// (weights), then 2 C + o (bias).  Thread t takes pixels p0 + t, p0 + t + 256,
+// ... of its block's chunk and keeps the 2 C + 2 sums in registers; the block
+// then adds the 256 thread sums of each column in thread order.
+template <int C>
+__global__ __launch_bounds__(256) void k_head_wgrad(const float* __restrict__ dout, const u16* __restrict__ x,
+                                                    float* __restrict__ part, long P, long chunk) {
+  constexpr int NC = 2 * C + 2;
+  __shared__ float red[NC][257];
+  const int t = threadIdx.x;
+  const long p0 = (long)blockIdx.x * chunk;
+  const long p1 = std::min(p0 + chunk, P);
+  float s[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) s[j] = 0.f;
+  for (long p = p0 + t; p < p1; p += 256) {
+    const float2 d = *reinterpret_cast<const float2*>(dout + 2 * p);
+    u16 xv[C];
+#pragma unroll
+    for (int q = 0; q < C / 8; ++q) *reinterpret_cast<uint4*>(xv + 8 * q) = reinterpret_cast<const uint4*>(x + (size_t)p * C)[q];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const float xc = bf2f(xv[c]);
+      s[c] += d.x * xc;
+      s[C + c] += d.y * xc;
+    }
+    s[2 * C] += d.x;
+    s[2 * C + 1] += d.y;
+  }
+#pragma unroll
+  for (int j = 0; j < NC; ++j) red[j][t] = s[j];
+  __syncthreads();
+  if (t < NC) {
+    float a = 0.f;
+    for (int i = 0; i < 256; ++i) a += red[t][i];
+    part[(size_t)blockIdx.x * NC + t] = a;
+  }
+}
+
+// generic channel count: one thread per column, serial over the chunk
+__global__ void k_head_wgrad_any(const float* __restrict__ dout, const u16* __restrict__ x, float* __restrict__ part,
+                                 long P, int C, long chunk) {
   const int j = threadIdx.x;
   const int ncol = 2 * C + 2;
   if (j >= ncol) return;
@@ -472,6 +502,14 @@ __global__ void k_head_wgrad(const float* __restrict__ dout, const u16* __restri
   part[(size_t)blockIdx.x * ncol + j] = s;
 }
 
+void head_wgrad_launch(const float* dout, const u16* x, float* part, long P, int C, int nparts, hipStream_t st) {
+  const long chunk = (P + nparts - 1) / nparts;
+  if (C == 16)
+    hipLaunchKernelGGL(k_head_wgrad<16>, dim3(nparts), dim3(256), 0, st, dout, x, part, P, chunk);
+  else
+    hipLaunchKernelGGL(k_head_wgrad_any, dim3(nparts), dim3(256), 0, st, dout, x, part, P, C, chunk);
+}
+
 // Adam (Kingma and Ba): m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
 // p -= lr (m / c1) / (sqrt(v / c2) + eps), c1 = 1 - b1^t, c2 = 1 - b2^t
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
@@ -486,30 +524,41 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// replay-plane start field: field = T y / |y| (y = 0 counts as phase 0);
-// y = NULL selects the quadratic phase 2 pi ((u - nx/2)^2 / nx + (v - ny/2)^2 / ny),
-// evaluated exactly through the integer residues of the squares.
+// e^{i psi0} of the quadratic replay-plane phase
+// psi0 = 2 pi ((u - nx/2)^2 / nx + (v - ny/2)^2 / ny) at centred pixel i of an
+// ny x nx plane, evaluated exactly through the integer residues of the squares.
+__device__ __forceinline__ float2 quadratic_phasor(long pix, int ny, int nx) {
+  const long u = pix % nx - nx / 2, v = pix / nx - ny / 2;
+  const double frac = (double)((u * u) % nx) / nx + (double)((v * v) % ny) / ny;
+  double sd, cd;
+  sincospi(2.0 * frac, &sd, &cd);
+  return make_float2((float)cd, (float)sd);
+}
+
+// replay-plane start field: field = T e^{i (arg y + [quad] psi0)}, y nullable
+// (NULL or 0 counts as phase 0)
 __global__ void k_replay_start(const float* __restrict__ t, const float2* __restrict__ y, float2* __restrict__ field,
-                               int ny, int nx, long total) {
+                               int ny, int nx, int quad, long total) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
   const float tv = t[i];
-  float c, s;
+  float2 e = make_float2(1.f, 0.f);
   if (y) {
     const float2 q = y[i];
     const float mg = sqrtf(q.x * q.x + q.y * q.y);
-    c = mg > 0.f ? q.x / mg : 1.f;
-    s = mg > 0.f ? q.y / mg : 0.f;
-  } else {
-    const long pix = i % ((long)ny * nx);
-    const long u = pix % nx - nx / 2, v = pix / nx - ny / 2;
-    const double frac = (double)((u * u) % nx) / nx + (double)((v * v) % ny) / ny;
-    double sd, cd;
-    sincospi(2.0 * frac, &sd, &cd);
-    c = (float)cd;
-    s = (float)sd;
+    if (mg > 0.f) e = make_float2(q.x / mg, q.y / mg);
   }
-  field[i] = make_float2(tv * c, tv * s);
+  if (quad) e = hg::cmul(e, quadratic_phasor(i % ((long)ny * nx), ny, nx));
+  field[i] = make_float2(tv * e.x, tv * e.y);
+}
+
+// field *= e^{sign i psi0}
+__global__ void k_apply_quadratic(float2* __restrict__ field, int ny, int nx, int sign, long total) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  float2 q = quadratic_phasor(i % ((long)ny * nx), ny, nx);
+  if (sign < 0) q.y = -q.y;
+  field[i] = hg::cmul(field[i], q);
 }
 
 __global__ void k_project_levels(const float2* __restrict__ g, uint8_t* __restrict__ levels, int L, long total) {
@@ -583,27 +632,21 @@ WgradPlan wgrad_plan(long P, int Cin, int Cout) {
   pb = std::max(256L, (pb + 31) / 32 * 32);
   return {pb, (int)((P + pb - 1) / pb)};
 }
-constexpr int kColsumParts = 64;
 size_t wgrad_ws_bytes(long P, int Cin, int Cout) {
   const WgradPlan w = wgrad_plan(P, Cin, Cout);
-  return al256((size_t)w.npb * Cout * kpad_of(9 * Cin) * sizeof(float)) +
-         al256((size_t)kColsumParts * Cout * sizeof(float));
+  return al256((size_t)w.npb * Cout * kpad_of(9 * Cin) * sizeof(float)) + al256((size_t)w.npb * Cout * sizeof(float));
 }
 void wgrad_launch(const u16* X, const u16* dY, float* dw, float* db, long P, int H, int W, int Cin, int Cout,
                   char* ws, hipStream_t st) {
   const WgradPlan wp = wgrad_plan(P, Cin, Cout);
   const int Kp = kpad_of(9 * Cin);
   float* part = reinterpret_cast<float*>(ws);
-  hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(wp.npb, Cout / 16, (Kp + 63) / 64), dim3(256), 0, st, X, dY, part, P, H, W,
-                     Cin, Cout, Kp, wp.pb_len);
+  float* bpart = db ? reinterpret_cast<float*>(ws + al256((size_t)wp.npb * Cout * Kp * sizeof(float))) : nullptr;
+  hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(wp.npb, Cout / 16, (Kp + 63) / 64), dim3(256), 0, st, X, dY, part, bpart,
+                     P, H, W, Cin, Cout, Kp, wp.pb_len);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk((long)Cout * 9 * Cin, 256)), dim3(256), 0, st, part, dw, wp.npb, Cout,
                      Kp, 9 * Cin);
-  if (db) {
-    float* bpart = reinterpret_cast<float*>(ws + al256((size_t)wp.npb * Cout * Kp * sizeof(float)));
-    const long chunk = (P + kColsumParts - 1) / kColsumParts;
-    hipLaunchKernelGGL(k_colsum_part, dim3(kColsumParts), dim3(256), 0, st, dY, bpart, P, Cout, chunk);
-    hipLaunchKernelGGL(k_sum_parts, dim3(nblk(Cout, 256)), dim3(256), 0, st, bpart, db, kColsumParts, Cout);
-  }
+  if (db) hipLaunchKernelGGL(k_sum_parts, dim3(nblk(Cout, 256)), dim3(256), 0, st, bpart, db, wp.npb, Cout);
 }
 
 constexpr int kLossParts = 64;
@@ -851,10 +894,9 @@ hg_status hg_nn_head_backward(const float* dout, const float* w, const void* x, 
   if (s != HG_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   float* part = (float*)ws;
-  const long chunk = (pixels + kHeadParts - 1) / kHeadParts;
   hipLaunchKernelGGL(k_head_bwd_data, dim3(nblk(pixels * c, 256)), dim3(256), 0, st, dout, w, (const u16*)x, (u16*)dx,
                      pixels, c);
-  hipLaunchKernelGGL(k_head_wgrad, dim3(kHeadParts), dim3(256), 0, st, dout, (const u16*)x, part, pixels, c, chunk);
+  head_wgrad_launch(dout, (const u16*)x, part, pixels, c, kHeadParts, st);
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, part, dwb, kHeadParts, 2 * c + 2);
   return nn_launch_status();
 }
@@ -973,10 +1015,9 @@ hg_status hg_nn_backward(const float* params, const float* out, const hg_complex
   u16* dh = G();
   {
     float* part = reinterpret_cast<float*>(scratch);
-    const long chunk = (p.P[0] + kHeadParts - 1) / kHeadParts;
     hipLaunchKernelGGL(k_head_bwd_data, dim3(nblk(p.P[0] * c0, 256)), dim3(256), 0, st, dout, params + n.L[HEAD].w,
                        A(p.act[D0B]), dh, p.P[0], c0);
-    hipLaunchKernelGGL(k_head_wgrad, dim3(kHeadParts), dim3(256), 0, st, dout, A(p.act[D0B]), part, p.P[0], c0, chunk);
+    head_wgrad_launch(dout, A(p.act[D0B]), part, p.P[0], c0, kHeadParts, st);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, part, grads + n.L[HEAD].w, kHeadParts, 2 * c0 + 2);
   }
   // one conv layer: dz (already masked) -> weight and bias gradients, and the
@@ -1032,8 +1073,19 @@ size_t hg_replay_phase_init_workspace_size(int batch, int ny, int nx) {
   return al256((size_t)batch * ny * nx * sizeof(float2)) + prop;
 }
 
+hg_status hg_quadratic_phase_apply(hg_complex* field, int batch, int ny, int nx, int sign, void* stream) {
+  clear_error();
+  if (!field || batch < 1 || ny < 1 || nx < 1 || (sign != 1 && sign != -1))
+    return nn_fail(HG_ERR_INVALID_ARG, "quadratic_phase_apply: NULL field, empty shape or sign not +-1");
+  const long total = (long)batch * ny * nx;
+  hipLaunchKernelGGL(k_apply_quadratic, dim3(nblk(total, 256)), dim3(256), 0, (hipStream_t)stream,
+                     reinterpret_cast<float2*>(field), ny, nx, sign, total);
+  return nn_launch_status();
+}
+
 hg_status hg_replay_phase_init(const hg_complex* phasor, const float* target, int batch, int ny, int nx,
-                               int slm_levels, uint8_t* levels_out, void* ws, size_t ws_bytes, void* stream) {
+                               int slm_levels, int add_quadratic, uint8_t* levels_out, void* ws, size_t ws_bytes,
+                               void* stream) {
   clear_error();
   if (!target || !levels_out) return nn_fail(HG_ERR_INVALID_ARG, "replay_phase_init: NULL target or levels_out");
   if (slm_levels < 2 || slm_levels > 256)
@@ -1048,7 +1100,7 @@ hg_status hg_replay_phase_init(const hg_complex* phasor, const float* target, in
   const size_t fbytes = al256((size_t)total * sizeof(float2));
   char* pws = (char*)ws + fbytes;
   hipLaunchKernelGGL(k_replay_start, dim3(nblk(total, 256)), dim3(256), 0, st, target,
-                     reinterpret_cast<const float2*>(phasor), field, ny, nx, total);
+                     reinterpret_cast<const float2*>(phasor), field, ny, nx, add_quadratic ? 1 : 0, total);
   s = nn_launch_status();
   if (s != HG_OK) return s;
   for (int b = 0; b < batch; ++b) {

@@ -49,11 +49,13 @@ def gaussian_target(n, seed, batch_item=0, count=32, ny=None):
     cx = x0 + wx * rng.random(count)
     sig = (5.0 + 55.0 * rng.random(count)) * scale
     amp = 0.2 + 0.8 * rng.random(count)
+    # each isotropic Gaussian is the outer product of two 1-D profiles, so the
+    # sum over Gaussians is one (ny x count) (count x nx) product
     yy = np.arange(ny, dtype=np.float64)[:, None]
-    xx = np.arange(nx, dtype=np.float64)[None, :]
-    inten = np.zeros((ny, nx))
-    for i in range(count):
-        inten += amp[i] * np.exp(-((yy - cy[i]) ** 2 + (xx - cx[i]) ** 2) / (2.0 * sig[i] ** 2))
+    xx = np.arange(nx, dtype=np.float64)[:, None]
+    gy = np.exp(-((yy - cy[None, :]) ** 2) / (2.0 * sig[None, :] ** 2))
+    gx = np.exp(-((xx - cx[None, :]) ** 2) / (2.0 * sig[None, :] ** 2))
+    inten = (gy * amp[None, :]) @ gx.T
     win = np.zeros((ny, nx), bool)
     win[y0:y0 + wy, x0:x0 + wx] = True
     inten = np.where(win, inten, 0.0)

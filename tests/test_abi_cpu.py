@@ -127,8 +127,9 @@ def test_nn_layer_validation():
     assert L.hg_nn_conv3x3(None, FAKE, None, None, FAKE, 1, 8, 8, 16, 16, 0, None) == hg.HG_ERR_INVALID_ARG
     assert L.hg_nn_avgpool2(FAKE, FAKE, 1, 7, 8, 4, None) == hg.HG_ERR_INVALID_ARG
     assert L.hg_nn_adam(FAKE, FAKE, FAKE, FAKE, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == hg.HG_ERR_INVALID_ARG
-    assert L.hg_replay_phase_init(None, FAKE, 1, 64, 64, 1, FAKE, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG
-    assert L.hg_replay_phase_init(None, FAKE, 1, 64, 48, 8, FAKE, FAKE, 1 << 30, None) == \
+    assert L.hg_replay_phase_init(None, FAKE, 1, 64, 64, 1, 1, FAKE, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG
+    assert L.hg_replay_phase_init(None, FAKE, 1, 64, 48, 8, 1, FAKE, FAKE, 1 << 30, None) == \
         hg.HG_ERR_UNSUPPORTED_SIZE
+    assert L.hg_quadratic_phase_apply(FAKE, 1, 64, 64, 0, None) == hg.HG_ERR_INVALID_ARG
     assert L.hg_nn_conv3x3_wgrad(FAKE, FAKE, FAKE, FAKE, 1, 8, 8, 16, 272, FAKE, 1 << 30, None) == \
         hg.HG_ERR_INVALID_ARG  # more than 256 output channels

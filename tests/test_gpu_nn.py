@@ -241,21 +241,23 @@ def test_adam_matches_oracle():
     np.testing.assert_allclose(host(tp), p["a"], rtol=1e-5, atol=1e-6)
 
 
-@pytest.mark.parametrize("quadratic", [False, True])
-def test_replay_phase_init_levels(quadratic):
-    say("replay-phase start levels, quadratic =", quadratic)
+@pytest.mark.parametrize("mode", ["phasor", "quadratic", "residual"])
+def test_replay_phase_init_levels(mode):
+    say("replay-phase start levels, mode =", mode)
     rng = np.random.default_rng(61)
     b, ny, nx, L = 2, 64, 128, 8
     T = np.stack([synth.gaussian_target(128, seed=9 + i)[:ny, :nx] for i in range(b)]).astype(np.float32)
-    if quadratic:
-        ph = np.broadcast_to(np.exp(1j * nn.quadratic_phase(ny, nx)), (b, ny, nx))
+    ph = (rng.standard_normal((b, ny, nx)) + 1j * rng.standard_normal((b, ny, nx))).astype(np.complex64)
+    if mode == "quadratic":
         lev = hg.hg_replay_phase_init(f32(T), L)
-    else:
-        ph = (rng.standard_normal((b, ny, nx)) + 1j * rng.standard_normal((b, ny, nx))).astype(np.complex64)
+    elif mode == "phasor":
         lev = hg.hg_replay_phase_init(f32(T), L, phasor=torch.from_numpy(ph).to(DEV))
+    else:
+        lev = hg.hg_replay_phase_init(f32(T), L, phasor=torch.from_numpy(ph).to(DEV), add_quadratic=True)
     got = host(lev)
     for i in range(b):
-        ref, g = nn.replay_phase_levels(T[i].astype(np.float64), np.asarray(ph[i], np.complex128), L)
+        ref, g = nn.replay_phase_levels(T[i].astype(np.float64), None if mode == "quadratic" else ph[i], L,
+                                        add_quadratic=mode != "phasor")
         mism = got[i].astype(np.int64) != ref
         margin = slm.boundary_margin(g, L)
         # FP32 transform error relative to the local |g|: exempt pixels near a
@@ -263,6 +265,17 @@ def test_replay_phase_init_levels(quadratic):
         bad = mism & (margin >= 1e-3)
         say(f"  image {i}: {int(mism.sum())} mismatches, {int((mism & (margin < 1e-3)).sum())} exempt")
         assert not bad.any()
+
+
+def test_quadratic_phase_apply():
+    say("quadratic phase apply")
+    rng = np.random.default_rng(65)
+    f = (rng.standard_normal((2, 64, 256)) + 1j * rng.standard_normal((2, 64, 256))).astype(np.complex64)
+    q = np.exp(1j * nn.quadratic_phase(64, 256))
+    for sign in (1, -1):
+        got = host(hg.hg_quadratic_phase_apply(torch.from_numpy(f).to(DEV), sign))
+        ref = f.astype(np.complex128) * (q if sign > 0 else np.conj(q))
+        assert np.max(np.abs(got - ref)) < 1e-5 * np.max(np.abs(ref))
 
 
 def test_batched_gs_with_start_levels_and_replay():

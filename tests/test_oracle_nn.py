@@ -151,3 +151,17 @@ def test_replay_phase_levels_recovers_consistent_hologram():
     got, g = nn.replay_phase_levels(np.abs(R), R * 3.7, L)
     np.testing.assert_array_equal(got, lev)
     np.testing.assert_allclose(g, slm.level_phasor(lev, L), atol=1e-12)
+
+
+def test_replay_phase_levels_quadratic_residual():
+    # a residual phase about the quadratic phase plus add_quadratic is the
+    # same start as the full phase
+    rng = np.random.default_rng(10)
+    T = rng.random((16, 32))
+    psi = rng.uniform(-np.pi, np.pi, (16, 32))
+    full, g1 = nn.replay_phase_levels(T, np.exp(1j * psi), 8)
+    res, g2 = nn.replay_phase_levels(T, np.exp(1j * (psi - nn.quadratic_phase(16, 32))), 8, add_quadratic=True)
+    np.testing.assert_allclose(g2, g1, atol=1e-12)
+    q, _ = nn.replay_phase_levels(T, None, 8, add_quadratic=True)
+    q2, _ = nn.replay_phase_levels(T, np.exp(1j * nn.quadratic_phase(16, 32)), 8)
+    np.testing.assert_array_equal(q, q2)
