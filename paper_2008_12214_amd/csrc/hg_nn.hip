@@ -122,6 +122,136 @@ __global__ __launch_bounds__(256) void k_conv3x3(const u16* __restrict__ X, cons
 }
 
 // ---------------------------------------------------------------------------
+// The same convolution with the input tile staged in LDS (Cin % 8 == 0,
+// W % 16 == 0).  A workgroup covers R rows x TW columns of one image for
+// 16 NB output channels: it copies the (R + 2) x (TW + 2) x Cin halo tile
+// into LDS with 16-byte loads (zeros outside the image), each wave runs GW
+// 16-pixel groups against NB weight fragments per 32-wide k step (A
+// fragments read from LDS, 16 bytes per lane), and the bf16 results go
+// through an LDS staging tile so the stores (and the mask loads) are 16
+// bytes per lane.  R TW = 64 GW.
+// ---------------------------------------------------------------------------
+// LDS elements per staged input pixel: Cin padded by 8 when Cin / 8 is even,
+// so the pixel stride is an odd multiple of 16 bytes and the 16 pixel lanes
+// of a 16-byte A-fragment read fall in distinct bank groups.
+__host__ __device__ inline int tile_pixel_stride(int Cin) { return ((Cin / 8) & 1) ? Cin : Cin + 8; }
+
+template <int NB, int GW>
+__global__ __launch_bounds__(256) void k_conv3x3_tile(const u16* __restrict__ X, const u16* __restrict__ Wg,
+                                                      const float* __restrict__ bias, const u16* __restrict__ mask,
+                                                      u16* __restrict__ Y, int H, int W, int Cin, int Cout, int Kpad,
+                                                      int relu, int TW, int R) {
+  extern __shared__ __align__(16) u16 smem[];
+  const int tiles_x = W / TW + (W % TW ? 1 : 0), tiles_y = H / R + (H % R ? 1 : 0);
+  int t = blockIdx.x;
+  const int tx = t % tiles_x;
+  t /= tiles_x;
+  const int ty = t % tiles_y;
+  const int n = t / tiles_y;
+  const int x0 = tx * TW, y0 = ty * R;
+  const int TWp = TW + 2;
+  const int PS = tile_pixel_stride(Cin);           // LDS elements per pixel
+  u16* in = smem;                                  // [(R + 2)][(TW + 2)][PS]
+  u16* outs = smem + (size_t)(R + 2) * TWp * PS;   // [R TW][16 NB]
+  const int cpp = Cin / 8;                         // 16-byte chunks per pixel
+  const u16* xn = X + (size_t)n * H * W * Cin;
+  for (int i = threadIdx.x; i < (R + 2) * TWp * cpp; i += 256) {
+    const int c = i % cpp, pix = i / cpp;
+    const int ly = pix / TWp, lx = pix - ly * TWp;
+    const int gy = y0 + ly - 1, gx = x0 + lx - 1;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+      v = *reinterpret_cast<const uint4*>(xn + ((size_t)gy * W + gx) * Cin + 8 * c);
+    *reinterpret_cast<uint4*>(in + (size_t)pix * PS + 8 * c) = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, kb = lane >> 4;
+  const int gpr = TW / 16;
+  const int co0 = blockIdx.y * 16 * NB;
+  const int K = 9 * Cin;
+  f32x4 acc[GW][NB];
+#pragma unroll
+  for (int j = 0; j < GW; ++j)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[j][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int abase[GW];  // LDS element offset of lane m's pixel (tap (0, 0)) in group j
+#pragma unroll
+  for (int j = 0; j < GW; ++j) {
+    const int g = wave * GW + j;
+    const int r = g / gpr, xg = (g - r * gpr) * 16;
+    abase[j] = (r * TWp + xg + m) * PS;
+  }
+  // weight fragments are fetched one k step ahead of their use
+  const u16* wrow[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) wrow[nb] = Wg + (size_t)(co0 + nb * 16 + m) * Kpad + 8 * kb;
+  bf16x8 b[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) b[nb] = load8(wrow[nb]);
+  for (int kc = 0; kc < Kpad; kc += 32) {
+    const int k = kc + 8 * kb;
+    const bool kv = k < K;
+    int off = 0;
+    if (kv) {
+      const int tap = k / Cin, ci = k - tap * Cin;
+      off = ((tap / 3) * TWp + tap % 3) * PS + ci;
+    }
+    bf16x8 bn[NB];
+    const int kn = kc + 32 < Kpad ? kc + 32 : kc;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) bn[nb] = load8(wrow[nb] + kn);
+#pragma unroll
+    for (int j = 0; j < GW; ++j) {
+      const bf16x8 a = kv ? load8(in + abase[j] + off) : zero8();
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[j][nb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) b[nb] = bn[nb];
+  }
+  constexpr int CW = 16 * NB;  // staged channels per pixel
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const float bv = bias ? bias[co0 + nb * 16 + m] : 0.f;
+#pragma unroll
+    for (int j = 0; j < GW; ++j) {
+      const int g = wave * GW + j;
+      const int r = g / gpr, xg = (g - r * gpr) * 16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float v = acc[j][nb][i] + bv;
+        if (relu) v = fmaxf(v, 0.f);
+        outs[(r * TW + xg + 4 * kb + i) * CW + nb * 16 + m] = f2bf(v);
+      }
+    }
+  }
+  __syncthreads();
+  constexpr int CPO = CW / 8;  // 16-byte chunks per staged pixel
+  for (int i = threadIdx.x; i < R * TW * CPO; i += 256) {
+    const int c = i % CPO, pl = i / CPO;
+    const int ly = pl / TW, lx = pl - ly * TW;
+    const int gy = y0 + ly, gx = x0 + lx;
+    if (gy < H && gx < W) {
+      uint4 v = *reinterpret_cast<const uint4*>(outs + pl * CW + 8 * c);
+      const size_t o = (((size_t)n * H + gy) * W + gx) * Cout + co0 + 8 * c;
+      if (mask) {
+        const uint4 mk = *reinterpret_cast<const uint4*>(mask + o);
+        uint32_t* vv = reinterpret_cast<uint32_t*>(&v);
+        const uint32_t* mm = reinterpret_cast<const uint32_t*>(&mk);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t lo = bf2f((u16)(mm[q] & 0xFFFFu)) > 0.f ? 0x0000FFFFu : 0u;
+          const uint32_t hi = bf2f((u16)(mm[q] >> 16)) > 0.f ? 0xFFFF0000u : 0u;
+          vv[q] &= lo | hi;
+        }
+      }
+      *reinterpret_cast<uint4*>(Y + o) = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient: part[pb][co][k] = sum over pixel block pb of
 // dY[p][co] A[p][k] (A = implicit im2col of X), i.e. dY^T A with pixels as
 // the MFMA reduction dimension:
@@ -264,6 +394,204 @@ __global__ void k_input(const float* __restrict__ t, const double* __restrict__ 
   const float scale = s > 0.0 ? (float)sqrt((double)HW / s) : 0.f;
   for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += (long)gridDim.x * blockDim.x)
     x[base + p] = f2bf(t[base + p] * scale);
+}
+
+// ---- 16-byte (8-channel) versions of the element-wise layers below; used
+// when the channel counts are multiples of 8.  They add in the same order as
+// the scalar kernels.
+__device__ __forceinline__ void unpack8(const uint4& q, float (&f)[8]) {
+  const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    f[2 * i] = bf2f((u16)(w[i] & 0xFFFFu));
+    f[2 * i + 1] = bf2f((u16)(w[i] >> 16));
+  }
+}
+__device__ __forceinline__ uint4 pack8(const float (&f)[8]) {
+  uint32_t w[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = (uint32_t)f2bf(f[2 * i]) | ((uint32_t)f2bf(f[2 * i + 1]) << 16);
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+__device__ __forceinline__ uint4 ld16(const u16* p) { return *reinterpret_cast<const uint4*>(p); }
+__device__ __forceinline__ void st16(u16* p, const uint4& v) { *reinterpret_cast<uint4*>(p) = v; }
+__device__ __forceinline__ void apply_mask8(float (&f)[8], const u16* m) {
+  float mk[8];
+  unpack8(ld16(m), mk);
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    if (!(mk[e] > 0.f)) f[e] = 0.f;
+}
+
+__global__ void k_avgpool2_v8(const u16* __restrict__ x, u16* __restrict__ y, int N, int H, int W, int C) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
+  if (i >= (long)N * Ho * Wo * C8) return;
+  const int c8 = (int)(i % C8);
+  long r = i / C8;
+  const int xo = (int)(r % Wo);
+  r /= Wo;
+  const int yo = (int)(r % Ho);
+  const long n = r / Ho;
+  const size_t b = (((size_t)n * H + 2 * yo) * W + 2 * xo) * C + 8 * c8;
+  const size_t rs = (size_t)W * C;
+  float a[8], bb[8], c[8], d[8], o[8];
+  unpack8(ld16(x + b), a);
+  unpack8(ld16(x + b + C), bb);
+  unpack8(ld16(x + b + rs), c);
+  unpack8(ld16(x + b + rs + C), d);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) o[e] = 0.25f * ((a[e] + bb[e]) + (c[e] + d[e]));
+  st16(y + (size_t)i * 8, pack8(o));
+}
+
+__global__ void k_avgpool2_bwd_v8(const u16* __restrict__ dy, const u16* __restrict__ dskip,
+                                  const u16* __restrict__ mask, u16* __restrict__ dx, int N, int H, int W, int C) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int C8 = C / 8;
+  if (i >= (long)N * H * W * C8) return;
+  const int c8 = (int)(i % C8);
+  long r = i / C8;
+  const int x = (int)(r % W);
+  r /= W;
+  const int yv = (int)(r % H);
+  const long n = r / H;
+  float g[8];
+  unpack8(ld16(dy + (((size_t)n * (H / 2) + yv / 2) * (W / 2) + x / 2) * C + 8 * c8), g);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) g[e] *= 0.25f;
+  if (dskip) {
+    float s2[8];
+    unpack8(ld16(dskip + (size_t)i * 8), s2);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) g[e] += s2[e];
+  }
+  if (mask) apply_mask8(g, mask + (size_t)i * 8);
+  st16(dx + (size_t)i * 8, pack8(g));
+}
+
+__global__ void k_upcat_v8(const u16* __restrict__ lo, const u16* __restrict__ skip, u16* __restrict__ out, int N,
+                           int H, int W, int C1, int C2) {
+  const int C8 = (C1 + C2) / 8, L8 = C1 / 8;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)N * H * W * C8) return;
+  const int c8 = (int)(i % C8);
+  const long p = i / C8;
+  uint4 v;
+  if (c8 < L8) {
+    const int x = (int)(p % W);
+    const long r = p / W;
+    const int yv = (int)(r % H);
+    const long n = r / H;
+    v = ld16(lo + (((size_t)n * (H / 2) + yv / 2) * (W / 2) + x / 2) * C1 + 8 * c8);
+  } else {
+    v = ld16(skip + (size_t)p * C2 + 8 * (c8 - L8));
+  }
+  st16(out + (size_t)i * 8, v);
+}
+
+__global__ void k_upcat_bwd_v8(const u16* __restrict__ dout, const u16* __restrict__ mask_lo, u16* __restrict__ dlo,
+                               u16* __restrict__ dskip, int N, int H, int W, int C1, int C2) {
+  const int C = C1 + C2, L8 = C1 / 8, S8 = C2 / 8;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nlo = (long)N * (H / 2) * (W / 2) * L8;
+  const long nsk = (long)N * H * W * S8;
+  if (i < nlo) {
+    const int c8 = (int)(i % L8);
+    long r = i / L8;
+    const int xo = (int)(r % (W / 2));
+    r /= (W / 2);
+    const int yo = (int)(r % (H / 2));
+    const long n = r / (H / 2);
+    const size_t b = (((size_t)n * H + 2 * yo) * W + 2 * xo) * C + 8 * c8;
+    const size_t rs = (size_t)W * C;
+    float a[8], bb[8], c[8], d[8], o[8];
+    unpack8(ld16(dout + b), a);
+    unpack8(ld16(dout + b + C), bb);
+    unpack8(ld16(dout + b + rs), c);
+    unpack8(ld16(dout + b + rs + C), d);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o[e] = (a[e] + bb[e]) + (c[e] + d[e]);
+    if (mask_lo) apply_mask8(o, mask_lo + (size_t)i * 8);
+    st16(dlo + (size_t)i * 8, pack8(o));
+  } else if (i < nlo + nsk) {
+    const long j = i - nlo;
+    const int c8 = (int)(j % S8);
+    const long p = j / S8;
+    st16(dskip + (size_t)j * 8, ld16(dout + (size_t)p * C + C1 + 8 * c8));
+  }
+}
+
+// 1x1 head with 16 input channels: one pixel per thread, two 16-byte loads
+__global__ void k_head16(const u16* __restrict__ x, const float* __restrict__ w, const float* __restrict__ b,
+                         float* __restrict__ out, long P) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  float v[16];
+  unpack8(ld16(x + (size_t)p * 16), *reinterpret_cast<float(*)[8]>(v));
+  unpack8(ld16(x + (size_t)p * 16 + 8), *reinterpret_cast<float(*)[8]>(v + 8));
+  float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    a0 += v[c] * bf2f(f2bf(w[c]));
+    a1 += v[c] * bf2f(f2bf(w[16 + c]));
+  }
+  *reinterpret_cast<float2*>(out + 2 * p) = make_float2(a0 + b[0], a1 + b[1]);
+}
+
+// head backward-data with 16 channels, one pixel per thread
+__global__ void k_head_bwd_data16(const float* __restrict__ dout, const float* __restrict__ w,
+                                  const u16* __restrict__ x, u16* __restrict__ dx, long P) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const float2 d = *reinterpret_cast<const float2*>(dout + 2 * p);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float g[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int c = 8 * h + e;
+      g[e] = d.x * bf2f(f2bf(w[c])) + d.y * bf2f(f2bf(w[16 + c]));
+    }
+    apply_mask8(g, x + (size_t)p * 16 + 8 * h);
+    st16(dx + (size_t)p * 16 + 8 * h, pack8(g));
+  }
+}
+
+// First layer (one input channel, 16 outputs): one pixel per thread, the nine
+// taps summed in tap order in FP32, bias, ReLU, optional mask, two 16-byte
+// stores.  Wg is the packed [16][32] operand (taps 0..8 used).
+__global__ void k_conv_first16(const u16* __restrict__ X, const u16* __restrict__ Wg, const float* __restrict__ bias,
+                               const u16* __restrict__ mask, u16* __restrict__ Y, long P, int H, int W, int Kpad,
+                               int relu) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const long HW = (long)H * W;
+  const long n = p / HW;
+  const int r = (int)(p - n * HW);
+  const int y = r / W, x = r - y * W;
+  const u16* xn = X + (size_t)n * HW;
+  float xv[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+    xv[t] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? bf2f(xn[(size_t)yy * W + xx]) : 0.f;
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float o[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int co = 8 * h + e;
+      float a = 0.f;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) a += xv[t] * bf2f(Wg[co * Kpad + t]);
+      a += bias ? bias[co] : 0.f;
+      o[e] = relu ? fmaxf(a, 0.f) : a;
+    }
+    if (mask) apply_mask8(o, mask + (size_t)p * 16 + 8 * h);
+    st16(Y + (size_t)p * 16 + 8 * h, pack8(o));
+  }
 }
 
 // 2x2 average pool, NHWC bf16
@@ -596,11 +924,117 @@ hg_status nn_launch_status() {
 inline unsigned nblk(long n, int t) { return (unsigned)((n + t - 1) / t); }
 inline int kpad_of(int K) { return (K + 31) / 32 * 32; }
 
+// ---- element-wise launchers: 16-byte kernels when the channels allow ----
+void pool_launch(const u16* x, u16* y, int N, int H, int W, int C, hipStream_t st) {
+  if (C % 8 == 0) {
+    const long cnt = (long)N * (H / 2) * (W / 2) * (C / 8);
+    hipLaunchKernelGGL(k_avgpool2_v8, dim3(nblk(cnt, 256)), dim3(256), 0, st, x, y, N, H, W, C);
+  } else {
+    const long cnt = (long)N * (H / 2) * (W / 2) * C;
+    hipLaunchKernelGGL(k_avgpool2, dim3(nblk(cnt, 256)), dim3(256), 0, st, x, y, N, H, W, C);
+  }
+}
+void pool_bwd_launch(const u16* dy, const u16* dskip, const u16* mask, u16* dx, int N, int H, int W, int C,
+                     hipStream_t st) {
+  if (C % 8 == 0) {
+    const long cnt = (long)N * H * W * (C / 8);
+    hipLaunchKernelGGL(k_avgpool2_bwd_v8, dim3(nblk(cnt, 256)), dim3(256), 0, st, dy, dskip, mask, dx, N, H, W, C);
+  } else {
+    const long cnt = (long)N * H * W * C;
+    hipLaunchKernelGGL(k_avgpool2_bwd, dim3(nblk(cnt, 256)), dim3(256), 0, st, dy, dskip, mask, dx, N, H, W, C);
+  }
+}
+void upcat_launch(const u16* lo, const u16* skip, u16* out, int N, int H, int W, int C1, int C2, hipStream_t st) {
+  if (C1 % 8 == 0 && C2 % 8 == 0) {
+    const long cnt = (long)N * H * W * ((C1 + C2) / 8);
+    hipLaunchKernelGGL(k_upcat_v8, dim3(nblk(cnt, 256)), dim3(256), 0, st, lo, skip, out, N, H, W, C1, C2);
+  } else {
+    const long cnt = (long)N * H * W * (C1 + C2);
+    hipLaunchKernelGGL(k_upcat, dim3(nblk(cnt, 256)), dim3(256), 0, st, lo, skip, out, N, H, W, C1, C2);
+  }
+}
+void upcat_bwd_launch(const u16* dout, const u16* mask_lo, u16* dlo, u16* dskip, int N, int H, int W, int C1, int C2,
+                      hipStream_t st) {
+  if (C1 % 8 == 0 && C2 % 8 == 0) {
+    const long cnt = (long)N * (H / 2) * (W / 2) * (C1 / 8) + (long)N * H * W * (C2 / 8);
+    hipLaunchKernelGGL(k_upcat_bwd_v8, dim3(nblk(cnt, 256)), dim3(256), 0, st, dout, mask_lo, dlo, dskip, N, H, W, C1,
+                       C2);
+  } else {
+    const long cnt = (long)N * (H / 2) * (W / 2) * C1 + (long)N * H * W * C2;
+    hipLaunchKernelGGL(k_upcat_bwd, dim3(nblk(cnt, 256)), dim3(256), 0, st, dout, mask_lo, dlo, dskip, N, H, W, C1,
+                       C2);
+  }
+}
+void head_launch(const u16* x, const float* w, const float* b, float* out, long P, int C, hipStream_t st) {
+  if (C == 16)
+    hipLaunchKernelGGL(k_head16, dim3(nblk(P, 256)), dim3(256), 0, st, x, w, b, out, P);
+  else
+    hipLaunchKernelGGL(k_head, dim3(nblk(P, 256)), dim3(256), 0, st, x, w, b, out, P, C);
+}
+void head_bwd_launch(const float* dout, const float* w, const u16* x, u16* dx, long P, int C, hipStream_t st) {
+  if (C == 16)
+    hipLaunchKernelGGL(k_head_bwd_data16, dim3(nblk(P, 256)), dim3(256), 0, st, dout, w, x, dx, P);
+  else
+    hipLaunchKernelGGL(k_head_bwd_data, dim3(nblk(P * C, 256)), dim3(256), 0, st, dout, w, x, dx, P, C);
+}
+
 // ---- layer launchers (arguments validated by the callers) ----
+constexpr size_t kTileLdsMax = 64 * 1024;
+
+// Tile shape of k_conv3x3_tile for this layer, largest first; false if none fits.
+bool tile_shape(int W, int Cin, int NB, int* R, int* TW, int* GW) {
+  if (Cin % 8 || W % 16) return false;
+  static const int cand[][3] = {{4, 64, 4}, {2, 64, 2}, {4, 32, 2}, {2, 32, 1}, {1, 64, 1}, {4, 16, 1}};
+  for (const auto& c : cand) {
+    if (c[1] > W && c[1] > 16) continue;
+    const size_t lds = ((size_t)(c[0] + 2) * (c[1] + 2) * tile_pixel_stride(Cin) + (size_t)c[0] * c[1] * 16 * NB) * 2;
+    if (lds > kTileLdsMax) continue;
+    *R = c[0];
+    *TW = c[1];
+    *GW = c[2];
+    return true;
+  }
+  return false;
+}
+
+template <int NB>
+void conv_tile_launch(int GW, dim3 grid, size_t lds, hipStream_t st, const u16* X, const u16* Wg, const float* bias,
+                      const u16* mask, u16* Y, int H, int W, int Cin, int Cout, int Kp, int relu, int TW, int R) {
+  if (GW == 4)
+    hipLaunchKernelGGL((k_conv3x3_tile<NB, 4>), grid, dim3(256), lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout, Kp,
+                       relu, TW, R);
+  else if (GW == 2)
+    hipLaunchKernelGGL((k_conv3x3_tile<NB, 2>), grid, dim3(256), lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout, Kp,
+                       relu, TW, R);
+  else
+    hipLaunchKernelGGL((k_conv3x3_tile<NB, 1>), grid, dim3(256), lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout, Kp,
+                       relu, TW, R);
+}
+
 void conv_launch(const u16* X, const u16* Wg, const float* bias, const u16* mask, u16* Y, long P, int H, int W,
                  int Cin, int Cout, int relu, hipStream_t st) {
   const int nb16 = Cout / 16;
   const int NB = nb16 % 4 == 0 ? 4 : nb16 % 3 == 0 ? 3 : nb16 % 2 == 0 ? 2 : 1;
+  int R, TW, GW;
+  if (tile_shape(W, Cin, NB, &R, &TW, &GW)) {
+    const long N = P / ((long)H * W);
+    const long tiles = N * (H / R + (H % R ? 1 : 0)) * (W / TW + (W % TW ? 1 : 0));
+    const dim3 grid((unsigned)tiles, nb16 / NB);
+    const size_t lds = ((size_t)(R + 2) * (TW + 2) * tile_pixel_stride(Cin) + (size_t)R * TW * 16 * NB) * 2;
+    const int Kp = kpad_of(9 * Cin);
+    switch (NB) {
+      case 4: conv_tile_launch<4>(GW, grid, lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout, Kp, relu, TW, R); break;
+      case 3: conv_tile_launch<3>(GW, grid, lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout, Kp, relu, TW, R); break;
+      case 2: conv_tile_launch<2>(GW, grid, lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout, Kp, relu, TW, R); break;
+      default: conv_tile_launch<1>(GW, grid, lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout, Kp, relu, TW, R); break;
+    }
+    return;
+  }
+  if (Cin == 1 && Cout == 16) {
+    hipLaunchKernelGGL(k_conv_first16, dim3(nblk(P, 256)), dim3(256), 0, st, X, Wg, bias, mask, Y, P, H, W,
+                       kpad_of(9), relu);
+    return;
+  }
   const dim3 grid(nblk(P, 64), nb16 / NB);
   const bool vec = (Cin % 8) == 0;
   const int Kp = kpad_of(9 * Cin);
@@ -815,9 +1249,7 @@ hg_status hg_nn_avgpool2(const void* x, void* y, int n, int h, int w, int c, voi
   clear_error();
   if (!x || !y || n < 1 || h < 2 || w < 2 || ((h | w) & 1) || c < 1)
     return nn_fail(HG_ERR_INVALID_ARG, "avgpool2: NULL buffer or odd/small size");
-  const long cnt = (long)n * (h / 2) * (w / 2) * c;
-  hipLaunchKernelGGL(k_avgpool2, dim3(nblk(cnt, 256)), dim3(256), 0, (hipStream_t)stream, (const u16*)x, (u16*)y, n,
-                     h, w, c);
+  pool_launch((const u16*)x, (u16*)y, n, h, w, c, (hipStream_t)stream);
   return nn_launch_status();
 }
 
@@ -826,9 +1258,7 @@ hg_status hg_nn_avgpool2_backward(const void* dy, const void* dskip, const void*
   clear_error();
   if (!dy || !dx || n < 1 || h < 2 || w < 2 || ((h | w) & 1) || c < 1)
     return nn_fail(HG_ERR_INVALID_ARG, "avgpool2_backward: NULL buffer or odd/small size");
-  const long cnt = (long)n * h * w * c;
-  hipLaunchKernelGGL(k_avgpool2_bwd, dim3(nblk(cnt, 256)), dim3(256), 0, (hipStream_t)stream, (const u16*)dy,
-                     (const u16*)dskip, (const u16*)mask, (u16*)dx, n, h, w, c);
+  pool_bwd_launch((const u16*)dy, (const u16*)dskip, (const u16*)mask, (u16*)dx, n, h, w, c, (hipStream_t)stream);
   return nn_launch_status();
 }
 
@@ -837,9 +1267,7 @@ hg_status hg_nn_upsample_concat(const void* lo, const void* skip, void* out, int
   clear_error();
   if (!lo || !skip || !out || n < 1 || h < 2 || w < 2 || ((h | w) & 1) || c1 < 1 || c2 < 1)
     return nn_fail(HG_ERR_INVALID_ARG, "upsample_concat: NULL buffer or bad size");
-  const long cnt = (long)n * h * w * (c1 + c2);
-  hipLaunchKernelGGL(k_upcat, dim3(nblk(cnt, 256)), dim3(256), 0, (hipStream_t)stream, (const u16*)lo,
-                     (const u16*)skip, (u16*)out, n, h, w, c1, c2);
+  upcat_launch((const u16*)lo, (const u16*)skip, (u16*)out, n, h, w, c1, c2, (hipStream_t)stream);
   return nn_launch_status();
 }
 
@@ -848,17 +1276,15 @@ hg_status hg_nn_upsample_concat_backward(const void* dout, const void* mask_lo, 
   clear_error();
   if (!dout || !dlo || !dskip || n < 1 || h < 2 || w < 2 || ((h | w) & 1) || c1 < 1 || c2 < 1)
     return nn_fail(HG_ERR_INVALID_ARG, "upsample_concat_backward: NULL buffer or bad size");
-  const long cnt = (long)n * (h / 2) * (w / 2) * c1 + (long)n * h * w * c2;
-  hipLaunchKernelGGL(k_upcat_bwd, dim3(nblk(cnt, 256)), dim3(256), 0, (hipStream_t)stream, (const u16*)dout,
-                     (const u16*)mask_lo, (u16*)dlo, (u16*)dskip, n, h, w, c1, c2);
+  upcat_bwd_launch((const u16*)dout, (const u16*)mask_lo, (u16*)dlo, (u16*)dskip, n, h, w, c1, c2,
+                   (hipStream_t)stream);
   return nn_launch_status();
 }
 
 hg_status hg_nn_head(const void* x, const float* w, const float* b, float* out, long pixels, int c, void* stream) {
   clear_error();
   if (!x || !w || !b || !out || pixels < 1 || c < 1) return nn_fail(HG_ERR_INVALID_ARG, "head: NULL buffer or size");
-  hipLaunchKernelGGL(k_head, dim3(nblk(pixels, 256)), dim3(256), 0, (hipStream_t)stream, (const u16*)x, w, b, out,
-                     pixels, c);
+  head_launch((const u16*)x, w, b, out, pixels, c, (hipStream_t)stream);
   return nn_launch_status();
 }
 
@@ -894,8 +1320,7 @@ hg_status hg_nn_head_backward(const float* dout, const float* w, const void* x, 
   if (s != HG_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   float* part = (float*)ws;
-  hipLaunchKernelGGL(k_head_bwd_data, dim3(nblk(pixels * c, 256)), dim3(256), 0, st, dout, w, (const u16*)x, (u16*)dx,
-                     pixels, c);
+  head_bwd_launch(dout, w, (const u16*)x, (u16*)dx, pixels, c, st);
   head_wgrad_launch(dout, (const u16*)x, part, pixels, c, kHeadParts, st);
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, part, dwb, kHeadParts, 2 * c + 2);
   return nn_launch_status();
@@ -954,9 +1379,7 @@ hg_status hg_nn_forward(const float* params, const float* target, int batch, int
     conv(2 * l, cur);
     conv(2 * l + 1, A(p.act[2 * l]));
     if (l < kLevels - 1) {
-      const long cnt = p.P[l + 1] * kEnc[l];
-      hipLaunchKernelGGL(k_avgpool2, dim3(nblk(cnt, 256)), dim3(256), 0, st, A(p.act[2 * l + 1]), A(p.pool[l]),
-                         batch, h >> l, w >> l, kEnc[l]);
+      pool_launch(A(p.act[2 * l + 1]), A(p.pool[l]), batch, h >> l, w >> l, kEnc[l], st);
       cur = A(p.pool[l]);
     } else {
       cur = A(p.act[2 * l + 1]);
@@ -965,15 +1388,12 @@ hg_status hg_nn_forward(const float* params, const float* target, int batch, int
   for (int l = kLevels - 2; l >= 0; --l) {
     const int ia = dec_a(l);
     const int c1 = kEnc[l + 1], c2 = kEnc[l];
-    const long cnt = p.P[l] * (c1 + c2);
-    hipLaunchKernelGGL(k_upcat, dim3(nblk(cnt, 256)), dim3(256), 0, st, cur, A(p.act[2 * l + 1]), A(p.cat[l]), batch,
-                       h >> l, w >> l, c1, c2);
+    upcat_launch(cur, A(p.act[2 * l + 1]), A(p.cat[l]), batch, h >> l, w >> l, c1, c2, st);
     conv(ia, A(p.cat[l]));
     conv(ia + 1, A(p.act[ia]));
     cur = A(p.act[ia + 1]);
   }
-  hipLaunchKernelGGL(k_head, dim3(nblk(p.P[0], 256)), dim3(256), 0, st, cur, params + n.L[HEAD].w,
-                     params + n.L[HEAD].b, out, p.P[0], n.L[HEAD].cin);
+  head_launch(cur, params + n.L[HEAD].w, params + n.L[HEAD].b, out, p.P[0], n.L[HEAD].cin, st);
   return nn_launch_status();
 }
 
@@ -1015,8 +1435,7 @@ hg_status hg_nn_backward(const float* params, const float* out, const hg_complex
   u16* dh = G();
   {
     float* part = reinterpret_cast<float*>(scratch);
-    hipLaunchKernelGGL(k_head_bwd_data, dim3(nblk(p.P[0] * c0, 256)), dim3(256), 0, st, dout, params + n.L[HEAD].w,
-                       A(p.act[D0B]), dh, p.P[0], c0);
+    head_bwd_launch(dout, params + n.L[HEAD].w, A(p.act[D0B]), dh, p.P[0], c0, st);
     head_wgrad_launch(dout, A(p.act[D0B]), part, p.P[0], c0, kHeadParts, st);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, part, grads + n.L[HEAD].w, kHeadParts, 2 * c0 + 2);
   }
@@ -1039,9 +1458,7 @@ hg_status hg_nn_backward(const float* params, const float* out, const hg_complex
     const int c1 = kEnc[l + 1], c2 = kEnc[l];
     const u16* lower = l + 1 < kLevels - 1 ? A(p.act[dec_a(l + 1) + 1]) : A(p.act[E3B]);
     u16* dlo = G();
-    const long cnt = p.P[l + 1] * c1 + p.P[l] * c2;
-    hipLaunchKernelGGL(k_upcat_bwd, dim3(nblk(cnt, 256)), dim3(256), 0, st, dcat, lower, dlo, A(p.skipg[l]), batch,
-                       h >> l, w >> l, c1, c2);
+    upcat_bwd_launch(dcat, lower, dlo, A(p.skipg[l]), batch, h >> l, w >> l, c1, c2, st);
     dh = dlo;
   }
   // encoder, deepest level first; dh is the masked gradient of e{l}b's output
@@ -1049,9 +1466,7 @@ hg_status hg_nn_backward(const float* params, const float* out, const hg_complex
   for (int l = kLevels - 1; l >= 0; --l) {
     if (l < kLevels - 1) {
       u16* d = G();
-      const long cnt = p.P[l] * kEnc[l];
-      hipLaunchKernelGGL(k_avgpool2_bwd, dim3(nblk(cnt, 256)), dim3(256), 0, st, dh, A(p.skipg[l]),
-                         A(p.act[2 * l + 1]), d, batch, h >> l, w >> l, kEnc[l]);
+      pool_bwd_launch(dh, A(p.skipg[l]), A(p.act[2 * l + 1]), d, batch, h >> l, w >> l, kEnc[l], st);
       dh = d;
     }
     u16* dza = G();

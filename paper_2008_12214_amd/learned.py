@@ -184,10 +184,19 @@ def evaluate(params, targets, levels=8, refine=10, gs_iters=200, seed=7, untrain
         lev0 = B.hg_replay_phase_init(targets, levels)
         return B.hg_gs_batched(T, refine, levels, init_levels=list(lev0))
 
+    # GS from the quadratic start: the stronger reference for the network
+    t_qinit = _time(lambda: B.hg_replay_phase_init(targets, levels))
+    lev_q = B.hg_replay_phase_init(targets, levels)
+    _, nm_q = B.hg_gs_batched(T, gs_iters, levels, init_levels=list(lev_q))
+    curves_q = torch.stack(nm_q).cpu().numpy()
+
     res = {"targets": K, "size": h, "levels": levels, "refine_iters": refine, "gs_iters": gs_iters,
-           "gs_ms_per_iter_batch": slope, "gs_ms_setup_batch": icpt}
+           "gs_ms_per_iter_batch": slope, "gs_ms_setup_batch": icpt,
+           "gs_nmse_median_at": {str(k): float(np.median(curves[:, k])) for k in (10, 50, 100, gs_iters)}}
     t_fwd = _time(lambda: B.hg_nn_forward(params, targets, ws))
     res["forward_ms_batch"] = t_fwd
+    res["quadratic_init_ms_batch"] = t_qinit
+    res["quadratic_gs_nmse_median_at"] = {str(k): float(np.median(curves_q[:, k])) for k in (10, 50, 100, gs_iters)}
     # how well the phase itself is predicted: network vs zero residual (the quadratic start)
     labels, _ = make_labels(targets, levels)
     out = B.hg_nn_forward(params, targets, ws)
@@ -215,6 +224,12 @@ def evaluate(params, targets, levels=8, refine=10, gs_iters=200, seed=7, untrain
                 kstar.append(None)
                 gain.append((icpt + slope * gs_iters) / t_path)  # lower bound: GS never got there
         reached = [k is not None for k in kstar]
+        kq, gain_q = [], []
+        for i in range(K):
+            hit = np.nonzero(curves_q[i] <= final[i])[0]
+            k = int(hit[0]) if hit.size else gs_iters
+            kq.append(k if hit.size else None)
+            gain_q.append((t_qinit + icpt + slope * k) / t_path)
         res[name] = {
             "path_ms_batch": t_path,
             "final_nmse_median": float(np.median(final)),
@@ -223,6 +238,10 @@ def evaluate(params, targets, levels=8, refine=10, gs_iters=200, seed=7, untrain
             "gs_reached_fraction": float(np.mean(reached)),
             "time_gain_median": float(np.median(gain)),
             "win_fraction": float(np.mean(np.array(gain) > 1.0)),
+            "quadratic_gs_kstar_median": float(np.median([k for k in kq if k is not None]))
+            if any(k is not None for k in kq) else None,
+            "quadratic_gs_reached_fraction": float(np.mean([k is not None for k in kq])),
+            "time_gain_vs_quadratic_gs_median": float(np.median(gain_q)),
         }
         log(name, json.dumps(res[name]))
     return res

@@ -61,12 +61,22 @@ def rng_bf(rng, shape, scale=1.0):
 
 
 CONV_CASES = [  # n, h, w, cin, cout, bias/relu, mask
+    # direct-gather kernel (width not a multiple of 16, or cin not of 8)
     (2, 16, 24, 16, 16, True, False),
-    (1, 7, 9, 1, 16, True, False),     # 63 pixels: ragged tail, scalar gather
+    (1, 7, 9, 1, 16, True, False),     # first layer: one input channel
+    (2, 5, 7, 1, 16, False, True),
+    (1, 7, 9, 3, 16, True, False),     # 63 pixels: ragged tail, scalar gather
     (2, 12, 20, 48, 48, False, True),  # three 16-channel groups per wave
     (1, 8, 8, 128, 128, True, False),
     (1, 9, 13, 192, 64, False, False),
     (3, 5, 6, 32, 96, True, True),
+    # LDS-tiled kernel: full and partial row/column tiles, every tile shape
+    (2, 9, 64, 16, 16, True, False),    # 4 x 64 tiles, ragged last tile row
+    (1, 6, 48, 48, 48, False, True),    # 32-wide tiles, partial last column tile
+    (2, 5, 128, 96, 32, True, False),   # 2 x 64 tiles
+    (1, 4, 32, 192, 64, True, True),    # 2 x 32 tiles
+    (1, 3, 16, 128, 128, False, False),  # 4 x 16 tiles
+    (1, 7, 80, 64, 64, True, False),
 ]
 
 
@@ -89,7 +99,8 @@ def test_conv3x3_forward(n, h, w, cin, cout, affine, masked):
     assert_bf16_close(host(y), ref, "conv3x3")
 
 
-@pytest.mark.parametrize("n,h,w,cin,cout", [(2, 10, 12, 16, 32), (1, 6, 7, 48, 16), (2, 4, 8, 128, 64)])
+@pytest.mark.parametrize("n,h,w,cin,cout", [(2, 10, 12, 16, 32), (1, 6, 7, 48, 16), (2, 4, 8, 128, 64),
+                                            (2, 6, 64, 48, 16), (1, 5, 32, 192, 64)])
 def test_conv3x3_data_gradient(n, h, w, cin, cout):
     say("conv3x3 data gradient", n, h, w, cin, cout)
     rng = np.random.default_rng(7 + cin)
@@ -117,10 +128,11 @@ def test_conv3x3_weight_gradient(n, h, w, cin, cout):
         assert err < 1e-4, what
 
 
-def test_pool_upsample_and_adjoints_bit_exact():
-    say("pool / upsample / adjoints")
+@pytest.mark.parametrize("c1,c2", [(32, 16), (20, 12)])  # 16-byte and scalar kernels
+def test_pool_upsample_and_adjoints_bit_exact(c1, c2):
+    say("pool / upsample / adjoints", c1, c2)
     rng = np.random.default_rng(21)
-    n, h, w, c1, c2 = 2, 12, 20, 32, 16
+    n, h, w = 2, 12, 20
     x = rng_bf(rng, (n, h, w, c2))
     np.testing.assert_array_equal(host(hg.hg_nn_avgpool2(bf(x))), nn.bf16(nn.avgpool2(x)))
     dy = rng_bf(rng, (n, h // 2, w // 2, c2))
@@ -139,10 +151,11 @@ def test_pool_upsample_and_adjoints_bit_exact():
     np.testing.assert_array_equal(host(dsk), dcat[..., c1:])
 
 
-def test_head_loss_and_head_backward():
-    say("head / loss / head backward")
+@pytest.mark.parametrize("c", [16, 12])  # 16-channel kernels and the generic ones
+def test_head_loss_and_head_backward(c):
+    say("head / loss / head backward", c)
     rng = np.random.default_rng(31)
-    n, h, w, c = 3, 16, 8, 16
+    n, h, w = 3, 16, 8
     x = nn.bf16(np.maximum(rng.standard_normal((n, h, w, c)), 0))
     wt = rng.standard_normal((2, 1, 1, c)) * 0.3
     b = np.array([0.5, -0.25])
