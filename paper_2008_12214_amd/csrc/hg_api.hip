@@ -137,7 +137,7 @@ Cfg get_cfg(int ny, int nx, int B) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t desc, field, tprep, wbuf, accum, twx, twy, chirp, part, total;
+  size_t desc, field, tprep, wbuf, accum, twx, twy, chirp, part, invm, total;
   int max_nblk, slots;
 };
 
@@ -157,6 +157,7 @@ Layout make_layout(int op, int ny, int nx, int B, int kmax) {
   L.twy = take(ny * sizeof(float2));
   L.chirp = take((size_t)B * (nx + ny) * sizeof(float2));
   L.part = take((size_t)B * L.slots * L.max_nblk * 4 * sizeof(double));
+  L.invm = take((size_t)B * sizeof(float));
   L.total = o;
   return L;
 }
@@ -259,6 +260,7 @@ Batch make_batch(void* ws, const Layout& L, int ny, int nx, int C) {
   bt.tw_y = ny != nx ? at<float2>(ws, L.twy) : bt.tw_x;
   bt.chirp = at<float2>(ws, L.chirp);
   bt.part = at<double>(ws, L.part);
+  bt.invm = at<float>(ws, L.invm);
   bt.ny = ny;
   bt.nx = nx;
   bt.nblk = nx / C;

@@ -163,8 +163,8 @@ __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
 // One Stockham stage S and, recursively, the following ones.
 //   Ex: LDS exchange policy with before_read(), before_write(), and
 //       ld(e) / st(e, v) on padded element index e.
-template <int N, int E, int DIR, int S, class Ex>
-__device__ __forceinline__ void fft_stage(float2 (&v)[E], int t, const float2* __restrict__ tw, Ex& ex) {
+template <int N, int E, int DIR, int S, class Ex, class TWP>
+__device__ __forceinline__ void fft_stage(float2 (&v)[E], int t, TWP tw, Ex& ex) {
   using P = Plan<N, E>;
   constexpr int R = P::radix(S), p = P::stride(S), T = P::T, M = E / R;
   constexpr bool last = (S == P::ns - 1);
@@ -188,7 +188,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], int t, const float2* _
     for (int r = 0; r < R; ++r) a[r] = v[m + r * M];
     if constexpr (p > 1) {
       constexpr int kTwOff = TwLayout<N, E>::twoff(S);
-      const float2* w = tw + kTwOff + k * (R - 1);
+      const auto w = tw + kTwOff + k * (R - 1);
 #pragma unroll
       for (int r = 1; r < R; ++r) a[r] = twmul<DIR>(a[r], w[r - 1]);
     }
@@ -238,6 +238,18 @@ template <class T> __device__ __forceinline__ gptr<T> launder(gptr<T> p) {
 template <int N, int E, int DIR, class Ex>
 __device__ __forceinline__ void fft(float2 (&v)[E], int t, const float2* __restrict__ tw, Ex& ex) {
   fft_stage<N, E, DIR, 0>(v, t, launder(tw), ex);
+}
+
+// LDS-resident twiddles (kept in the LDS address space so no table read
+// becomes a flat or global access).
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T> using lptr = __attribute__((address_space(3))) T*;
+#else
+template <class T> using lptr = T*;
+#endif
+template <int N, int E, int DIR, class Ex>
+__device__ __forceinline__ void fft_lds(float2 (&v)[E], int t, lptr<const float2> tw, Ex& ex) {
+  fft_stage<N, E, DIR, 0>(v, t, tw, ex);
 }
 
 // ---------------------------------------------------------------------------

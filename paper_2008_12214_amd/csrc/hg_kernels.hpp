@@ -49,6 +49,7 @@ struct Batch {
   const float2* tw_y;   // staged twiddle table for length ny
   const float2* chirp;  // [B][nx + ny]: cx[x] (-1)^x, then cy[y] (-1)^y
   double* part;         // [B][slots][nblk][4] partial sums
+  float* invm;          // [B] weighted GS: 1 / m_{k-1} of the current column pass
   int ny, nx;
   int nblk;             // column tiles per problem (= nx / C)
   int slots;            // partial slots per problem
@@ -180,12 +181,12 @@ __device__ __forceinline__ double slot_total(const Batch& bt, int b, int slot, i
 // ---------------------------------------------------------------------------
 // Staged twiddles of a length-N transform: stage s, butterfly class k,
 // r = 1..R-1 -> exp(-2 pi i r k / (p R)).  Stages are walked at compile time.
-template <int N, int S>
+template <int N, int S, int E = kE>
 __device__ __forceinline__ void twiddle_entry(float2* tw, int m) {
-  using P = Plan<N, kE>;
+  using P = Plan<N, E>;
   if constexpr (S < P::ns) {
     constexpr int R = P::radix(S), p = P::stride(S);
-    constexpr int off = TwLayout<N, kE>::twoff(S), sz = TwLayout<N, kE>::size_of(S);
+    constexpr int off = TwLayout<N, E>::twoff(S), sz = TwLayout<N, E>::size_of(S);
     if (m >= off && m < off + sz) {
       const int k = (m - off) / (R - 1), r = (m - off) % (R - 1) + 1;
       double sn, cs;
@@ -193,7 +194,7 @@ __device__ __forceinline__ void twiddle_entry(float2* tw, int m) {
       tw[m] = make_float2((float)cs, (float)-sn);
       return;
     }
-    twiddle_entry<N, S + 1>(tw, m);
+    twiddle_entry<N, S + 1, E>(tw, m);
   }
 }
 
@@ -785,6 +786,272 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < E; ++i) fld[(size_t)(r0 + T * i) * NX + u] = mine[lds_pad(r0 + T * i)];
+}
+
+// ---------------------------------------------------------------------------
+// Persistent, software-pipelined column pass for GS / weighted GS.
+//
+// A resident grid of workgroups walks the column tiles of the whole batch.
+// While a workgroup transforms tile i, the field, target and weight columns
+// of its tile i + 1 stream into a second LDS stage with direct-to-LDS loads
+// (global_load_lds_dwordx4: 16 bytes per lane, no registers held), so HBM
+// traffic never waits for the transforms.  Everything the transforms touch
+// lives in LDS (stages, twiddles) and the only global accesses during the
+// compute phase are stores, so nothing waits on the in-flight prefetch until
+// the tile's end.  The two stages are distinct arrays and the loop is
+// unrolled by two, so every LDS access names its stage statically.
+//
+// Tile order: tiles that share 128-byte lines (16 / C of them) are handed,
+// in the same step, to workgroups on the same XCD (workgroups are dispatched
+// round-robin over the 8 XCDs), so each line is fetched into one L2 once.
+// ---------------------------------------------------------------------------
+// Workgroup barrier that orders LDS traffic only: waits for this wave's LDS
+// operations, then s_barrier.  The fenced __syncthreads() would also wait for
+// the in-flight direct-to-LDS prefetch (counted by vmcnt), which is exactly
+// what the pipelined pass must not do.  The memory clobber keeps the compiler
+// from moving memory operations across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// ColEx<C, false> with LDS-only barriers.
+template <int C> struct ColExL {
+  float2* s;
+  __device__ void before_read() { lds_barrier(); }
+  __device__ void before_write() { lds_barrier(); }
+  __device__ float2 ld(int e) const { return s[e * C]; }
+  __device__ void st(int e, float2 v) { s[e * C] = v; }
+};
+
+// block_sum4 with LDS-only barriers.
+template <int NT>
+__device__ __forceinline__ void block_sum4_l(float a0, float a1, float a2, float a3, double (&red)[kMaxWaves][4],
+                                             double (&tot)[4]) {
+  constexpr int NW = (NT + 63) / 64;
+  const double d0 = wave_sum((double)a0), d1 = wave_sum((double)a1);
+  const double d2 = wave_sum((double)a2), d3 = wave_sum((double)a3);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  lds_barrier();
+  if (lane == 0) { red[wv][0] = d0; red[wv][1] = d1; red[wv][2] = d2; red[wv][3] = d3; }
+  lds_barrier();
+  if (threadIdx.x < 4) {
+    double acc = 0.0;
+    for (int w = 0; w < NW; ++w) acc += red[w][threadIdx.x];
+    tot[threadIdx.x] = acc;
+  }
+  lds_barrier();
+}
+
+// Make a uniform value available (loaded) at this point: later memory
+// operations are not hoisted above it and the value is not re-loaded later.
+__device__ __forceinline__ int pin_uniform(int x) {
+  x = __builtin_amdgcn_readfirstlane(x);
+  asm volatile("" : "+s"(x)::"memory");
+  return x;
+}
+__device__ __forceinline__ const float* pin_uniform_ptr(const float* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  asm volatile("" : "+s"(lo), "+s"(hi)::"memory");
+  return reinterpret_cast<const float*>(((uint64_t)hi << 32) | lo);
+}
+
+// Elements per thread of the pipelined transforms (the 16 of every other
+// pass; an 8-element variant with 512-thread workgroups is compiled for
+// comparison, HG_COLP_E=8).
+constexpr int kColpE = 16;
+
+template <int NY, int C, int E = kColpE>
+struct ColpShape {
+  static constexpr int T = NY / E, NT = C * T;
+  static constexpr int FE = (NY + NY / 16) * C;  // float2: padded exchange tile (unpadded fill first)
+  static constexpr int TWN = TwLayout<NY, E>::total();
+  static constexpr int G = C >= 16 ? 1 : 16 / C;  // tiles sharing a 128-byte line
+};
+
+template <int NY, int C, int E = kColpE>
+__host__ __device__ constexpr int colp_lds_bytes() {
+  using S = ColpShape<NY, C, E>;
+  return 2 * S::FE * 8 + S::TWN * 8 + (kMaxWaves * 4 + 5) * 8;
+}
+// Compiled tile shapes (C columns of NY rows) of the pipelined pass.
+__host__ __device__ constexpr bool colp_ok(int NY, int C) {
+  return (NY == 1024 && C == 4) || (NY == 512 && C == 8) || (NY == 256 && C == 16);
+}
+
+#if defined(__HIP_DEVICE_COMPILE__)
+#define HG_AS1(p) ((const __attribute__((address_space(1))) void*)(p))
+#define HG_AS3(p) ((__attribute__((address_space(3))) void*)(p))
+#else
+#define HG_AS1(p) ((const void*)(p))
+#define HG_AS3(p) ((void*)(p))
+#endif
+
+// Issue the direct-to-LDS loads of tile vt's field columns (16-byte chunks,
+// C / 2 per row) into F in [row][c] order.  Each wave instruction fills 64
+// consecutive chunks (1 KB of LDS from a wave-uniform base).
+template <int NY, int C, int E>
+__device__ __forceinline__ void colp_prefetch(const Batch& bt, int vt, int tpp, float2* F) {
+  using S = ColpShape<NY, C, E>;
+  constexpr int NW = S::NT / 64, FPR = C / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int b = vt / tpp, blk = vt - b * tpp;
+  const int NX = bt.nx;
+  const float2* src = bt.field + (size_t)b * NY * NX + (size_t)blk * C;
+#pragma unroll
+  for (int q = 0; q < NY * FPR / S::NT; ++q) {
+    const int base = (q * NW + wave) * 64;
+    const int ch = base + lane;
+    const int row = ch / FPR, part = ch - row * FPR;
+    __builtin_amdgcn_global_load_lds(HG_AS1(src + (size_t)row * NX + 2 * part), HG_AS3(F + 2 * base), 16, 0, 0);
+  }
+}
+
+// Register-held per-tile inputs: activity, 1/m, the weight array, target
+// and weight columns.
+template <int E> struct ColpIn {
+  int active;
+  float inv_m;
+  float* wout;
+  float tv[E], wv[E];
+};
+
+// Load tile vt's inputs.  Issued at the end of the previous tile, after its
+// stores, so these loads and that tile's prefetch complete under one wait.
+template <int NY, int C, int MODE, int E>
+__device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int tpp, ColpIn<E>& in) {
+  constexpr int T = NY / E;
+  const int b = vt / tpp, blk = vt - b * tpp;
+  const Desc& d = bt.desc[b];
+  in.active = d.iters >= k;
+  if (!in.active) return;
+  const int c = threadIdx.x % C, t = threadIdx.x / C;
+  const int u = blk * C + c;
+  const int NX = bt.nx;
+  const size_t off = (size_t)b * NY * NX;
+  gptr<const float> tp = to_global(bt.tprep + off);
+#pragma unroll
+  for (int j = 0; j < E; ++j) in.tv[j] = tp[(size_t)(t + T * j) * NX + u];
+  if constexpr (MODE == COL_WGS) {
+    in.inv_m = bt.invm[b];
+    in.wout = d.user_weights ? d.weights : bt.wbuf + off;
+    gptr<const float> w = to_global(in.wout);
+    if (part_ptr(bt, b, bt.slots - 1, blk)[1] > 0.0) {  // the tile meets the support
+#pragma unroll
+      for (int j = 0; j < E; ++j) in.wv[j] = w[(size_t)(t + T * j) * NX + u];
+    }
+  }
+}
+
+// One tile: transform the field in stage Fc with the register-held inputs
+// while tile vtn's field streams into Fn; then load tile vtn's inputs and
+// wait for everything (each wave for its own loads) before the barrier.
+template <int NY, int C, int MODE, int E>
+__device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vtn, int total, int tpp,
+                                          float2* __restrict__ Fc, float2* __restrict__ Fn, lptr<const float2> tw,
+                                          double (&red)[kMaxWaves][4], double (&tot)[4], ColpIn<E>& in) {
+  using S = ColpShape<NY, C, E>;
+  constexpr int T = S::T, NT = S::NT;
+  constexpr bool WGS = MODE == COL_WGS;
+  if (vtn < total) colp_prefetch<NY, C, E>(bt, vtn, tpp, Fn);
+  if (in.active) {
+    const int b = vt / tpp, blk = vt - b * tpp;
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int u = blk * C + c;
+    const int NX = bt.nx;
+    const size_t off = (size_t)b * NY * NX;
+    float2 v[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = Fc[(t + T * j) * C + c];
+    ColExL<C> ex{Fc + c};
+    fft_lds<NY, E, -1>(v, t, tw, ex);
+    float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f, s_w = 0.f;
+    gptr<float> w = nullptr;
+    if constexpr (WGS) w = to_global(in.wout);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int row = t + T * j;
+      const float2 Rr = v[j];  // unscaled replay, centred index (row, u)
+      const float a2 = Rr.x * Rr.x + Rr.y * Rr.y;
+      const float inv = a2 > 0.f ? __builtin_amdgcn_rsqf(a2) : 0.f;
+      const float A = a2 * inv * bt.fwd_scale;
+      const float Tv = in.tv[j];
+      s_ta += Tv * A;
+      s_aa += A * A;
+      s_tt += Tv * Tv;
+      float amp = Tv;
+      if constexpr (WGS) {
+        if (Tv > 0.f) {
+          const float ratio = fmaxf(Tv, kWgsEps) * __builtin_amdgcn_rcpf(fmaxf(A, kWgsEps));
+          const float wc = fminf(fmaxf(in.wv[j] * ratio * in.inv_m, kWMin), kWMax);
+          const float wn = __builtin_amdgcn_exp2f(kWgsGamma * __builtin_amdgcn_logf(wc));
+          w[(size_t)row * NX + u] = wn;
+          s_w += wn;
+          amp = wn * Tv;
+        }
+      }
+      v[j] = a2 > 0.f ? cscale(Rr, amp * inv) : make_float2(amp, 0.f);
+    }
+    block_sum4_l<NT>(s_ta, s_aa, s_tt, s_w, red, tot);
+    if (threadIdx.x == 0) {
+      double* pp = part_ptr(bt, b, k - 1, blk);
+      pp[0] = tot[0]; pp[1] = tot[1]; pp[2] = tot[2];
+      if (WGS) part_ptr(bt, b, k, blk)[3] = tot[3];
+    }
+    fft_lds<NY, E, +1>(v, t, tw, ex);
+    gptr<float2> fld = to_global(bt.field + off);
+#pragma unroll
+    for (int j = 0; j < E; ++j) fld[(size_t)(t + T * j) * NX + u] = v[j];
+  }
+  if (vtn < total) colp_load_in<NY, C, MODE, E>(bt, k, vtn, tpp, in);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
+template <int NY, int C, int MODE, int E = kColpE>
+__global__ __launch_bounds__(C * (NY / E))
+void k_colp(Batch bt, int k, int nprob) {
+  using S = ColpShape<NY, C, E>;
+  static_assert(S::NT <= 1024 && S::NT % 64 == 0 && C >= 4, "pipelined column tile shape");
+  static_assert(2 * colp_lds_bytes<NY, C, E>() <= 160 * 1024, "two workgroups' stages must fit in LDS");
+  __shared__ float2 FA[S::FE], FB[S::FE];
+  __shared__ float2 TW[S::TWN];
+  __shared__ double red[kMaxWaves][4];
+  __shared__ double tot[4];
+  // twiddles of this plan, FP64-evaluated into LDS
+  for (int i = threadIdx.x; i < S::TWN; i += S::NT) twiddle_entry<NY, 1, E>(TW, i);
+  const int tpp = bt.nx / C, total = tpp * nprob;
+  const int NBK = gridDim.x;  // a multiple of 8 G
+  const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+  const int slot = ((j / S::G) * 8 + xcd) * S::G + (j % S::G);
+  int vt = slot;
+  ColpIn<E> in;
+  if (vt < total) {
+    colp_prefetch<NY, C, E>(bt, vt, tpp, FA);
+    colp_load_in<NY, C, MODE, E>(bt, k, vt, tpp, in);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const lptr<const float2> tw = (lptr<const float2>)TW;
+  while (vt < total) {
+    colp_tile<NY, C, MODE, E>(bt, k, vt, vt + NBK, total, tpp, FA, FB, tw, red, tot, in);
+    vt += NBK;
+    if (vt >= total) break;
+    colp_tile<NY, C, MODE, E>(bt, k, vt, vt + NBK, total, tpp, FB, FA, tw, red, tot, in);
+    vt += NBK;
+  }
+}
+
+// 1 / m_{k-1} of every problem for the pipelined weighted-GS column pass k:
+// the same fixed-order sums as slot_total.
+static __global__ __launch_bounds__(64) void k_wgs_invm(Batch bt, int k) {
+  const int b = blockIdx.x;
+  double om = 0.0, ws = 0.0;
+  for (int i = threadIdx.x; i < bt.nblk; i += 64) {
+    om += part_ptr(bt, b, bt.slots - 1, i)[1];
+    ws += part_ptr(bt, b, k - 1, i)[3];
+  }
+  om = wave_sum(om);
+  ws = wave_sum(ws);
+  if (threadIdx.x == 0) bt.invm[b] = (float)((om > 0.0 ? om : 1.0) / ws);
 }
 
 // nmse[k] = 1 - sta^2 / (stt saa) from the block partials of slot k; a GS

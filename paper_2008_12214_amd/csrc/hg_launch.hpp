@@ -2,6 +2,10 @@
 // and the launchers that pick one at run time.  Each length lives in its own
 // translation unit (hg_n<N>.hip) so the kernels build in parallel.
 #pragma once
+#include <algorithm>
+#include <cstdlib>
+#include <string>
+
 #include "hg_kernels.hpp"
 
 namespace hg {
@@ -24,6 +28,26 @@ __host__ __device__ constexpr bool col_ok(int N, int C) {
 __host__ __device__ constexpr bool rpb_ok(int N, int RPB) {
   const int T = N / kE;
   return (RPB * T == 128 || RPB * T == 256) || (T >= 256 && RPB == 1);
+}
+
+// The persistent pipelined column pass (k_colp) runs GS / weighted GS column
+// passes where it is compiled; HG_COLUMN_KERNEL=classic selects the
+// one-tile-per-workgroup kernels instead (for comparison).
+inline bool colp_enabled() {
+  static const int on = [] {
+    const char* e = std::getenv("HG_COLUMN_KERNEL");
+    return (e && std::string(e) == "classic") ? 0 : 1;
+  }();
+  return on != 0;
+}
+
+// Elements per thread of the pipelined pass (HG_COLP_E=8 for comparison).
+inline int colp_elements() {
+  static const int e = [] {
+    const char* v = std::getenv("HG_COLP_E");
+    return (v && std::string(v) == "8") ? 8 : kColpE;
+  }();
+  return e;
 }
 
 template <int N> void launch_col_t(int C, const Batch& bt, int B, int mode, int arg, int adaptive,
