@@ -226,7 +226,7 @@ def main():
                    "slm_levels": LEVELS, "target": "gaussian sum, 32 blobs, central window"},
         "roofline": {"bound": "hbm", "achieved": round(col_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(col_gbs / HBM_PEAK_GBS, 4), "traffic": committed_traffic(B),
-                     "kernel": "column pass k_col<1024,C,COL_WGS> (weighted GS)",
+                     "kernel": "column pass of weighted GS (persistent pipelined k_colp<1024,4,COL_WGS>)",
                      "bytes_per_launch": int(col_bytes / kt["col_launches"]),
                      "bytes_per_px": round(col_px_bytes, 3), "support_fraction": round(omega, 4),
                      "avg_launch_us": round(col_avg_ms * 1e3, 2)},

@@ -244,6 +244,11 @@ void launch_col(const Batch& bt, int C, int B, int mode, int arg, int adaptive, 
   });
 }
 
+void launch_col_prep(const Batch& bt, int C, int B, int mode, int arg, hipStream_t st) {
+  TimeScope ts(TC_SETUP, st);
+  with_size(bt.ny, [&](auto nc) { launch_col_prep_t<decltype(nc)::value>(C, bt, B, mode, arg, st); });
+}
+
 void launch_setup(const Batch& bt, int C, int B, int weighted, hipStream_t st) {
   TimeScope ts(TC_SETUP, st);
   with_size(bt.ny, [&](auto nc) { launch_setup_t<decltype(nc)::value>(C, bt, B, weighted, st); });
@@ -292,8 +297,13 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
   launch_row(bt, cfg.RPB, B, fresnel, lk, ROW_INIT, 0, nullptr, nullptr, st);
   const int cmode = weighted ? COL_WGS : COL_GS;
   for (int k = 1; k <= kmax; ++k) {
+    launch_col_prep(bt, cfg.C, B, cmode, k, st);
     launch_col(bt, cfg.C, B, cmode, k, 0, nullptr, nullptr, st);
     launch_row(bt, cfg.RPB, B, fresnel, lk, ROW_ITER, k, nullptr, nullptr, st);
+  }
+  if (weighted) {
+    TimeScope ts(TC_SETUP, st);
+    hipLaunchKernelGGL(k_weights_out, dim3((unsigned)(((size_t)ny * nx + 255) / 256), B), dim3(256), 0, st, bt);
   }
   // final measurement pass of every distinct iteration count in the class
   std::vector<int> ks;
@@ -658,6 +668,7 @@ hg_status hg_autotune(int ny, int nx, int batch, int* col_tile, int* rows_per_gr
     if (ny != nx) launch_twiddles(const_cast<float2*>(bt.tw_y), ny, st);
     launch_setup(bt, C, batch, 1, st);
     launch_row(bt, def.RPB, batch, false, LK_BIN, ROW_INIT, 0, nullptr, nullptr, st);
+    launch_col_prep(bt, C, batch, COL_WGS, 1, st);
     const float ms = time_ms([&] { launch_col(bt, C, batch, COL_WGS, 1, 0, nullptr, nullptr, st); });
     if (ms < best_col) { best_col = ms; best.C = C; }
   }

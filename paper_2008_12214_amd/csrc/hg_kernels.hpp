@@ -61,6 +61,17 @@ __device__ __forceinline__ double* part_ptr(const Batch& bt, int b, int slot, in
   return bt.part + (((size_t)b * bt.slots + slot) * bt.nblk + blk) * 4;
 }
 
+// Workspace planes (field, prepared target, weights, OSPR accumulator) are
+// stored in 4 x 4 tiles, tile rows in order: element (y, x) of a plane with
+// nx columns sits at tix(y, x, nx).  A tile of the field is one 128-byte
+// line, so a row pass over 4-row groups and a column pass over 4- or
+// 8-column tiles both read and write whole lines.  Caller-owned arrays
+// (targets, levels, fields, replays, weights) keep natural [y][x] order.
+// (32-bit: a plane has at most 4096^2 elements.)
+__host__ __device__ __forceinline__ uint32_t tix(int y, int x, int nx) {
+  return (((uint32_t)y >> 2) * ((uint32_t)nx >> 2) + ((uint32_t)x >> 2)) * 16u + (uint32_t)((y & 3) * 4 + (x & 3));
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
 // Give each XCD a contiguous run of column tiles so neighbouring tiles, which
 // share 128-byte lines when a tile is narrower than 16 columns, meet in the
@@ -277,7 +288,7 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_prepare(Batch bt, int weighte
   const double e = slot_total(bt, b, bt.slots - 1, 0, &bc);
   const float scale = (float)sqrt((double)bt.nx * (double)bt.ny / e);
   const size_t off = (size_t)b * bt.ny * bt.nx;
-  float* w = d.user_weights ? d.weights : bt.wbuf + off;
+  float* w = bt.wbuf + off;  // caller's weights are copied in here
   float om = 0.f, ws = 0.f;
   const int um = (bt.nx - u) & (bt.nx - 1);
 #pragma unroll
@@ -291,10 +302,11 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_prepare(Batch bt, int weighte
       tv = sqrtf(0.5f * (tv * tv + tm * tm));
     }
     tv *= scale;
-    bt.tprep[off + idx] = tv;
+    const uint32_t ti = tix(v, u, bt.nx);
+    bt.tprep[off + ti] = tv;
     if (weighted) {
-      float wv = 1.0f;
-      if (d.user_weights) wv = w[idx]; else w[idx] = 1.0f;
+      const float wv = d.user_weights ? d.weights[idx] : 1.0f;
+      w[ti] = wv;
       if (tv > 0.f) { om += 1.f; ws += wv; }
     }
   }
@@ -339,12 +351,15 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
   constexpr bool XCH = P::ns > 1;
   constexpr bool WAVE = T <= 64;  // each row inside one wave
   constexpr int NBUF = WAVE ? 1 : 2;
+  static_assert(T % 4 == 0, "a thread's elements share one column of the 4 x 4 tiles");
+  constexpr bool QSYNC = WAVE && RPB >= 4 && (RPB % 4) == 0;
   __shared__ float2 lds[XCH ? RPB * NBUF * LW : 1];
   const int b = blockIdx.y;
   const int r = threadIdx.x / T, t = threadIdx.x % T;
   const int y = blockIdx.x * RPB + r;
   const size_t off = (size_t)b * bt.ny * NX;
-  gptr<float2> row = to_global(bt.field + off + (size_t)y * NX);
+  // this row's elements in the tiled field: x at row[(x >> 2) * 16 + (x & 3)]
+  gptr<float2> row = to_global(bt.field + off + (size_t)(y >> 2) * (NX >> 2) * 16 + (y & 3) * 4);
   const float2* cx = bt.chirp + (size_t)b * (NX + bt.ny);
   const float2 cyv = FRESNEL ? cx[NX + y] : make_float2(1.f, 0.f);
   RowEx<WAVE> ex;
@@ -397,8 +412,11 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
       const bool last = (MODE == ROW_OSPR) || (arg == d.iters);
       gptr<uint8_t> lev = to_global(d.levels_out);
       if (MODE == ROW_OSPR) lev += (size_t)(arg - 1) * bt.ny * NX;
+      // The rows of a 4-row group each hold a quarter of every 128-byte tile;
+      // their waves load (and below store) in step so each line moves whole.
+      if constexpr (QSYNC) __syncthreads();
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = row[t + T * j];
+      for (int j = 0; j < E; ++j) v[j] = row[((t + T * j) >> 2) * 16 + (t & 3)];
       fft<NX, E, +1>(v, t, bt.tw_x, ex);
 #pragma unroll
       for (int j = 0; j < E; ++j) {
@@ -417,8 +435,9 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
       }
     }
     fft<NX, E, -1>(v, t, bt.tw_x, ex);
+    if constexpr (QSYNC) __syncthreads();
 #pragma unroll
-    for (int j = 0; j < E; ++j) row[t + T * j] = v[j];
+    for (int j = 0; j < E; ++j) row[((t + T * j) >> 2) * 16 + (t & 3)] = v[j];
   }
 }
 
@@ -490,20 +509,21 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
       const double om = slot_total(bt, b, bt.slots - 1, 1, &bc);
       const double wsum = slot_total(bt, b, k - 1, 3, &bc);
       inv_m = (float)((om > 0.0 ? om : 1.0) / wsum);
-      w = to_global(d.user_weights ? d.weights : bt.wbuf + off);
+      w = to_global(bt.wbuf + off);
     }
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = fld[(size_t)(t + T * j) * NX + u];
+    for (int j = 0; j < E; ++j) v[j] = fld[tix(t + T * j, u, NX)];
     fft<NY, E, -1>(v, t, bt.tw_y, ex);
     float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f, s_w = 0.f;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const size_t idx = (size_t)(t + T * j) * NX + u;
+      const size_t idx = (size_t)(t + T * j) * NX + u;  // caller arrays
+      const uint32_t ti = tix(t + T * j, u, NX);            // workspace planes
       const float2 Rr = v[j];  // unscaled replay, centred index (t + T j, u)
       const float a2 = Rr.x * Rr.x + Rr.y * Rr.y;
       const float inv = a2 > 0.f ? __builtin_amdgcn_rsqf(a2) : 0.f;
       const float A = a2 * inv * bt.fwd_scale;  // |R| of the unitary transform
-      const float Tv = tp[idx];
+      const float Tv = tp[ti];
       s_ta += Tv * A;
       s_aa += A * A;
       s_tt += Tv * Tv;
@@ -514,9 +534,9 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
         if constexpr (MODE == COL_WGS) {
           if (Tv > 0.f) {
             const float ratio = fmaxf(Tv, kWgsEps) * __builtin_amdgcn_rcpf(fmaxf(A, kWgsEps));
-            const float wc = fminf(fmaxf(w[idx] * ratio * inv_m, kWMin), kWMax);
+            const float wc = fminf(fmaxf(w[ti] * ratio * inv_m, kWMin), kWMax);
             const float wn = __builtin_amdgcn_exp2f(kWgsGamma * __builtin_amdgcn_logf(wc));
-            w[idx] = wn;
+            w[ti] = wn;
             s_w += wn;
             amp = wn * Tv;
           }
@@ -533,7 +553,7 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
     if constexpr (MODE != COL_FINAL) {
       fft<NY, E, +1>(v, t, bt.tw_y, ex);
 #pragma unroll
-      for (int j = 0; j < E; ++j) fld[(size_t)(t + T * j) * NX + u] = v[j];
+      for (int j = 0; j < E; ++j) fld[tix(t + T * j, u, NX)] = v[j];
     }
   } else {
     // OSPR.  Subframe n's column work: finish subframe n-1 (forward FFT,
@@ -545,23 +565,24 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
     gptr<float> acc = to_global(bt.accum + off);
     if constexpr (MODE != COL_OSPR_FIRST) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = fld[(size_t)(t + T * j) * NX + u];
+      for (int j = 0; j < E; ++j) v[j] = fld[tix(t + T * j, u, NX)];
       fft<NY, E, -1>(v, t, bt.tw_y, ex);
     }
     const float inv_prev = 1.0f / (float)(n - 1);
     float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const size_t idx = (size_t)(t + T * j) * NX + u;
-      const float Tv = tp[idx];
+      const size_t idx = (size_t)(t + T * j) * NX + u;  // caller arrays
+      const uint32_t ti = tix(t + T * j, u, NX);            // workspace planes
+      const float Tv = tp[ti];
       float Tn = Tv;
       if constexpr (MODE != COL_OSPR_FIRST) {
         const float2 R = cscale(v[j], bt.fwd_scale);
-        const float a = (n == 2 ? 0.f : acc[idx]) + (R.x * R.x + R.y * R.y);  // A_{n-1}
+        const float a = (n == 2 ? 0.f : acc[ti]) + (R.x * R.x + R.y * R.y);  // A_{n-1}
         if constexpr (MODE == COL_OSPR_FINAL) {
           if (d.accum_out) to_global(d.accum_out)[idx] = a;
         } else {
-          acc[idx] = a;
+          acc[ti] = a;
         }
         const float avg = a * inv_prev;
         s_ta += Tv * __builtin_amdgcn_sqrtf(avg);
@@ -591,7 +612,7 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
       }
       fft<NY, E, +1>(v, t, bt.tw_y, ex);
 #pragma unroll
-      for (int j = 0; j < E; ++j) fld[(size_t)(t + T * j) * NX + u] = v[j];
+      for (int j = 0; j < E; ++j) fld[tix(t + T * j, u, NX)] = v[j];
     }
   }
 }
@@ -659,14 +680,14 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
     const double om = slot_total(bt, b, bt.slots - 1, 1, &bc);
     const double wsum = slot_total(bt, b, k - 1, 3, &bc);
     inv_m = (float)((om > 0.0 ? om : 1.0) / wsum);
-    w = to_global(d.user_weights ? d.weights : bt.wbuf + off);
+    w = to_global(bt.wbuf + off);
   }
   float2 v[E];
 
   // A + B: forward column transform of the field
   if constexpr (MODE != COL_OSPR_FIRST) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = fld[(size_t)(r0 + T * i) * NX + u];
+    for (int i = 0; i < E; ++i) v[i] = fld[tix(r0 + T * i, u, NX)];
 #pragma unroll
     for (int i = 0; i < E; ++i) mine[lds_pad(r0 + T * i)] = v[i];
     __syncthreads();
@@ -690,12 +711,13 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int row = r0 + T * i;
-      const size_t idx = (size_t)row * NX + u;
+      const size_t idx = (size_t)row * NX + u;  // caller arrays
+      const uint32_t ti = tix(row, u, NX);        // workspace planes
       const float2 Rr = mine[lds_pad(row)];  // unscaled replay at centred index (row, u)
       const float a2 = Rr.x * Rr.x + Rr.y * Rr.y;
       const float inv = a2 > 0.f ? __builtin_amdgcn_rsqf(a2) : 0.f;
       const float A = a2 * inv * bt.fwd_scale;  // |R| of the unitary transform
-      const float Tv = tp[idx];
+      const float Tv = tp[ti];
       s_ta += Tv * A;
       s_aa += A * A;
       s_tt += Tv * Tv;
@@ -706,9 +728,9 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
         if constexpr (MODE == COL_WGS) {
           if (Tv > 0.f) {
             const float ratio = fmaxf(Tv, kWgsEps) * __builtin_amdgcn_rcpf(fmaxf(A, kWgsEps));
-            const float wc = fminf(fmaxf(w[idx] * ratio * inv_m, kWMin), kWMax);
+            const float wc = fminf(fmaxf(w[ti] * ratio * inv_m, kWMin), kWMax);
             const float wn = __builtin_amdgcn_exp2f(kWgsGamma * __builtin_amdgcn_logf(wc));
-            w[idx] = wn;
+            w[ti] = wn;
             s_w += wn;
             amp = wn * Tv;
           }
@@ -733,16 +755,17 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int row = r0 + T * i;
-      const size_t idx = (size_t)row * NX + u;
-      const float Tv = tp[idx];
+      const size_t idx = (size_t)row * NX + u;  // caller arrays
+      const uint32_t ti = tix(row, u, NX);        // workspace planes
+      const float Tv = tp[ti];
       float Tn = Tv;
       if constexpr (MODE != COL_OSPR_FIRST) {
         const float2 R = cscale(mine[lds_pad(row)], bt.fwd_scale);
-        const float a = (n == 2 ? 0.f : acc[idx]) + (R.x * R.x + R.y * R.y);  // A_{n-1}
+        const float a = (n == 2 ? 0.f : acc[ti]) + (R.x * R.x + R.y * R.y);  // A_{n-1}
         if constexpr (MODE == COL_OSPR_FINAL) {
           if (d.accum_out) to_global(d.accum_out)[idx] = a;
         } else {
-          acc[idx] = a;
+          acc[ti] = a;
         }
         const float avg = a * inv_prev;
         s_ta += Tv * __builtin_amdgcn_sqrtf(avg);
@@ -785,7 +808,7 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
   for (int j = 0; j < E; ++j) ex.s[lds_pad(tw + T * j)] = v[j];
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < E; ++i) fld[(size_t)(r0 + T * i) * NX + u] = mine[lds_pad(r0 + T * i)];
+  for (int i = 0; i < E; ++i) fld[tix(r0 + T * i, u, NX)] = mine[lds_pad(r0 + T * i)];
 }
 
 // ---------------------------------------------------------------------------
@@ -801,9 +824,10 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
 // the tile's end.  The two stages are distinct arrays and the loop is
 // unrolled by two, so every LDS access names its stage statically.
 //
-// Tile order: tiles that share 128-byte lines (16 / C of them) are handed,
-// in the same step, to workgroups on the same XCD (workgroups are dispatched
-// round-robin over the 8 XCDs), so each line is fetched into one L2 once.
+// Tile order: column tiles that share 128-byte lines (of the tiled target
+// and weights, when C = 4) are handed, in the same step, to workgroups on
+// the same XCD (workgroups are dispatched round-robin over the 8 XCDs), so
+// each line is fetched into one L2 once.
 // ---------------------------------------------------------------------------
 // Workgroup barrier that orders LDS traffic only: waits for this wave's LDS
 // operations, then s_barrier.  The fenced __syncthreads() would also wait for
@@ -864,7 +888,9 @@ struct ColpShape {
   static constexpr int T = NY / E, NT = C * T;
   static constexpr int FE = (NY + NY / 16) * C;  // float2: padded exchange tile (unpadded fill first)
   static constexpr int TWN = TwLayout<NY, E>::total();
-  static constexpr int G = C >= 16 ? 1 : 16 / C;  // tiles sharing a 128-byte line
+  // column tiles sharing a 128-byte line: a 4 x 4 tile of the field is a
+  // whole line, one of the 4-byte target / weights half a line
+  static constexpr int G = C >= 8 ? 1 : 8 / C;
 };
 
 template <int NY, int C, int E = kColpE>
@@ -874,7 +900,7 @@ __host__ __device__ constexpr int colp_lds_bytes() {
 }
 // Compiled tile shapes (C columns of NY rows) of the pipelined pass.
 __host__ __device__ constexpr bool colp_ok(int NY, int C) {
-  return (NY == 1024 && C == 4) || (NY == 512 && C == 8) || (NY == 256 && C == 16);
+  return (NY == 1024 && (C == 4 || C == 8)) || (NY == 512 && (C == 8 || C == 16)) || (NY == 256 && C == 16);
 }
 
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -885,23 +911,31 @@ __host__ __device__ constexpr bool colp_ok(int NY, int C) {
 #define HG_AS3(p) ((void*)(p))
 #endif
 
-// Issue the direct-to-LDS loads of tile vt's field columns (16-byte chunks,
-// C / 2 per row) into F in [row][c] order.  Each wave instruction fills 64
-// consecutive chunks (1 KB of LDS from a wave-uniform base).
+// Stage layout of a tile: the tiled field's own order, row quads of C / 4
+// consecutive 4 x 4 tiles, so element (row, c) is at colp_sidx<C>(row, c).
+template <int C> __device__ __forceinline__ int colp_sidx(int row, int c) {
+  return ((row >> 2) * (C / 4) + (c >> 2)) * 16 + (row & 3) * 4 + (c & 3);
+}
+
+// Issue the direct-to-LDS loads of tile vt's field columns: per row quad,
+// C / 4 tiles of 128 contiguous bytes (2 C chunks of 16 bytes).  Each wave
+// instruction fills 64 consecutive chunks (1 KB of LDS from a wave-uniform
+// base).
 template <int NY, int C, int E>
 __device__ __forceinline__ void colp_prefetch(const Batch& bt, int vt, int tpp, float2* F) {
   using S = ColpShape<NY, C, E>;
-  constexpr int NW = S::NT / 64, FPR = C / 2;
+  constexpr int NW = S::NT / 64, CPQ = 2 * C;  // chunks per row quad
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int b = vt / tpp, blk = vt - b * tpp;
   const int NX = bt.nx;
-  const float2* src = bt.field + (size_t)b * NY * NX + (size_t)blk * C;
+  const float2* src = bt.field + (size_t)b * NY * NX + (size_t)blk * C * 4;  // tile (0, blk C / 4)
+  const size_t qstride = (size_t)(NX >> 2) * 16;                               // elements per tile row
 #pragma unroll
-  for (int q = 0; q < NY * FPR / S::NT; ++q) {
+  for (int q = 0; q < NY * 2 * C / 4 / S::NT; ++q) {
     const int base = (q * NW + wave) * 64;
     const int ch = base + lane;
-    const int row = ch / FPR, part = ch - row * FPR;
-    __builtin_amdgcn_global_load_lds(HG_AS1(src + (size_t)row * NX + 2 * part), HG_AS3(F + 2 * base), 16, 0, 0);
+    const int quad = ch / CPQ, part = ch - quad * CPQ;
+    __builtin_amdgcn_global_load_lds(HG_AS1(src + quad * qstride + 2 * part), HG_AS3(F + 2 * base), 16, 0, 0);
   }
 }
 
@@ -929,14 +963,14 @@ __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int
   const size_t off = (size_t)b * NY * NX;
   gptr<const float> tp = to_global(bt.tprep + off);
 #pragma unroll
-  for (int j = 0; j < E; ++j) in.tv[j] = tp[(size_t)(t + T * j) * NX + u];
+  for (int j = 0; j < E; ++j) in.tv[j] = tp[tix(t + T * j, u, NX)];
   if constexpr (MODE == COL_WGS) {
     in.inv_m = bt.invm[b];
-    in.wout = d.user_weights ? d.weights : bt.wbuf + off;
+    in.wout = bt.wbuf + off;
     gptr<const float> w = to_global(in.wout);
     if (part_ptr(bt, b, bt.slots - 1, blk)[1] > 0.0) {  // the tile meets the support
 #pragma unroll
-      for (int j = 0; j < E; ++j) in.wv[j] = w[(size_t)(t + T * j) * NX + u];
+      for (int j = 0; j < E; ++j) in.wv[j] = w[tix(t + T * j, u, NX)];
     }
   }
 }
@@ -960,7 +994,7 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
     const size_t off = (size_t)b * NY * NX;
     float2 v[E];
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = Fc[(t + T * j) * C + c];
+    for (int j = 0; j < E; ++j) v[j] = Fc[colp_sidx<C>(t + T * j, c)];
     ColExL<C> ex{Fc + c};
     fft_lds<NY, E, -1>(v, t, tw, ex);
     float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f, s_w = 0.f;
@@ -983,7 +1017,7 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
           const float ratio = fmaxf(Tv, kWgsEps) * __builtin_amdgcn_rcpf(fmaxf(A, kWgsEps));
           const float wc = fminf(fmaxf(in.wv[j] * ratio * in.inv_m, kWMin), kWMax);
           const float wn = __builtin_amdgcn_exp2f(kWgsGamma * __builtin_amdgcn_logf(wc));
-          w[(size_t)row * NX + u] = wn;
+          w[tix(row, u, NX)] = wn;
           s_w += wn;
           amp = wn * Tv;
         }
@@ -999,7 +1033,7 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
     fft_lds<NY, E, +1>(v, t, tw, ex);
     gptr<float2> fld = to_global(bt.field + off);
 #pragma unroll
-    for (int j = 0; j < E; ++j) fld[(size_t)(t + T * j) * NX + u] = v[j];
+    for (int j = 0; j < E; ++j) fld[tix(t + T * j, u, NX)] = v[j];
   }
   if (vtn < total) colp_load_in<NY, C, MODE, E>(bt, k, vtn, tpp, in);
   __builtin_amdgcn_s_waitcnt(0);
@@ -1011,7 +1045,7 @@ __global__ __launch_bounds__(C * (NY / E))
 void k_colp(Batch bt, int k, int nprob) {
   using S = ColpShape<NY, C, E>;
   static_assert(S::NT <= 1024 && S::NT % 64 == 0 && C >= 4, "pipelined column tile shape");
-  static_assert(2 * colp_lds_bytes<NY, C, E>() <= 160 * 1024, "two workgroups' stages must fit in LDS");
+  static_assert(colp_lds_bytes<NY, C, E>() <= 160 * 1024, "the two stages must fit in LDS");
   __shared__ float2 FA[S::FE], FB[S::FE];
   __shared__ float2 TW[S::TWN];
   __shared__ double red[kMaxWaves][4];
@@ -1038,6 +1072,18 @@ void k_colp(Batch bt, int k, int nprob) {
     colp_tile<NY, C, MODE, E>(bt, k, vt, vt + NBK, total, tpp, FB, FA, tw, red, tot, in);
     vt += NBK;
   }
+}
+
+// Copy the final weights of problems that passed their own weight array back
+// to it (natural order from the tiled workspace plane).
+static __global__ void k_weights_out(Batch bt) {
+  const Desc& d = bt.desc[blockIdx.y];
+  if (!d.user_weights) return;
+  const long px = (long)bt.ny * bt.nx;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= px) return;
+  const int y = (int)(i / bt.nx), x = (int)(i % bt.nx);
+  d.weights[i] = bt.wbuf[(size_t)blockIdx.y * px + tix(y, x, bt.nx)];
 }
 
 // 1 / m_{k-1} of every problem for the pipelined weighted-GS column pass k:

