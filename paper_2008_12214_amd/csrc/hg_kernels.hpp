@@ -338,6 +338,36 @@ __device__ __forceinline__ float2 modulate(float2 v, int x, int y, const float2*
   }
 }
 
+// Row groups of 4 rows (one row of 4 x 4 field tiles, NX / 4 tiles of 128
+// contiguous bytes) move between HBM and the rows' LDS buffers with
+// 16-byte accesses by the whole workgroup: chunk c holds elements
+// x = 4 (c >> 3) + 2 (c & 1) + {0, 1} of row (c & 7) >> 1.
+template <int NX, int NT, int LW>
+__device__ __forceinline__ void quad_to_lds(gptr<const float2> q, float2* lds) {
+  constexpr int NCH = NX * 4 * 8 / 16;
+#pragma unroll
+  for (int m = 0; m < NCH / NT; ++m) {
+    const int c = threadIdx.x + NT * m;
+    const float4 val = reinterpret_cast<gptr<const float4>>(q)[c];
+    const int rr = (c & 7) >> 1, x = 4 * (c >> 3) + 2 * (c & 1);
+    float2* dst = lds + rr * LW;
+    dst[lds_pad(x)] = make_float2(val.x, val.y);
+    dst[lds_pad(x + 1)] = make_float2(val.z, val.w);
+  }
+}
+template <int NX, int NT, int LW>
+__device__ __forceinline__ void lds_to_quad(const float2* lds, gptr<float2> q) {
+  constexpr int NCH = NX * 4 * 8 / 16;
+#pragma unroll
+  for (int m = 0; m < NCH / NT; ++m) {
+    const int c = threadIdx.x + NT * m;
+    const int rr = (c & 7) >> 1, x = 4 * (c >> 3) + 2 * (c & 1);
+    const float2* src = lds + rr * LW;
+    const float2 a = src[lds_pad(x)], bq = src[lds_pad(x + 1)];
+    reinterpret_cast<gptr<float4>>(q)[c] = make_float4(a.x, a.y, bq.x, bq.y);
+  }
+}
+
 // MODE  ROW_INIT: build f0 (Philox, levels or field), forward FFT.
 //       ROW_ITER: inverse FFT, project, forward FFT (iteration k = arg).
 //       ROW_OSPR: as ROW_ITER with L = 2, writing subframe arg's levels.
@@ -352,7 +382,9 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
   constexpr bool WAVE = T <= 64;  // each row inside one wave
   constexpr int NBUF = WAVE ? 1 : 2;
   static_assert(T % 4 == 0, "a thread's elements share one column of the 4 x 4 tiles");
-  constexpr bool QSYNC = WAVE && RPB >= 4 && (RPB % 4) == 0;
+  // one 4-row group per workgroup, each row in one wave: stage the group's
+  // tiles through the rows' LDS buffers for whole-line 16-byte accesses
+  constexpr bool STAGE = WAVE && XCH && RPB == 4;
   __shared__ float2 lds[XCH ? RPB * NBUF * LW : 1];
   const int b = blockIdx.y;
   const int r = threadIdx.x / T, t = threadIdx.x % T;
@@ -360,6 +392,7 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
   const size_t off = (size_t)b * bt.ny * NX;
   // this row's elements in the tiled field: x at row[(x >> 2) * 16 + (x & 3)]
   gptr<float2> row = to_global(bt.field + off + (size_t)(y >> 2) * (NX >> 2) * 16 + (y & 3) * 4);
+  gptr<float2> quad = to_global(bt.field + off + (size_t)(y >> 2) * (NX >> 2) * 16);  // the group's tiles
   const float2* cx = bt.chirp + (size_t)b * (NX + bt.ny);
   const float2 cyv = FRESNEL ? cx[NX + y] : make_float2(1.f, 0.f);
   RowEx<WAVE> ex;
@@ -412,11 +445,15 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
       const bool last = (MODE == ROW_OSPR) || (arg == d.iters);
       gptr<uint8_t> lev = to_global(d.levels_out);
       if (MODE == ROW_OSPR) lev += (size_t)(arg - 1) * bt.ny * NX;
-      // The rows of a 4-row group each hold a quarter of every 128-byte tile;
-      // their waves load (and below store) in step so each line moves whole.
-      if constexpr (QSYNC) __syncthreads();
+      if constexpr (STAGE) {
+        quad_to_lds<NX, RPB * T, LW>(quad, lds);
+        __syncthreads();
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = row[((t + T * j) >> 2) * 16 + (t & 3)];
+        for (int j = 0; j < E; ++j) v[j] = ex.b[0][lds_pad(t + T * j)];
+      } else {
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = row[((t + T * j) >> 2) * 16 + (t & 3)];
+      }
       fft<NX, E, +1>(v, t, bt.tw_x, ex);
 #pragma unroll
       for (int j = 0; j < E; ++j) {
@@ -435,9 +472,16 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
       }
     }
     fft<NX, E, -1>(v, t, bt.tw_x, ex);
-    if constexpr (QSYNC) __syncthreads();
+    if constexpr (STAGE) {
+      wave_lds_sync();  // this wave's transform reads of its buffer are done
 #pragma unroll
-    for (int j = 0; j < E; ++j) row[((t + T * j) >> 2) * 16 + (t & 3)] = v[j];
+      for (int j = 0; j < E; ++j) ex.b[0][lds_pad(t + T * j)] = v[j];
+      __syncthreads();
+      lds_to_quad<NX, RPB * T, LW>(lds, quad);
+    } else {
+#pragma unroll
+      for (int j = 0; j < E; ++j) row[((t + T * j) >> 2) * 16 + (t & 3)] = v[j];
+    }
   }
 }
 
