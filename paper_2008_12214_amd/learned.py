@@ -22,6 +22,7 @@ weighted by the target amplitude.
 import argparse
 import json
 import math
+import os
 import sys
 import time
 
@@ -65,6 +66,26 @@ def init_params(seed, device="cuda", head_scale=0.01):
     v = np.concatenate(parts).astype(np.float32)
     assert v.size == B.hg_nn_param_count()
     return torch.from_numpy(v).to(device)
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet512_l8.npy")
+
+
+def load_params(path=WEIGHTS, device="cuda"):
+    """Trained parameters (float32 vector in the library's layout); the default
+    file was trained on 20000 512^2 Gaussian-sum targets with 8 phase levels."""
+    torch = _torch()
+    v = np.load(path, allow_pickle=False).astype(np.float32)
+    if v.size != B.hg_nn_param_count():
+        raise ValueError(f"{path}: {v.size} parameters, the network has {B.hg_nn_param_count()}")
+    return torch.from_numpy(v).to(device)
+
+
+def learned_start(params, targets, levels=8, workspace=None):
+    """SLM start levels from the network: psi0 + arg(network output) for targets [B, n, n]."""
+    ws = workspace if workspace is not None else B.hg_nn_workspace(*targets.shape, targets.device)
+    out = B.hg_nn_forward(params, targets, ws)
+    return B.hg_replay_phase_init(targets, levels, phasor=out, add_quadratic=True)
 
 
 def make_targets(n, seeds, device="cuda"):

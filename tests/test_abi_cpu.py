@@ -133,3 +133,11 @@ def test_nn_layer_validation():
     assert L.hg_quadratic_phase_apply(FAKE, 1, 64, 64, 0, None) == hg.HG_ERR_INVALID_ARG
     assert L.hg_nn_conv3x3_wgrad(FAKE, FAKE, FAKE, FAKE, 1, 8, 8, 16, 272, FAKE, 1 << 30, None) == \
         hg.HG_ERR_INVALID_ARG  # more than 256 output channels
+
+
+def test_committed_network_weights_match_the_layout():
+    import numpy as np
+    from paper_2008_12214_amd import learned
+    v = np.load(learned.WEIGHTS, allow_pickle=False)
+    assert v.dtype == np.float32 and v.shape == (hg.hg_nn_param_count(),)
+    assert np.isfinite(v).all()
