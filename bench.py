@@ -100,6 +100,151 @@ def cpu_baseline(budget_s=20.0):
                       f"evaluation), FP64 DFT-matrix oracle, {dt:.1f} s"}
 
 
+def other_workload(args):
+    """The non-headline workloads, one JSON line each.  The timed region is K
+    replays of a HIP graph holding one whole library call (set-up, every
+    iteration or subframe, NMSE finisher); the eager rate of the same call
+    and per-kernel hipEvent times of an instrumented eager pass are reported
+    beside it."""
+    import ctypes
+    import torch
+    import synth
+    import paper_2008_12214_amd as hg
+    from paper_2008_12214_amd._binding import hg_problem
+
+    dev = torch.device("cuda:0")
+    lib = hg.lib()
+    wl = args.workload
+
+    def cur_stream():
+        return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+    def check(st):
+        if st != 0:
+            raise RuntimeError(hg.hg_last_error())
+
+    if wl == "gs64":
+        n, iters, levels = 64, 50, 8
+        T = torch.from_numpy(synth.uniform_target(n, n, seed=1)).to(dev)
+        lv = torch.empty((n, n), dtype=torch.uint8, device=dev)
+        nm = torch.empty(iters + 1, dtype=torch.float64, device=dev)
+        nb = lib.hg_workspace_size(hg.HG_OP_GS, n, n, iters)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+
+        def step():
+            check(lib.hg_gs(ctypes.c_void_p(T.data_ptr()), n, n, iters, levels, 1, None, None, 0.0, 0.0, 0.0,
+                            ctypes.c_void_p(lv.data_ptr()), None, None, ctypes.c_void_p(nm.data_ptr()),
+                            ctypes.c_void_p(ws.data_ptr()), nb, cur_stream()))
+        px, units, unit = n * n, iters, "iter/s"
+        bytes_col = px * (iters * 20 + 12)
+        bytes_row = px * (8 + iters * 16 + 1)
+        config = {"workload": "gs_8level_64x64_50it", "grid": [n, n], "iters": iters, "slm_levels": levels,
+                  "target": "sqrt of uniform intensity"}
+        kernel = "column pass of GS (k_col<64>)"
+    elif wl == "ospr512":
+        n, sub = 512, 24
+        T = torch.from_numpy(synth.gaussian_target(n, seed=3)).to(dev)
+        lv = torch.empty((sub, n, n), dtype=torch.uint8, device=dev)
+        nm = torch.empty(sub, dtype=torch.float64, device=dev)
+        nb = lib.hg_workspace_size(hg.HG_OP_OSPR, n, n, sub)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+
+        def step():
+            check(lib.hg_ospr(ctypes.c_void_p(T.data_ptr()), n, n, sub, 1, 3, ctypes.c_void_p(lv.data_ptr()),
+                              ctypes.c_void_p(nm.data_ptr()), None, ctypes.c_void_p(ws.data_ptr()), nb,
+                              cur_stream()))
+        px, units, unit = n * n, sub, "subframes/s"
+        # column launches: first (T r 4, field w 8), subframes 2..N (field r+w 16, T 4, accumulator
+        # r+w 8; no read for subframe 2), final (field r 8, T 4); row: field r+w 16 + levels w 1
+        bytes_col = px * (12 + 28 * (sub - 1) - 4 + 12)
+        bytes_row = px * 17 * sub
+        config = {"workload": "adaptive_ospr_binary_512x512_24sf", "grid": [n, n], "subframes": sub,
+                  "slm_levels": 2, "target": "gaussian sum, 32 blobs, central window"}
+        kernel = "column pass of adaptive OSPR (k_col<512,COL_OSPR>)"
+    else:
+        sizes = synth.batch_mix()
+        iters, levels = 50, 8
+        B = len(sizes)
+        tg = [torch.from_numpy(synth.gaussian_target(s, seed=4, batch_item=b)).to(dev) for b, s in enumerate(sizes)]
+        lv = [torch.empty((s, s), dtype=torch.uint8, device=dev) for s in sizes]
+        nm = [torch.empty(iters + 1, dtype=torch.float64, device=dev) for _ in sizes]
+        arr = (hg_problem * B)()
+        for b, s in enumerate(sizes):
+            arr[b] = hg_problem(s, s, levels, iters, 1000 + b, synth.WAVELENGTH_M, synth.PITCH_M,
+                                synth.fresnel_z(4, b), tg[b].data_ptr(), lv[b].data_ptr(), nm[b].data_ptr())
+        nb = lib.hg_gs_batched_workspace_size(arr, B)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+
+        def step():
+            check(lib.hg_gs_batched(arr, B, 0, ctypes.c_void_p(ws.data_ptr()), nb, cur_stream()))
+        px = sum(s * s for s in sizes)
+        units, unit = iters, "batch-iter/s"
+        bytes_col = px * (iters * 20 + 12)
+        bytes_row = px * (8 + iters * 16 + 1)
+        config = {"workload": "batched_uneven_fresnel_8level_50it", "problems": B,
+                  "sizes": {str(s): sizes.count(s) for s in sorted(set(sizes))}, "pixels": px, "iters": iters,
+                  "slm_levels": levels, "wavelength_m": synth.WAVELENGTH_M, "pitch_m": synth.PITCH_M,
+                  "z_m": "uniform [0.1, 0.5]"}
+        kernel = "column pass of Fresnel GS, all size classes (k_col / k_colp)"
+
+    log(f"{wl}: warmup {args.warmup}, steps {args.steps}")
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize(dev)
+    k = args.steps
+    t0 = time.perf_counter()
+    for _ in range(k):
+        step()
+    torch.cuda.synchronize(dev)
+    eager = (time.perf_counter() - t0) / k
+
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for _ in range(max(1, args.warmup)):
+        g.replay()
+    torch.cuda.synchronize(dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        g.replay()
+        b.record()
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    per = sorted(a.elapsed_time(b) * 1e-3 for a, b in ev)
+    med = per[len(per) // 2]
+
+    hg.hg_timing_enable(True)
+    hg.hg_timing_read()
+    step()
+    torch.cuda.synchronize(dev)
+    kt = hg.hg_timing_read()
+    hg.hg_timing_enable(False)
+    col_gbs = bytes_col / (kt["col_ms"] * 1e-3) / 1e9
+    row_gbs = bytes_row / (kt["row_ms"] * 1e-3) / 1e9
+    call_gbs = (bytes_col + bytes_row) / med / 1e9
+    log(f"graph median {med * 1e3:.3f} ms/call, eager {eager * 1e3:.3f} ms/call; column {col_gbs:.0f} GB/s, "
+        f"row {row_gbs:.0f} GB/s, whole call {call_gbs:.0f} GB/s")
+    out = {
+        "metric": f"{unit} ({wl})", "value": round(units / med, 1), "unit": unit, "n_gpus": 1, "steps": k,
+        "warmup": args.warmup, "ms_per_step": round(wall / k * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": config,
+        "roofline": {"bound": "hbm", "achieved": round(col_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(col_gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
+                     "bytes_per_launch": int(bytes_col / kt["col_launches"]),
+                     "avg_launch_us": round(kt["col_ms"] / kt["col_launches"] * 1e3, 2)},
+        "cpu_baseline": None,
+        "extra": {"graph_median_ms_per_call": round(med * 1e3, 4), "eager_ms_per_call": round(eager * 1e3, 4),
+                  "eager_value": round(units / eager, 1),
+                  "row_pass": {"avg_launch_us": round(kt["row_ms"] / kt["row_launches"] * 1e3, 2),
+                               "achieved_GBs": round(row_gbs, 1)},
+                  "whole_call_algorithmic_GBs": round(call_gbs, 1),
+                  "setup_ms": round(kt.get("setup_ms", 0.0), 4)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +255,10 @@ def main():
     ap.add_argument("--no-b1", action="store_true")
     ap.add_argument("--iters", type=int, default=100,
                     help="iterations per hologram (100 is the workload; fewer only for short profiles)")
+    ap.add_argument("--workload", default="wgs1024", choices=["wgs1024", "gs64", "ospr512", "uneven"],
+                    help="wgs1024 (default): the headline batch; gs64: one 64^2 8-level GS, latency; "
+                         "ospr512: adaptive binary OSPR, 512^2, 24 subframes; uneven: 256 Fresnel problems "
+                         "of four sizes, 8 levels, 50 iterations")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -121,6 +270,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload != "wgs1024":
+        other_workload(args)
+        return
 
     import ctypes
     import torch

@@ -96,7 +96,22 @@ __device__ __forceinline__ void wave_lds_sync() {
 // (T <= 64 threads) exchanges through one buffer with wave-level ordering
 // only; a row spread over several waves uses ping-pong buffers and one
 // workgroup barrier per exchange.
-template <bool WAVE> struct RowEx {
+// Values that are the same for the whole workgroup (descriptor fields read
+// at a uniform address) moved into scalar registers, so that branches on
+// them stay scalar branches.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+template <class T> __device__ __forceinline__ T* uni_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+// Row exchange buffers.  A row inside one wave needs only wave-level LDS
+// ordering.  A row spread over several waves uses two buffers (PP: one
+// barrier per exchange) or, where LDS is short, one buffer with a barrier
+// before the writes and another before the reads.
+template <bool WAVE, bool PP = true> struct RowEx {
   float2* b[2];
   int w, rd;
   __device__ void before_read() {
@@ -104,16 +119,19 @@ template <bool WAVE> struct RowEx {
       wave_lds_sync();
     } else {
       __syncthreads();
-      rd = w;
-      w ^= 1;
+      if constexpr (PP) {
+        rd = w;
+        w ^= 1;
+      }
     }
   }
   __device__ void before_write() {
     if constexpr (WAVE) wave_lds_sync();
+    else if constexpr (!PP) __syncthreads();
   }
-  __device__ float2 ld(int e) const { return WAVE ? b[0][e] : b[rd][e]; }
+  __device__ float2 ld(int e) const { return (WAVE || !PP) ? b[0][e] : b[rd][e]; }
   __device__ void st(int e, float2 v) {
-    if constexpr (WAVE) b[0][e] = v;
+    if constexpr (WAVE || !PP) b[0][e] = v;
     else b[w][e] = v;
   }
 };
@@ -327,16 +345,23 @@ enum RowMode { ROW_INIT = 0, ROW_ITER = 1, ROW_OSPR = 2, ROW_PROP_FWD = 3, ROW_P
 enum LevelKind { LK_ANY = 0, LK_BIN = 1 };  // LK_BIN: every problem of the launch has L = 2
 
 // Modulation m[y][x] applied before the forward row FFT and conjugated after
-// the inverse one: (-1)^(x+y) for Fourier, chirp * (-1)^(x+y) for Fresnel.
-template <bool FRESNEL>
-__device__ __forceinline__ float2 modulate(float2 v, int x, int y, const float2* cx, float2 cyv, bool conj) {
-  if constexpr (FRESNEL) {
-    const float2 m = cmul(cx[x], cyv);
-    return conj ? cmulc(v, m) : cmul(v, m);
-  } else {
-    return ((x + y) & 1) ? make_float2(-v.x, -v.y) : v;
+// the inverse one: (-1)^(x+y) for Fourier, chirp * (-1)^(x+y) for Fresnel
+// (the sign is folded into the chirp tables).  Built once per element.
+template <bool FRESNEL> struct Mod {
+  float2 m;  // Fresnel: the chirp product; Fourier: (+-1, 0)
+  __device__ __forceinline__ Mod(int x, int y, gptr<const float2> cx, float2 cyv) {
+    if constexpr (FRESNEL) m = cmul(cx[x], cyv);
+    else m = make_float2(((x + y) & 1) ? -1.0f : 1.0f, 0.0f);
   }
-}
+  __device__ __forceinline__ float2 fwd(float2 v) const {
+    if constexpr (FRESNEL) return cmul(v, m);
+    else return make_float2(v.x * m.x, v.y * m.x);
+  }
+  __device__ __forceinline__ float2 inv(float2 v) const {
+    if constexpr (FRESNEL) return cmulc(v, m);
+    else return make_float2(v.x * m.x, v.y * m.x);
+  }
+};
 
 // Row groups of 4 rows (one row of 4 x 4 field tiles, NX / 4 tiles of 128
 // contiguous bytes) move between HBM and the rows' LDS buffers with
@@ -380,12 +405,17 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
   constexpr int LW = NX + NX / 16;
   constexpr bool XCH = P::ns > 1;
   constexpr bool WAVE = T <= 64;  // each row inside one wave
-  constexpr int NBUF = WAVE ? 1 : 2;
   static_assert(T % 4 == 0, "a thread's elements share one column of the 4 x 4 tiles");
-  // one 4-row group per workgroup, each row in one wave: stage the group's
-  // tiles through the rows' LDS buffers for whole-line 16-byte accesses
-  constexpr bool STAGE = WAVE && XCH && RPB == 4;
+  // one 4-row group per workgroup: stage the group's tiles through the rows'
+  // LDS buffers for whole-line 16-byte accesses (rows of several waves then
+  // exchange through one buffer each)
+  constexpr bool STAGE = XCH && RPB == 4;
+  constexpr bool PP = !WAVE && !STAGE;
+  constexpr int NBUF = PP ? 2 : 1;
   __shared__ float2 lds[XCH ? RPB * NBUF * LW : 1];
+  // phasors of the problem's levels (general L, projection only)
+  constexpr bool TAB = (MODE == ROW_ITER && LK == LK_ANY);
+  __shared__ float2 lvl[TAB ? 256 : 1];
   const int b = blockIdx.y;
   const int r = threadIdx.x / T, t = threadIdx.x % T;
   const int y = blockIdx.x * RPB + r;
@@ -393,9 +423,9 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
   // this row's elements in the tiled field: x at row[(x >> 2) * 16 + (x & 3)]
   gptr<float2> row = to_global(bt.field + off + (size_t)(y >> 2) * (NX >> 2) * 16 + (y & 3) * 4);
   gptr<float2> quad = to_global(bt.field + off + (size_t)(y >> 2) * (NX >> 2) * 16);  // the group's tiles
-  const float2* cx = bt.chirp + (size_t)b * (NX + bt.ny);
-  const float2 cyv = FRESNEL ? cx[NX + y] : make_float2(1.f, 0.f);
-  RowEx<WAVE> ex;
+  gptr<const float2> cx = to_global(static_cast<const float2*>(bt.chirp)) + (size_t)b * (NX + bt.ny);
+  const float2 cyv = FRESNEL ? static_cast<float2>(cx[NX + y]) : make_float2(1.f, 0.f);
+  RowEx<WAVE, PP> ex;
   ex.b[0] = lds + (XCH ? r * NBUF * LW : 0);
   ex.b[1] = ex.b[0] + (XCH && !WAVE ? LW : 0);
   ex.w = 0;
@@ -410,12 +440,12 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
     for (int j = 0; j < E; ++j) v[j] = src[t + T * j];
     if constexpr (MODE == ROW_PROP_FWD) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = cscale(modulate<FRESNEL>(v[j], t + T * j, y, cx, cyv, false), s);
+      for (int j = 0; j < E; ++j) v[j] = cscale(Mod<FRESNEL>(t + T * j, y, cx, cyv).fwd(v[j]), s);
       fft<NX, E, -1>(v, t, bt.tw_x, ex);
     } else {
       fft<NX, E, +1>(v, t, bt.tw_x, ex);
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = cscale(modulate<FRESNEL>(v[j], t + T * j, y, cx, cyv, true), s);
+      for (int j = 0; j < E; ++j) v[j] = cscale(Mod<FRESNEL>(t + T * j, y, cx, cyv).inv(v[j]), s);
     }
 #pragma unroll
     for (int j = 0; j < E; ++j) dst[t + T * j] = v[j];
@@ -438,13 +468,21 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
         }
       }
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = modulate<FRESNEL>(v[j], t + T * j, y, cx, cyv, false);
+      for (int j = 0; j < E; ++j) v[j] = Mod<FRESNEL>(t + T * j, y, cx, cyv).fwd(v[j]);
     } else {
-      if (MODE == ROW_ITER && arg > d.iters) return;  // uniform per block
-      const int L = (MODE == ROW_OSPR || LK == LK_BIN) ? 2 : d.L;
-      const bool last = (MODE == ROW_OSPR) || (arg == d.iters);
-      gptr<uint8_t> lev = to_global(d.levels_out);
+      const int iters = uni(d.iters);
+      if (MODE == ROW_ITER && arg > iters) return;  // uniform per block
+      const int L = (MODE == ROW_OSPR || LK == LK_BIN) ? 2 : uni(d.L);
+      const bool last = (MODE == ROW_OSPR) || (arg == iters);
+      gptr<uint8_t> lev = to_global(uni_ptr(d.levels_out));
+      gptr<float2> fout = to_global(uni_ptr(d.field_out));
       if (MODE == ROW_OSPR) lev += (size_t)(arg - 1) * bt.ny * NX;
+      if constexpr (TAB) {
+        if (L > 2) {  // uniform per block
+          for (int i = threadIdx.x; i < L; i += RPB * T) lvl[i] = level_phasor(i, L);
+          __syncthreads();
+        }
+      }
       if constexpr (STAGE) {
         quad_to_lds<NX, RPB * T, LW>(quad, lds);
         __syncthreads();
@@ -455,25 +493,52 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
         for (int j = 0; j < E; ++j) v[j] = row[((t + T * j) >> 2) * 16 + (t & 3)];
       }
       fft<NX, E, +1>(v, t, bt.tw_x, ex);
+      // projection onto the SLM set, one code path per kind of level set
+      // (uniform per block: 0 continuous, 2 binary, 3 any other L) and per
+      // iteration kind (only the last writes levels and the field)
+      auto project = [&](auto kind, auto wr) {
+        constexpr int KIND = decltype(kind)::value;
+        constexpr bool WR = decltype(wr)::value;
 #pragma unroll
-      for (int j = 0; j < E; ++j) {
-        const int x = t + T * j;
-        const float2 g = modulate<FRESNEL>(v[j], x, y, cx, cyv, true);
-        float2 f;
-        if (L == 0) {
-          f = unit_phase(g);
-        } else {
-          const int k = level_index(g, L);
-          f = level_phasor(k, L);
-          if (last && lev) lev[(size_t)y * NX + x] = (uint8_t)k;
+        for (int j = 0; j < E; ++j) {
+          const int x = t + T * j;
+          const Mod<FRESNEL> md(x, y, cx, cyv);
+          const float2 g = md.inv(v[j]);
+          float2 f;
+          if constexpr (KIND == 0) {
+            f = unit_phase(g);
+          } else {
+            const int k = level_index(g, KIND == 2 ? 2 : L);
+            if constexpr (KIND == 2) f = level_phasor(k, 2);
+            else f = lvl[k];
+            if constexpr (WR) {
+              if (lev) lev[(size_t)y * NX + x] = (uint8_t)k;
+            }
+          }
+          if constexpr (WR && MODE == ROW_ITER) {
+            if (fout) fout[(size_t)y * NX + x] = f;
+          }
+          v[j] = md.fwd(f);
         }
-        if (MODE == ROW_ITER && last && d.field_out) to_global(d.field_out)[(size_t)y * NX + x] = f;
-        v[j] = modulate<FRESNEL>(f, x, y, cx, cyv, false);
-      }
+      };
+      auto by_kind = [&](auto wr) {
+        if constexpr (TAB) {
+          if (L == 2) project(std::integral_constant<int, 2>{}, wr);
+          else if (L == 0) project(std::integral_constant<int, 0>{}, wr);
+          else project(std::integral_constant<int, 3>{}, wr);
+        } else {
+          project(std::integral_constant<int, 2>{}, wr);  // every problem binary
+        }
+      };
+      if (last) by_kind(std::true_type{});
+      else by_kind(std::false_type{});
     }
     fft<NX, E, -1>(v, t, bt.tw_x, ex);
     if constexpr (STAGE) {
-      wave_lds_sync();  // this wave's transform reads of its buffer are done
+      // the transform's reads of the row buffers are done (this wave's, or
+      // the whole block's when a row spans several waves)
+      if constexpr (WAVE) wave_lds_sync();
+      else __syncthreads();
 #pragma unroll
       for (int j = 0; j < E; ++j) ex.b[0][lds_pad(t + T * j)] = v[j];
       __syncthreads();

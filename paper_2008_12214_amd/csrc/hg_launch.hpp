@@ -24,10 +24,11 @@ __host__ __device__ constexpr bool col_ok(int N, int C) {
     default: return false;
   }
 }
-// Rows per row-pass workgroup compiled for a row length N (128 or 256 threads).
+// Rows per row-pass workgroup compiled for a row length N (128 or 256
+// threads; and one 4-row group of two-wave rows, 512 threads, at N = 2048).
 __host__ __device__ constexpr bool rpb_ok(int N, int RPB) {
   const int T = N / kE;
-  return (RPB * T == 128 || RPB * T == 256) || (T >= 256 && RPB == 1);
+  return (RPB * T == 128 || RPB * T == 256) || (T >= 256 && RPB == 1) || (T == 128 && RPB == 4);
 }
 
 // The persistent pipelined column pass (k_colp) runs GS / weighted GS column
