@@ -189,6 +189,14 @@ hg_status hg_autotune(int ny, int nx, int batch, int* col_tile, int* rows_per_gr
 hg_status hg_set_launch_config(int ny, int nx, int batch, int col_tile, int rows_per_group);
 hg_status hg_get_launch_config(int ny, int nx, int batch, int* col_tile, int* rows_per_group);
 
+/* Small problems (ny and nx each 64 or 128) run a whole hg_gs / hg_wgs call,
+ * or a size class of hg_gs_batched, in one launch: one workgroup per
+ * problem with the field resident in LDS.  enable = 0 selects the
+ * multi-launch pipeline for them instead, 1 (the default, unless the
+ * environment sets HG_SMALL_KERNEL=off) the single launch.  Process-wide;
+ * results are identical up to the order of the NMSE partial sums. */
+hg_status hg_set_small_fused(int enable);
+
 /* Kernel timing (instrumentation for benchmarks).  While enabled, every
  * launch of a column pass, row pass or set-up kernel made by this process
  * is bracketed by a pair of hipEvents on the stream it is launched on.

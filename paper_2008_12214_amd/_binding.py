@@ -82,6 +82,8 @@ def lib():
         L.hg_autotune.argtypes = [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), _vp, _sz, _vp]
         L.hg_set_launch_config.restype = _i
         L.hg_set_launch_config.argtypes = [_i, _i, _i, _i, _i]
+        L.hg_set_small_fused.restype = _i
+        L.hg_set_small_fused.argtypes = [_i]
         L.hg_get_launch_config.restype = _i
         L.hg_get_launch_config.argtypes = [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]
         L.hg_timing_enable.restype = None
@@ -123,6 +125,11 @@ def hg_autotune(ny, nx, batch=1, device="cuda", stream=None):
 
 def hg_set_launch_config(ny, nx, batch, col_tile, rows_per_group):
     _check(lib().hg_set_launch_config(ny, nx, batch, col_tile, rows_per_group))
+
+
+def hg_set_small_fused(enable):
+    """Single-launch path for small problems (each side 64 or 128): on (default) or off."""
+    _check(lib().hg_set_small_fused(int(bool(enable))))
 
 
 def hg_get_launch_config(ny, nx, batch=1):

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -287,10 +288,17 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
   const Cfg cfg = get_cfg(ny, nx, B);
   Batch bt = make_batch(ws, L, ny, nx, cfg.C);
   upload_descs(const_cast<Desc*>(bt.desc), ds, st);
-  launch_twiddles(const_cast<float2*>(bt.tw_x), nx, st);
-  if (ny != nx) launch_twiddles(const_cast<float2*>(bt.tw_y), ny, st);
   bool fresnel = false;
   for (double r : rates) fresnel |= (r != 0.0);
+  if (small_ok(ny, nx) && small_enabled()) {
+    // whole call in one launch, one workgroup per problem
+    if (fresnel) launch_chirps(const_cast<float2*>(bt.chirp), ny, nx, rates, st);
+    TimeScope ts(TC_COL, st);
+    launch_small(bt, B, fresnel, weighted, st);
+    return check_launch();
+  }
+  launch_twiddles(const_cast<float2*>(bt.tw_x), nx, st);
+  if (ny != nx) launch_twiddles(const_cast<float2*>(bt.tw_y), ny, st);
   if (fresnel) launch_chirps(const_cast<float2*>(bt.chirp), ny, nx, rates, st);
   launch_setup(bt, cfg.C, B, weighted ? 1 : 0, st);
   const int lk = all_bin ? LK_BIN : LK_ANY;
@@ -392,6 +400,17 @@ ClassPlan plan_classes(const hg_problem* probs, int count) {
 
 }  // namespace
 
+// Single-launch path for small problems: on unless HG_SMALL_KERNEL=off or
+// switched by hg_set_small_fused.
+static std::atomic<int> g_small_fused{[] {
+  const char* e = std::getenv("HG_SMALL_KERNEL");
+  return (e && std::string(e) == "off") ? 0 : 1;
+}()};
+
+namespace hg {
+bool small_enabled() { return g_small_fused.load(std::memory_order_relaxed) != 0; }
+}  // namespace hg
+
 // Error text shared with the network translation unit (same thread-local
 // buffer that hg_last_error returns).
 namespace hg_internal {
@@ -430,6 +449,13 @@ hg_status hg_timing_read(hg_kernel_times* out) {
   }
   g_timing.marks.clear();
   g_timing.used = 0;
+  return HG_OK;
+}
+
+hg_status hg_set_small_fused(int enable) {
+  g_err[0] = 0;
+  if (enable != 0 && enable != 1) return fail(HG_ERR_INVALID_ARG, "enable must be 0 or 1");
+  g_small_fused.store(enable, std::memory_order_relaxed);
   return HG_OK;
 }
 

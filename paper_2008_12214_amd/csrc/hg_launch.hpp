@@ -51,6 +51,12 @@ inline int colp_elements() {
   return e;
 }
 
+// Small problems (each side 64 or 128) run whole in one workgroup with the
+// field resident in LDS (hg_small.hip) unless switched off (hg_set_small_fused).
+inline bool small_ok(int ny, int nx) { return (ny == 64 || ny == 128) && (nx == 64 || nx == 128); }
+bool small_enabled();
+void launch_small(const Batch& bt, int B, bool fresnel, bool weighted, hipStream_t st);
+
 template <int N> void launch_col_t(int C, const Batch& bt, int B, int mode, int arg, int adaptive,
                                    const float2* pin, float2* pout, hipStream_t st);
 template <int N> void launch_setup_t(int C, const Batch& bt, int B, int weighted, hipStream_t st);

@@ -119,7 +119,8 @@ def test_propagate_4096_properties():
 # continuous-phase GS, free-running
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("ny,nx,iters,optics", [(64, 64, 50, None), (128, 256, 20, None),
-                                                (256, 128, 10, (532e-9, 8e-6, 0.1)), (1024, 1024, 5, None)])
+                                                (256, 128, 10, (532e-9, 8e-6, 0.1)), (1024, 1024, 5, None),
+                                                (128, 128, 10, (532e-9, 8e-6, 0.15))])
 def test_gs_continuous_free_running(ny, nx, iters, optics):
     """Free-running: NMSE of every iteration; fields while the trajectories
     have not yet drifted apart (zero-amplitude target regions leave the
@@ -209,6 +210,17 @@ def test_gs_fresnel_lockstep():
     say("gs L=8 fresnel 256^2 lock-step x5")
     T = synth.gaussian_target(256, seed=4)
     _lockstep(T, 8, 5, weighted=False, optics=(532e-9, 8e-6, synth.fresnel_z(4, 0)))
+
+
+@pytest.mark.parametrize("ny,nx,weighted,L,optics", [
+    (64, 128, True, 2, None), (128, 64, False, 4, (532e-9, 8e-6, 0.12)),
+    (128, 128, True, 8, (532e-9, 8e-6, 0.2)), (128, 128, False, 3, None)])
+def test_small_single_launch_lockstep(ny, nx, weighted, L, optics):
+    """Sizes that run whole in the single-launch small-problem kernel."""
+    say("small single launch lock-step", ny, nx, "wgs" if weighted else "gs", L, optics)
+    T = synth.gaussian_target(nx, seed=5, ny=ny)
+    worst, ex, _ = _lockstep(T, L, 4, weighted=weighted, optics=optics)
+    say(f"  worst nmse rel err {worst:.2e}, exempt level flips {ex}")
 
 
 @pytest.mark.parametrize("rpb", [2, 4])
