@@ -366,18 +366,19 @@ template <bool FRESNEL> struct Mod {
 // Row groups of 4 rows (one row of 4 x 4 field tiles, NX / 4 tiles of 128
 // contiguous bytes) move between HBM and the rows' LDS buffers with
 // 16-byte accesses by the whole workgroup: chunk c holds elements
-// x = 4 (c >> 3) + 2 (c & 1) + {0, 1} of row (c & 7) >> 1.
+// x = 4 (c >> 3) + 2 (c & 1) + {0, 1} of row (c & 7) >> 1.  Staged rows are
+// unpadded (element x at x), so each chunk is one aligned 16-byte LDS access
+// and a row's chunks are contiguous.
 template <int NX, int NT, int LW>
 __device__ __forceinline__ void quad_to_lds(gptr<const float2> q, float2* lds) {
   constexpr int NCH = NX * 4 * 8 / 16;
+  static_assert(LW % 2 == 0, "16-byte aligned rows");
 #pragma unroll
   for (int m = 0; m < NCH / NT; ++m) {
     const int c = threadIdx.x + NT * m;
     const float4 val = reinterpret_cast<gptr<const float4>>(q)[c];
     const int rr = (c & 7) >> 1, x = 4 * (c >> 3) + 2 * (c & 1);
-    float2* dst = lds + rr * LW;
-    dst[lds_pad(x)] = make_float2(val.x, val.y);
-    dst[lds_pad(x + 1)] = make_float2(val.z, val.w);
+    *reinterpret_cast<float4*>(lds + rr * LW + x) = val;
   }
 }
 template <int NX, int NT, int LW>
@@ -387,9 +388,7 @@ __device__ __forceinline__ void lds_to_quad(const float2* lds, gptr<float2> q) {
   for (int m = 0; m < NCH / NT; ++m) {
     const int c = threadIdx.x + NT * m;
     const int rr = (c & 7) >> 1, x = 4 * (c >> 3) + 2 * (c & 1);
-    const float2* src = lds + rr * LW;
-    const float2 a = src[lds_pad(x)], bq = src[lds_pad(x + 1)];
-    reinterpret_cast<gptr<float4>>(q)[c] = make_float4(a.x, a.y, bq.x, bq.y);
+    reinterpret_cast<gptr<float4>>(q)[c] = *reinterpret_cast<const float4*>(lds + rr * LW + x);
   }
 }
 
@@ -402,7 +401,6 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
   constexpr int E = kE;
   using P = Plan<NX, E>;
   constexpr int T = P::T;
-  constexpr int LW = NX + NX / 16;
   constexpr bool XCH = P::ns > 1;
   constexpr bool WAVE = T <= 64;  // each row inside one wave
   static_assert(T % 4 == 0, "a thread's elements share one column of the 4 x 4 tiles");
@@ -410,9 +408,13 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
   // LDS buffers for whole-line 16-byte accesses (rows of several waves then
   // exchange through one buffer each)
   constexpr bool STAGE = XCH && RPB == 4;
+  // row buffer pitch; staged rows are offset by 8 elements so that the four
+  // rows of a group, which the staging accesses interleave, fall in
+  // different LDS banks
+  constexpr int LW = NX + NX / 16 + (STAGE ? 8 : 0);
   constexpr bool PP = !WAVE && !STAGE;
   constexpr int NBUF = PP ? 2 : 1;
-  __shared__ float2 lds[XCH ? RPB * NBUF * LW : 1];
+  __shared__ __align__(16) float2 lds[XCH ? RPB * NBUF * LW : 1];
   // phasors of the problem's levels (general L, projection only)
   constexpr bool TAB = (MODE == ROW_ITER && LK == LK_ANY);
   __shared__ float2 lvl[TAB ? 256 : 1];
@@ -487,7 +489,7 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
         quad_to_lds<NX, RPB * T, LW>(quad, lds);
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = ex.b[0][lds_pad(t + T * j)];
+        for (int j = 0; j < E; ++j) v[j] = ex.b[0][t + T * j];  // unpadded staging order
       } else {
 #pragma unroll
         for (int j = 0; j < E; ++j) v[j] = row[((t + T * j) >> 2) * 16 + (t & 3)];
@@ -540,7 +542,7 @@ __global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, cons
       if constexpr (WAVE) wave_lds_sync();
       else __syncthreads();
 #pragma unroll
-      for (int j = 0; j < E; ++j) ex.b[0][lds_pad(t + T * j)] = v[j];
+      for (int j = 0; j < E; ++j) ex.b[0][t + T * j] = v[j];  // unpadded staging order
       __syncthreads();
       lds_to_quad<NX, RPB * T, LW>(lds, quad);
     } else {
