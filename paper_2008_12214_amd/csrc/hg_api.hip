@@ -116,7 +116,7 @@ Cfg default_cfg(int ny, int nx, int B) {
     default: c.C = 2; break;
   }
   const int T = nx / kE;
-  c.RPB = T >= 256 ? 1 : 256 / T;
+  c.RPB = T >= 256 ? 1 : T == 128 ? 4 : 256 / T;  // 2048-wide rows: staged 4-row groups
   (void)B;
   return c;
 }

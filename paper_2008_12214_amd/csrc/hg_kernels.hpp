@@ -396,8 +396,14 @@ __device__ __forceinline__ void lds_to_quad(const float2* lds, gptr<float2> q) {
 //       ROW_ITER: inverse FFT, project, forward FFT (iteration k = arg).
 //       ROW_OSPR: as ROW_ITER with L = 2, writing subframe arg's levels.
 //       ROW_PROP_FWD / _BWD: scaled propagation between pin and pout.
+// Waves per SIMD asked of the compiler for the staged 4-row groups: within
+// 128 registers per lane, two 512-thread workgroups of 2048-wide rows (or
+// four 256-thread ones of 1024-wide rows) share a CU.
+template <int NX, int RPB> constexpr int row_min_waves() { return ((NX == 2048 || NX == 1024) && RPB == 4) ? 4 : 1; }
+
 template <int NX, int RPB, bool FRESNEL, int MODE, int LK>
-__global__ __launch_bounds__(RPB * (NX / kE)) void k_row(Batch bt, int arg, const float2* pin, float2* pout) {
+__global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k_row(Batch bt, int arg,
+                                                                                     const float2* pin, float2* pout) {
   constexpr int E = kE;
   using P = Plan<NX, E>;
   constexpr int T = P::T;
