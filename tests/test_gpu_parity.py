@@ -2,7 +2,8 @@
 
 Tolerances: complex fields and NMSE within 1e-4 relative (L2 for fields).
 Quantised levels must match exactly except at pixels whose oracle phase lies
-within 1e-5 rad of a decision boundary; those are counted and reported.
+within 1e-5 rad of a decision boundary or whose field is zero to FP32
+precision (|g| below 1e-6 of its rms); those are counted and reported.
 Quantised runs are checked in lock-step: each step starts both sides from
 the GPU's own state (levels, weights, accumulated intensity), because a
 single legitimate near-threshold flip changes the rest of a free-running
@@ -23,6 +24,10 @@ DEV = "cuda:0"
 FIELD_TOL = 1e-4
 NMSE_TOL = 1e-4
 BAND = 1e-5
+# |g| below this fraction of its rms is zero to FP32 transform precision
+# (about 16 FP32 ulps, the error growth of a 1024-point FFT): no phase, and
+# so no level, is defined there
+ZERO = 1e-6
 
 
 def say(*a):
@@ -54,10 +59,10 @@ def level_check(gpu_lev, ref_lev, g_ref, L):
     """(non-exempt mismatches, exempt mismatches); prints each non-exempt one."""
     mism = np.asarray(gpu_lev, np.int64) != np.asarray(ref_lev, np.int64)
     margin = slm.boundary_margin(g_ref, L)
-    exempt = mism & (margin < BAND)
+    rms = np.sqrt(np.mean(np.abs(g_ref) ** 2))
+    exempt = mism & ((margin < BAND) | (np.abs(g_ref) < ZERO * rms))
     bad = mism & ~exempt
     if bad.any():
-        rms = np.sqrt(np.mean(np.abs(g_ref) ** 2))
         for y, x in zip(*np.nonzero(bad)):
             a = abs(g_ref[y, x])
             say(f"  mismatch at ({y},{x}): margin {margin[y, x]:.3e} rad, |g|/rms {a / rms:.3e}, "

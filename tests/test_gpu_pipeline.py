@@ -1,0 +1,104 @@
+"""Persistent pipelined column pass (GPU): the kernel the 1024^2 weighted-GS
+benchmark times and that the large classes of uneven batches run.
+
+hg_gs_batched selects it for 1024^2 (4-column tiles) and 512^2 (8-column
+tiles) GS / weighted GS once a size class holds at least 2048 column tiles:
+8 problems of 1024^2, 32 of 512^2.  Single calls of those sizes take the
+one-tile-per-workgroup column kernels, which the lock-step parity tests pin
+to the oracle.  Here: the first iteration of a batch in lock-step against
+the FP64 oracle on sampled problems, and a 4-iteration batch against the
+same problems called one by one (the two column kernels round differently,
+so NMSE agrees to the parity tolerance and levels up to rare flips at
+decision boundaries).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import hologram, slm
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2008_12214_amd as hg  # noqa: E402
+
+DEV = "cuda:0"
+NMSE_TOL = 1e-4
+BAND = 1e-5
+ZERO = 1e-6  # |g| / rms below which the field is zero to FP32 transform precision
+
+
+def say(*a):
+    print("[gpu-pipeline]", *a, flush=True)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+CASES = [
+    # n, batch, weighted, levels, fresnel   (the first is the benchmark's configuration)
+    (1024, 32, True, 2, False),
+    (1024, 8, False, 8, True),
+    (512, 32, False, 8, True),
+]
+
+
+def _problem(n, b, L, fresnel):
+    T = synth.gaussian_target(n, seed=2, batch_item=b)
+    start = np.random.default_rng(1000 + b).integers(0, L, (n, n)).astype(np.uint8)
+    optics = (synth.WAVELENGTH_M, synth.PITCH_M, synth.fresnel_z(4, b)) if fresnel else (0.0, 0.0, 0.0)
+    return T, start, optics
+
+
+def _batched(n, B, weighted, L, fresnel, iters):
+    probs = [_problem(n, b, L, fresnel) for b in range(B)]
+    lv, nm = hg.hg_gs_batched([dev(p[0]) for p in probs], iters, L, weighted=weighted,
+                              init_levels=[dev(p[1]) for p in probs], optics=[p[2] for p in probs])
+    return probs, [host(x) for x in lv], [host(x) for x in nm]
+
+
+@pytest.mark.parametrize("n,B,weighted,L,fresnel", CASES)
+def test_pipelined_first_iteration_lockstep(n, B, weighted, L, fresnel):
+    say("lock-step", n, B, "wgs" if weighted else "gs", L, "fresnel" if fresnel else "fourier")
+    probs, lv, nm = _batched(n, B, weighted, L, fresnel, 1)
+    for b in (0, B - 1):
+        T, start, optics = probs[b]
+        ref = hologram.gs(T, 1, L, init_levels=start.astype(np.int64), weighted=weighted,
+                          optics=optics if fresnel else None)
+        mism = lv[b].astype(np.int64) != ref["levels"]
+        margin = slm.boundary_margin(ref["g"], L)
+        rms = np.sqrt(np.mean(np.abs(ref["g"]) ** 2))
+        badm = mism & (margin >= BAND) & (np.abs(ref["g"]) >= ZERO * rms)
+        for y, x in zip(*np.nonzero(badm)):
+            a = abs(ref["g"][y, x])
+            say(f"  mismatch ({y},{x}): margin {margin[y, x]:.3e} rad, |g|/rms {a / rms:.3e}, "
+                f"distance/rms {a * np.sin(margin[y, x]) / rms:.3e}")
+        bad = int(np.sum(badm))
+        assert bad == 0, f"problem {b}: {bad} non-exempt level mismatches"
+        err = np.max(np.abs(nm[b] - ref["nmse"]) / ref["nmse"])
+        assert err < NMSE_TOL, (b, err)
+        say(f"  problem {b}: nmse rel err {err:.2e}, exempt flips {int(np.sum(mism))}")
+
+
+@pytest.mark.parametrize("n,B,weighted,L,fresnel", CASES)
+def test_pipelined_batch_matches_single_calls(n, B, weighted, L, fresnel):
+    say("batch vs single calls", n, B, "wgs" if weighted else "gs", L)
+    K = 4
+    probs, lv, nm = _batched(n, B, weighted, L, fresnel, K)
+    for b in (0, B // 2, B - 1):
+        T, start, (lam, p, z) = probs[b]
+        call = hg.hg_wgs if weighted else hg.hg_gs
+        o = call(dev(T), K, L, init_levels=dev(start), wavelength_m=lam, pitch_m=p, z_m=z)
+        nm1, lv1 = host(o["nmse"]), host(o["levels"])
+        err = np.max(np.abs(nm[b] - nm1) / nm1)
+        flips = float(np.mean(lv[b] != lv1))
+        say(f"  problem {b}: nmse rel diff {err:.2e}, level differences {flips:.2e}")
+        assert err < NMSE_TOL, (b, err)
+        assert flips < 1e-3, (b, flips)
+        assert nm[b][-1] < nm[b][0]
