@@ -1095,13 +1095,15 @@ __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int
 // One tile: transform the field in stage Fc with the register-held inputs
 // while tile vtn's field streams into Fn; then load tile vtn's inputs and
 // wait for everything (each wave for its own loads) before the barrier.
-template <int NY, int C, int MODE, int E>
+template <int NY, int C, int MODE, int E, int PAR>
 __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vtn, int total, int tpp,
                                           float2* __restrict__ Fc, float2* __restrict__ Fn, lptr<const float2> tw,
                                           double (&red)[kMaxWaves][4], double (&tot)[4], ColpIn<E>& in) {
   using S = ColpShape<NY, C, E>;
   constexpr int T = S::T, NT = S::NT;
   constexpr bool WGS = MODE == COL_WGS;
+  static_assert(2 * (NT / 64) <= kMaxWaves, "two tiles' per-wave partial slots");
+  static_assert(Plan<NY, E>::ns > 1, "the inverse transform's exchange orders the slot writes before the reads");
   if (vtn < total) colp_prefetch<NY, C, E>(bt, vtn, tpp, Fn);
   if (in.active) {
     const int b = vt / tpp, blk = vt - b * tpp;
@@ -1141,13 +1143,26 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
       }
       v[j] = a2 > 0.f ? cscale(Rr, amp * inv) : make_float2(amp, 0.f);
     }
-    block_sum4_l<NT>(s_ta, s_aa, s_tt, s_w, red, tot);
-    if (threadIdx.x == 0) {
-      double* pp = part_ptr(bt, b, k - 1, blk);
-      pp[0] = tot[0]; pp[1] = tot[1]; pp[2] = tot[2];
-      if (WGS) part_ptr(bt, b, k, blk)[3] = tot[3];
+    // the tile's partial sums: one FP64 sum per wave into this tile's LDS
+    // slots now, added over the waves after the inverse transform, whose
+    // barriers order the slot writes before those reads (alternate tiles use
+    // alternate slots)
+    {
+      constexpr int NW = NT / 64;
+      const double d0 = wave_sum((double)s_ta), d1 = wave_sum((double)s_aa);
+      const double d2 = wave_sum((double)s_tt), d3 = wave_sum((double)s_w);
+      double* slot = red[PAR * NW + (threadIdx.x >> 6)];
+      if ((threadIdx.x & 63) == 0) { slot[0] = d0; slot[1] = d1; slot[2] = d2; slot[3] = d3; }
     }
     fft_lds<NY, E, +1>(v, t, tw, ex);
+    if (threadIdx.x < 4) {
+      constexpr int NW = NT / 64;
+      double acc = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) acc += red[PAR * NW + w][threadIdx.x];
+      if (threadIdx.x < 3) part_ptr(bt, b, k - 1, blk)[threadIdx.x] = acc;
+      else if (WGS) part_ptr(bt, b, k, blk)[3] = acc;
+    }
     gptr<float2> fld = to_global(bt.field + off);
 #pragma unroll
     for (int j = 0; j < E; ++j) fld[tix(t + T * j, u, NX)] = v[j];
@@ -1183,10 +1198,10 @@ void k_colp(Batch bt, int k, int nprob) {
   __syncthreads();
   const lptr<const float2> tw = (lptr<const float2>)TW;
   while (vt < total) {
-    colp_tile<NY, C, MODE, E>(bt, k, vt, vt + NBK, total, tpp, FA, FB, tw, red, tot, in);
+    colp_tile<NY, C, MODE, E, 0>(bt, k, vt, vt + NBK, total, tpp, FA, FB, tw, red, tot, in);
     vt += NBK;
     if (vt >= total) break;
-    colp_tile<NY, C, MODE, E>(bt, k, vt, vt + NBK, total, tpp, FB, FA, tw, red, tot, in);
+    colp_tile<NY, C, MODE, E, 1>(bt, k, vt, vt + NBK, total, tpp, FB, FA, tw, red, tot, in);
     vt += NBK;
   }
 }
