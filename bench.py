@@ -185,7 +185,7 @@ def other_workload(args):
                   "sizes": {str(s): sizes.count(s) for s in sorted(set(sizes))}, "pixels": px, "iters": iters,
                   "slm_levels": levels, "wavelength_m": synth.WAVELENGTH_M, "pitch_m": synth.PITCH_M,
                   "z_m": "uniform [0.1, 0.5]"}
-        kernel = "column pass of Fresnel GS, all size classes (k_col / k_colp)"
+        kernel = "column pass of Fresnel GS, all size classes (k_colq / k_col)"
 
     log(f"{wl}: warmup {args.warmup}, steps {args.steps}")
     for _ in range(max(1, args.warmup)):
@@ -402,7 +402,7 @@ def main():
                    "slm_levels": LEVELS, "target": "gaussian sum, 32 blobs, central window"},
         "roofline": {"bound": "hbm", "achieved": round(col_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(col_gbs / HBM_PEAK_GBS, 4), "traffic": committed_traffic(B),
-                     "kernel": "column pass of weighted GS (persistent pipelined k_colp<1024,4,COL_WGS>)",
+                     "kernel": "column pass of weighted GS (one tile per workgroup, k_colq<1024,4,COL_WGS>)",
                      "bytes_per_launch": int(col_bytes / kt["col_launches"]),
                      "bytes_per_px": round(col_px_bytes, 3), "support_fraction": round(omega, 4),
                      "avg_launch_us": round(col_avg_ms * 1e3, 2)},

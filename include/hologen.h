@@ -197,6 +197,18 @@ hg_status hg_get_launch_config(int ny, int nx, int batch, int* col_tile, int* ro
  * results are identical up to the order of the NMSE partial sums. */
 hg_status hg_set_small_fused(int enable);
 
+/* Kernel of the GS / weighted GS column passes, process-wide:
+ *   0  one column tile per workgroup (the default, unless the environment
+ *      sets HG_COLUMN_KERNEL=persistent or =classic);
+ *   1  a persistent, software-pipelined pass for batches of at least 2048
+ *      column tiles (each workgroup streams its next tile into LDS while it
+ *      transforms the current one);
+ *   2  the classic one-tile kernels only.
+ * Sizes or batches a kind does not cover use the next kind that does.
+ * Results agree to rounding (identical arithmetic; the compiler may contract
+ * it differently in each kernel). */
+hg_status hg_set_column_kernel(int kind);
+
 /* Kernel timing (instrumentation for benchmarks).  While enabled, every
  * launch of a column pass, row pass or set-up kernel made by this process
  * is bracketed by a pair of hipEvents on the stream it is launched on.

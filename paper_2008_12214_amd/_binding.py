@@ -84,6 +84,8 @@ def lib():
         L.hg_set_launch_config.argtypes = [_i, _i, _i, _i, _i]
         L.hg_set_small_fused.restype = _i
         L.hg_set_small_fused.argtypes = [_i]
+        L.hg_set_column_kernel.restype = _i
+        L.hg_set_column_kernel.argtypes = [_i]
         L.hg_get_launch_config.restype = _i
         L.hg_get_launch_config.argtypes = [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]
         L.hg_timing_enable.restype = None
@@ -125,6 +127,14 @@ def hg_autotune(ny, nx, batch=1, device="cuda", stream=None):
 
 def hg_set_launch_config(ny, nx, batch, col_tile, rows_per_group):
     _check(lib().hg_set_launch_config(ny, nx, batch, col_tile, rows_per_group))
+
+
+COLUMN_TILE, COLUMN_PERSISTENT, COLUMN_CLASSIC = 0, 1, 2
+
+
+def hg_set_column_kernel(kind):
+    """Column-pass kernel kind: COLUMN_TILE (default), COLUMN_PERSISTENT or COLUMN_CLASSIC."""
+    _check(lib().hg_set_column_kernel(int(kind)))
 
 
 def hg_set_small_fused(enable):

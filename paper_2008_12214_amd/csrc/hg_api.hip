@@ -407,8 +407,18 @@ static std::atomic<int> g_small_fused{[] {
   return (e && std::string(e) == "off") ? 0 : 1;
 }()};
 
+// Column-pass kernel kind (ColumnKernel): one tile per workgroup unless
+// HG_COLUMN_KERNEL=persistent or =classic, or switched by hg_set_column_kernel.
+static std::atomic<int> g_column_kernel{[] {
+  const char* e = std::getenv("HG_COLUMN_KERNEL");
+  if (e && std::string(e) == "persistent") return (int)hg::CK_PERSISTENT;
+  if (e && std::string(e) == "classic") return (int)hg::CK_CLASSIC;
+  return (int)hg::CK_TILE;
+}()};
+
 namespace hg {
 bool small_enabled() { return g_small_fused.load(std::memory_order_relaxed) != 0; }
+int column_kernel() { return g_column_kernel.load(std::memory_order_relaxed); }
 }  // namespace hg
 
 // Error text shared with the network translation unit (same thread-local
@@ -449,6 +459,13 @@ hg_status hg_timing_read(hg_kernel_times* out) {
   }
   g_timing.marks.clear();
   g_timing.used = 0;
+  return HG_OK;
+}
+
+hg_status hg_set_column_kernel(int kind) {
+  g_err[0] = 0;
+  if (kind < CK_TILE || kind > CK_CLASSIC) return fail(HG_ERR_INVALID_ARG, "kind must be 0, 1 or 2");
+  g_column_kernel.store(kind, std::memory_order_relaxed);
   return HG_OK;
 }
 

@@ -995,9 +995,8 @@ __device__ __forceinline__ const float* pin_uniform_ptr(const float* p) {
   return reinterpret_cast<const float*>(((uint64_t)hi << 32) | lo);
 }
 
-// Elements per thread of the pipelined transforms (the 16 of every other
-// pass; an 8-element variant with 512-thread workgroups is compiled for
-// comparison, HG_COLP_E=8).
+// Elements per thread of the tile transforms of k_colp / k_colq (the 16 of
+// every other pass).
 constexpr int kColpE = 16;
 
 template <int NY, int C, int E = kColpE>
@@ -1095,9 +1094,11 @@ __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int
 // One tile: transform the field in stage Fc with the register-held inputs
 // while tile vtn's field streams into Fn; then load tile vtn's inputs and
 // wait for everything (each wave for its own loads) before the barrier.
-template <int NY, int C, int MODE, int E, int PAR>
+// LATE: this tile's target and weights are loaded here, after the forward
+// transform, instead of ahead (in.active set by the caller).
+template <int NY, int C, int MODE, int E, int PAR, class TWP, bool LATE = false>
 __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vtn, int total, int tpp,
-                                          float2* __restrict__ Fc, float2* __restrict__ Fn, lptr<const float2> tw,
+                                          float2* __restrict__ Fc, float2* __restrict__ Fn, TWP tw,
                                           double (&red)[kMaxWaves][4], double (&tot)[4], ColpIn<E>& in) {
   using S = ColpShape<NY, C, E>;
   constexpr int T = S::T, NT = S::NT;
@@ -1115,7 +1116,8 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
 #pragma unroll
     for (int j = 0; j < E; ++j) v[j] = Fc[colp_sidx<C>(t + T * j, c)];
     ColExL<C> ex{Fc + c};
-    fft_lds<NY, E, -1>(v, t, tw, ex);
+    fft_stage<NY, E, -1, 0>(v, t, tw, ex);
+    if constexpr (LATE) colp_load_in<NY, C, MODE, E>(bt, k, vt, tpp, in);
     float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f, s_w = 0.f;
     gptr<float> w = nullptr;
     if constexpr (WGS) w = to_global(in.wout);
@@ -1154,7 +1156,7 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
       double* slot = red[PAR * NW + (threadIdx.x >> 6)];
       if ((threadIdx.x & 63) == 0) { slot[0] = d0; slot[1] = d1; slot[2] = d2; slot[3] = d3; }
     }
-    fft_lds<NY, E, +1>(v, t, tw, ex);
+    fft_stage<NY, E, +1, 0>(v, t, tw, ex);
     if (threadIdx.x < 4) {
       constexpr int NW = NT / 64;
       double acc = 0.0;
@@ -1204,6 +1206,30 @@ void k_colp(Batch bt, int k, int nprob) {
     colp_tile<NY, C, MODE, E, 1>(bt, k, vt, vt + NBK, total, tpp, FB, FA, tw, red, tot, in);
     vt += NBK;
   }
+}
+
+// One column tile per workgroup (the row pass's scheme): the pipelined
+// pass's tile work without persistence, one LDS stage, twiddles from the
+// global table, and at most 128 registers so that four workgroups share a
+// CU and hide each other's loads.
+template <int NY, int C, int MODE, int E = kColpE>
+__global__ __launch_bounds__(C * (NY / E), 4)
+void k_colq(Batch bt, int k, int nprob) {
+  using S = ColpShape<NY, C, E>;
+  static_assert(S::NT == 256, "four 4-wave workgroups per CU");
+  __shared__ float2 FA[S::FE];
+  __shared__ double red[kMaxWaves][4];
+  __shared__ double tot[4];
+  const int tpp = bt.nx / C, total = tpp * nprob;
+  const int vt = xcd_tile(blockIdx.x, gridDim.x);
+  if (vt >= total) return;  // uniform per block
+  colp_prefetch<NY, C, E>(bt, vt, tpp, FA);
+  ColpIn<E> in;
+  colp_load_in<NY, C, MODE, E>(bt, k, vt, tpp, in);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  colp_tile<NY, C, MODE, E, 0, decltype(launder(to_global(bt.tw_y))), false>(
+      bt, k, vt, total, total, tpp, FA, FA, launder(to_global(bt.tw_y)), red, tot, in);
 }
 
 // Copy the final weights of problems that passed their own weight array back

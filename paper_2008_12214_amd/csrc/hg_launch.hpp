@@ -31,25 +31,14 @@ __host__ __device__ constexpr bool rpb_ok(int N, int RPB) {
   return (RPB * T == 128 || RPB * T == 256) || (T >= 256 && RPB == 1) || (T == 128 && RPB == 4);
 }
 
-// The persistent pipelined column pass (k_colp) runs GS / weighted GS column
-// passes where it is compiled; HG_COLUMN_KERNEL=classic selects the
-// one-tile-per-workgroup kernels instead (for comparison).
-inline bool colp_enabled() {
-  static const int on = [] {
-    const char* e = std::getenv("HG_COLUMN_KERNEL");
-    return (e && std::string(e) == "classic") ? 0 : 1;
-  }();
-  return on != 0;
-}
-
-// Elements per thread of the pipelined pass (HG_COLP_E=8 for comparison).
-inline int colp_elements() {
-  static const int e = [] {
-    const char* v = std::getenv("HG_COLP_E");
-    return (v && std::string(v) == "8") ? 8 : kColpE;
-  }();
-  return e;
-}
+// Kernel of the GS / weighted GS column passes (hg_set_column_kernel):
+//   CK_TILE        one column tile per workgroup (k_colq) where its
+//                  256-thread tile is compiled, else as CK_PERSISTENT;
+//   CK_PERSISTENT  the persistent pipelined pass (k_colp) for batches of at
+//                  least 2048 column tiles, else the classic kernels;
+//   CK_CLASSIC     the classic kernels (k_col / k_colw) only.
+enum ColumnKernel { CK_TILE = 0, CK_PERSISTENT = 1, CK_CLASSIC = 2 };
+int column_kernel();
 
 // Small problems (each side 64 or 128) run whole in one workgroup with the
 // field resident in LDS (hg_small.hip) unless switched off (hg_set_small_fused).

@@ -1,15 +1,15 @@
-"""Persistent pipelined column pass (GPU): the kernel the 1024^2 weighted-GS
-benchmark times and that the large classes of uneven batches run.
+"""Column-pass kernels for GS / weighted GS at batch scale (GPU).
 
-hg_gs_batched selects it for 1024^2 (4-column tiles) and 512^2 (8-column
-tiles) GS / weighted GS once a size class holds at least 2048 column tiles:
-8 problems of 1024^2, 32 of 512^2.  Single calls of those sizes take the
-one-tile-per-workgroup column kernels, which the lock-step parity tests pin
-to the oracle.  Here: the first iteration of a batch in lock-step against
-the FP64 oracle on sampled problems, and a 4-iteration batch against the
-same problems called one by one (the two column kernels round differently,
-so NMSE agrees to the parity tolerance and levels up to rare flips at
-decision boundaries).
+Three kinds run these passes (hg_set_column_kernel): one column tile per
+workgroup (the default), a persistent software-pipelined pass for batches
+of at least 2048 column tiles (8 problems of 1024^2, 32 of 512^2), and the
+classic one-tile kernels.  For each of the first two, in the 1024^2 x 32
+weighted binary configuration the benchmark times and in the 1024^2 and
+512^2 Fresnel 8-level classes of the uneven batch: the first iteration in
+lock-step against the FP64 oracle on sampled problems, and a 4-iteration
+batch against the same problems called one by one through the classic
+kernels (the kernels round differently, so NMSE agrees to the parity
+tolerance and levels up to rare flips at decision boundaries).
 """
 import numpy as np
 import pytest
@@ -56,17 +56,33 @@ def _problem(n, b, L, fresnel):
     return T, start, optics
 
 
-def _batched(n, B, weighted, L, fresnel, iters):
+KINDS = {"tile": hg.COLUMN_TILE, "persistent": hg.COLUMN_PERSISTENT}
+
+
+def _with_kind(kind, fn):
+    hg.hg_set_column_kernel(kind)
+    try:
+        return fn()
+    finally:
+        hg.hg_set_column_kernel(hg.COLUMN_TILE)
+
+
+def _batched(n, B, weighted, L, fresnel, iters, kind):
     probs = [_problem(n, b, L, fresnel) for b in range(B)]
-    lv, nm = hg.hg_gs_batched([dev(p[0]) for p in probs], iters, L, weighted=weighted,
-                              init_levels=[dev(p[1]) for p in probs], optics=[p[2] for p in probs])
-    return probs, [host(x) for x in lv], [host(x) for x in nm]
+
+    def run():
+        lv, nm = hg.hg_gs_batched([dev(p[0]) for p in probs], iters, L, weighted=weighted,
+                                  init_levels=[dev(p[1]) for p in probs], optics=[p[2] for p in probs])
+        return [host(x) for x in lv], [host(x) for x in nm]
+    lv, nm = _with_kind(kind, run)
+    return probs, lv, nm
 
 
+@pytest.mark.parametrize("kind", sorted(KINDS))
 @pytest.mark.parametrize("n,B,weighted,L,fresnel", CASES)
-def test_pipelined_first_iteration_lockstep(n, B, weighted, L, fresnel):
-    say("lock-step", n, B, "wgs" if weighted else "gs", L, "fresnel" if fresnel else "fourier")
-    probs, lv, nm = _batched(n, B, weighted, L, fresnel, 1)
+def test_batch_column_pass_first_iteration_lockstep(n, B, weighted, L, fresnel, kind):
+    say("lock-step", kind, n, B, "wgs" if weighted else "gs", L, "fresnel" if fresnel else "fourier")
+    probs, lv, nm = _batched(n, B, weighted, L, fresnel, 1, KINDS[kind])
     for b in (0, B - 1):
         T, start, optics = probs[b]
         ref = hologram.gs(T, 1, L, init_levels=start.astype(np.int64), weighted=weighted,
@@ -86,15 +102,17 @@ def test_pipelined_first_iteration_lockstep(n, B, weighted, L, fresnel):
         say(f"  problem {b}: nmse rel err {err:.2e}, exempt flips {int(np.sum(mism))}")
 
 
+@pytest.mark.parametrize("kind", sorted(KINDS))
 @pytest.mark.parametrize("n,B,weighted,L,fresnel", CASES)
-def test_pipelined_batch_matches_single_calls(n, B, weighted, L, fresnel):
-    say("batch vs single calls", n, B, "wgs" if weighted else "gs", L)
+def test_batch_column_pass_matches_classic_single_calls(n, B, weighted, L, fresnel, kind):
+    say("batch vs classic single calls", kind, n, B, "wgs" if weighted else "gs", L)
     K = 4
-    probs, lv, nm = _batched(n, B, weighted, L, fresnel, K)
+    probs, lv, nm = _batched(n, B, weighted, L, fresnel, K, KINDS[kind])
     for b in (0, B // 2, B - 1):
         T, start, (lam, p, z) = probs[b]
         call = hg.hg_wgs if weighted else hg.hg_gs
-        o = call(dev(T), K, L, init_levels=dev(start), wavelength_m=lam, pitch_m=p, z_m=z)
+        o = _with_kind(hg.COLUMN_CLASSIC, lambda: call(dev(T), K, L, init_levels=dev(start), wavelength_m=lam,
+                                                         pitch_m=p, z_m=z))
         nm1, lv1 = host(o["nmse"]), host(o["levels"])
         err = np.max(np.abs(nm[b] - nm1) / nm1)
         flips = float(np.mean(lv[b] != lv1))
