@@ -1209,14 +1209,16 @@ void k_colp(Batch bt, int k, int nprob) {
 }
 
 // One column tile per workgroup (the row pass's scheme): the pipelined
-// pass's tile work without persistence, one LDS stage, twiddles from the
-// global table, and at most 128 registers so that four workgroups share a
-// CU and hide each other's loads.
+// pass's tile work without persistence, one LDS stage (35 KB) and twiddles
+// from the global table, so that three (weighted: 136 registers) or four
+// (plain GS) workgroups share a CU and hide each other's loads.  Capping the
+// weighted kernel at 128 registers to fit four spills, and measured 9%
+// slower.
 template <int NY, int C, int MODE, int E = kColpE>
-__global__ __launch_bounds__(C * (NY / E), 4)
+__global__ __launch_bounds__(C * (NY / E))
 void k_colq(Batch bt, int k, int nprob) {
   using S = ColpShape<NY, C, E>;
-  static_assert(S::NT == 256, "four 4-wave workgroups per CU");
+  static_assert(S::NT == 256, "4-wave workgroups, several per CU");
   __shared__ float2 FA[S::FE];
   __shared__ double red[kMaxWaves][4];
   __shared__ double tot[4];
