@@ -6,8 +6,8 @@ Follows, in order:
   * Algorithms section: quantisation = adapting the ideal aperture to the
     SLM's states; the "three freedoms" (amplitude, phase, scale).
   * Floating Points section: every image is scaled automatically.
-  * Iterative Fourier Transform Algorithms section: Gerchberg-Saxton (GS)
-    and its weighted variant.
+  * Iterative Fourier Transform Algorithms section: Gerchberg-Saxton (GS),
+    its weighted variant and Liu-Taghizadeh (LT).
   * Time-Averaged Algorithms section: OSPR and adaptive OSPR.
 
 Readings where the paper is silent (each is restated in the design notes):
@@ -18,6 +18,9 @@ Readings where the paper is silent (each is restated in the design notes):
   * GS order: f0 -> [R = forward(f); nmse; R' = T R/|R|; g = backward(R');
     f = P_L(g)] x K -> nmse of the final, projected field.  The initial
     field is an unquantised random phase (or a supplied field / levels).
+  * LT: at iteration i the amplitude is constrained inside the centred
+    square of radius r0 + (i-1) dr pixels and left free (R' = R) outside;
+    nmse is still taken over the whole plane.
   * Weighted GS (the paper names weighting only): a leaky log-domain
     integrator of the amplitude error,
       w_k = clamp(w_{k-1} * ratio / m_{k-1}, 1e-6, 1e6) ** GAMMA,
@@ -115,11 +118,25 @@ def fienup_error(T, A):
     return float(np.sum((np.asarray(A) - np.asarray(T)) ** 2))
 
 
+def lt_window(ny, nx, r):
+    """Liu-Taghizadeh target region of radius r pixels: the centred square
+    |v - ny/2| <= r, |u - nx/2| <= r of the replay plane.  The Iterative
+    Fourier Transform Algorithms section has LT target part of the replay
+    field first and enlarge it every iteration; the paper gives neither the
+    region's shape nor its growth, so both are a reading."""
+    v = np.abs(np.arange(ny) - ny // 2)[:, None]
+    u = np.abs(np.arange(nx) - nx // 2)[None, :]
+    return (v <= r) & (u <= r)
+
+
 def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
-       weighted=False, weights=None, optics=None, batch_item=0):
-    """Gerchberg-Saxton / weighted GS.  Returns a dict of final state.
+       weighted=False, weights=None, optics=None, batch_item=0, lt=None):
+    """Gerchberg-Saxton / weighted GS / Liu-Taghizadeh.  Returns a dict of final state.
 
     optics = (wavelength_m, pitch_m, z_m) selects a Fresnel hologram.
+    lt = (r0, dr) selects Liu-Taghizadeh (GS only): iteration i = 1..K
+    constrains the replay amplitude only inside lt_window(r0 + (i-1) dr)
+    and leaves it free (R' = R) outside.
     Keys: field (f_K), levels (k_K or None), g (the last field before
     projection), replay (R_K), nmse (K+1), fienup (K+1), weights (w_K),
     m (mean of w_K on Omega), target (prepared T).
@@ -139,12 +156,17 @@ def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
     m = float(np.mean(w[omega])) if np.any(omega) else 1.0
     nm, fe = [], []
     g = None
-    for _ in range(iters):
+    if lt is not None and weighted:
+        raise ValueError("Liu-Taghizadeh is a GS variant: weighted=False")
+    for it in range(iters):
         R = forward(f, Q)
         ph, A = _phase_of(R)
         nm.append(_m.nmse(T, A))
         fe.append(fienup_error(T, A))
-        if weighted:
+        if lt is not None:
+            inside = lt_window(ny, nx, lt[0] + it * lt[1])
+            Rp = np.where(inside, T * ph, R)
+        elif weighted:
             ratio = np.maximum(T, WGS_EPS) / np.maximum(A, WGS_EPS)
             w = np.where(omega, np.clip(w * ratio / m, W_MIN, W_MAX) ** WGS_GAMMA, w)
             m = float(np.mean(w[omega]))

@@ -182,3 +182,46 @@ def test_weighting_improves_convergence(L):
     assert wgs["nmse"][-1] < plain["nmse"][-1]
     om = wgs["target"] > 0
     assert 1e-4 < wgs["weights"][om].min() and wgs["weights"][om].max() < 1e2
+
+
+# ---------------------------------------------------------------------------
+# Liu-Taghizadeh (growing target region, amplitude freedom outside it)
+# ---------------------------------------------------------------------------
+def test_lt_full_window_equals_gs():
+    T = synth.gaussian_target(32, seed=4)
+    a = hologram.gs(T, 4, 8, seed=3)
+    b = hologram.gs(T, 4, 8, seed=3, lt=(16, 0))
+    np.testing.assert_array_equal(a["levels"], b["levels"])
+    np.testing.assert_array_equal(a["nmse"], b["nmse"])
+
+
+def test_lt_amplitude_free_outside_and_constrained_inside():
+    """One continuous-phase LT iteration: the field g that is projected has
+    the replay R of the start field outside the window and amplitude T inside
+    (the two parts of R' = where(window, T R/|R|, R))."""
+    T = synth.gaussian_target(32, seed=5)
+    rng = np.random.default_rng(2)
+    f0 = np.exp(2j * np.pi * rng.random((32, 32)))
+    out = hologram.gs(T, 1, 0, init_field=f0, lt=(6, 0))
+    inside = hologram.lt_window(32, 32, 6)
+    R0 = hologram.forward(f0)
+    Rg = hologram.forward(out["g"])
+    Tp = out["target"]
+    np.testing.assert_allclose(Rg[~inside], R0[~inside], atol=1e-12)
+    np.testing.assert_allclose(np.abs(Rg[inside]), Tp[inside], atol=1e-12)
+    assert inside.sum() == 13 * 13
+
+
+def test_lt_becomes_gs_once_the_window_covers_the_plane():
+    """r0 = 8, dr = 4 on 32 x 32: iterations 1 and 2 use radii 8 and 12, the
+    third and later cover the whole plane, so they are GS from the state after
+    two iterations."""
+    T = synth.gaussian_target(32, seed=6)
+    full = hologram.gs(T, 5, 4, seed=9, lt=(8, 4))
+    head = hologram.gs(T, 2, 4, seed=9, lt=(8, 4))
+    tail = hologram.gs(T, 3, 4, init_levels=head["levels"])
+    np.testing.assert_array_equal(full["levels"], tail["levels"])
+    np.testing.assert_allclose(full["nmse"][2:], tail["nmse"], rtol=0, atol=0)
+    # and the growing window differs from plain GS early on
+    gs = hologram.gs(T, 5, 4, seed=9)
+    assert gs["nmse"][1] != full["nmse"][1]
