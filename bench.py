@@ -161,6 +161,28 @@ def other_workload(args):
         config = {"workload": "adaptive_ospr_binary_512x512_24sf", "grid": [n, n], "subframes": sub,
                   "slm_levels": 2, "target": "gaussian sum, 32 blobs, central window"}
         kernel = "column pass of adaptive OSPR (k_col<512,COL_OSPR>)"
+    elif wl == "lt1024":
+        n, B, iters, levels = 1024, 32, 100, 2
+        tg = [torch.from_numpy(synth.gaussian_target(n, seed=2, batch_item=b)).to(dev) for b in range(B)]
+        lv = [torch.empty((n, n), dtype=torch.uint8, device=dev) for _ in range(B)]
+        nm = [torch.empty(iters + 1, dtype=torch.float64, device=dev) for _ in range(B)]
+        arr = (hg_problem * B)()
+        for b in range(B):
+            arr[b] = hg_problem(n, n, levels, iters, 1, 0.0, 0.0, 0.0, tg[b].data_ptr(), lv[b].data_ptr(),
+                                nm[b].data_ptr())
+            arr[b].lt, arr[b].lt_r0, arr[b].lt_dr = 1, 256, 4
+        nb = lib.hg_gs_batched_workspace_size(arr, B)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+
+        def step():
+            check(lib.hg_gs_batched(arr, B, 0, ctypes.c_void_p(ws.data_ptr()), nb, cur_stream()))
+        px = n * n * B
+        units, unit = iters * B, "iter/s"
+        bytes_col = px * (iters * 20 + 12)
+        bytes_row = px * (8 + iters * 16 + 1)
+        config = {"workload": "lt_binary_1024x1024_100it", "batch": B, "grid": [n, n], "iters": iters,
+                  "slm_levels": levels, "lt_r0": 256, "lt_dr": 4, "target": "gaussian sum, 32 blobs, central window"}
+        kernel = "column pass of Liu-Taghizadeh (classic k_colw<1024,4,COL_GS>)"
     else:
         sizes = synth.batch_mix()
         iters, levels = 50, 8
@@ -279,10 +301,11 @@ def main():
     ap.add_argument("--no-b1", action="store_true")
     ap.add_argument("--iters", type=int, default=100,
                     help="iterations per hologram (100 is the workload; fewer only for short profiles)")
-    ap.add_argument("--workload", default="wgs1024", choices=["wgs1024", "gs64", "ospr512", "uneven"],
+    ap.add_argument("--workload", default="wgs1024", choices=["wgs1024", "gs64", "ospr512", "uneven", "lt1024"],
                     help="wgs1024 (default): the headline batch; gs64: one 64^2 8-level GS, latency; "
                          "ospr512: adaptive binary OSPR, 512^2, 24 subframes; uneven: 256 Fresnel problems "
-                         "of four sizes, 8 levels, 50 iterations")
+                         "of four sizes, 8 levels, 50 iterations; lt1024: 32 binary Liu-Taghizadeh problems "
+                         "of 1024^2, 100 iterations, region radius 256 + 4 per iteration")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()

@@ -119,6 +119,20 @@ hg_status hg_wgs(const float* target, int ny, int nx, int iters, int slm_levels,
                  double* nmse_out, float* weights_inout,
                  void* workspace, size_t workspace_bytes, void* stream);
 
+/* Liu-Taghizadeh ("Iterative Fourier Transform Algorithms" section: part of
+ * the replay field is targeted first and the part grows every iteration;
+ * the region's shape and growth are this library's reading).  GS in which
+ * iteration k = 1..iters constrains the amplitude only inside the centred
+ * square |v - ny/2| <= r_k, |u - nx/2| <= r_k, r_k = lt_r0 + (k-1) lt_dr
+ * pixels, and leaves it free outside (R' = R there).  NMSE is taken over the
+ * whole plane.  Once r_k reaches max(ny, nx)/2 the iteration is plain GS.
+ * Arguments as hg_gs, plus lt_r0 >= 0 and lt_dr >= 0.                       */
+hg_status hg_lt(const float* target, int ny, int nx, int iters, int slm_levels, uint64_t seed,
+                const uint8_t* init_levels, const hg_complex* init_field,
+                double wavelength_m, double pitch_m, double z_m, int lt_r0, int lt_dr,
+                uint8_t* levels_out, hg_complex* slm_field_out, hg_complex* replay_out,
+                double* nmse_out, void* workspace, size_t workspace_bytes, void* stream);
+
 /* OSPR / adaptive OSPR with binary-phase subframes ("Time-Averaged
  * Algorithms" section).  Subframe n = 1..subframes: random replay phase
  * phi_n (Philox tag 0x100 + n), h_n = binary projection of
@@ -164,6 +178,9 @@ typedef struct hg_problem {
   double* nmse_out;             /* nullable, iters+1 */
   const uint8_t* init_levels;   /* nullable start levels (slm_levels >= 2) */
   hg_complex* replay_out;       /* nullable centred replay of the final field */
+  int lt;                       /* nonzero: Liu-Taghizadeh as hg_lt (GS only) */
+  int lt_r0, lt_dr;             /* its region radius and growth, pixels >= 0 */
+  int reserved_;                /* 0 */
 } hg_problem;
 
 size_t hg_gs_batched_workspace_size(const hg_problem* problems, int count);

@@ -37,7 +37,8 @@ class hg_problem(ctypes.Structure):
     _fields_ = [("ny", _i), ("nx", _i), ("slm_levels", _i), ("iters", _i), ("seed", _u64),
                 ("wavelength_m", _d), ("pitch_m", _d), ("z_m", _d),
                 ("target", _vp), ("levels_out", _vp), ("nmse_out", _vp),
-                ("init_levels", _vp), ("replay_out", _vp)]
+                ("init_levels", _vp), ("replay_out", _vp),
+                ("lt", _i), ("lt_r0", _i), ("lt_dr", _i), ("reserved_", _i)]
 
 
 _LIB = None
@@ -66,6 +67,9 @@ def lib():
         L.hg_wgs.restype = _i
         L.hg_wgs.argtypes = [_vp, _i, _i, _i, _i, _u64, _vp, _vp, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                              _vp]
+        L.hg_lt.restype = _i
+        L.hg_lt.argtypes = [_vp, _i, _i, _i, _i, _u64, _vp, _vp, _d, _d, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz,
+                            _vp]
         L.hg_ospr.restype = _i
         L.hg_ospr.argtypes = [_vp, _i, _i, _i, _i, _u64, _vp, _vp, _vp, _vp, _sz, _vp]
         L.hg_fresnel_propagate.restype = _i
@@ -195,7 +199,7 @@ def _workspace(nbytes, dev, workspace):
 
 
 def _gs_call(weighted, target, iters, slm_levels, seed, init_levels, init_field, wavelength_m, pitch_m, z_m,
-             weights, want_field, want_replay, stream, workspace):
+             weights, want_field, want_replay, stream, workspace, lt=None):
     torch = _torch()
     ny, nx = target.shape
     _dev_tensor(target, torch.float32, (ny, nx), "target")
@@ -214,11 +218,15 @@ def _gs_call(weighted, target, iters, slm_levels, seed, init_levels, init_field,
     field = torch.empty((ny, nx), dtype=torch.complex64, device=dev) if want_field else None
     replay = torch.empty((ny, nx), dtype=torch.complex64, device=dev) if want_replay else None
     args = [_ptr(target), ny, nx, iters, slm_levels, seed & (2**64 - 1), _ptr(init_levels), _ptr(init_field),
-            float(wavelength_m), float(pitch_m), float(z_m), _ptr(levels), _ptr(field), _ptr(replay), _ptr(nmse)]
+            float(wavelength_m), float(pitch_m), float(z_m)]
+    if lt is not None:
+        args += [int(lt[0]), int(lt[1])]
+    args += [_ptr(levels), _ptr(field), _ptr(replay), _ptr(nmse)]
     if weighted:
         args.append(_ptr(weights))
     args += [_ptr(ws), ws.numel(), _stream(dev, stream)]
-    _check((lib().hg_wgs if weighted else lib().hg_gs)(*args))
+    fn = lib().hg_lt if lt is not None else (lib().hg_wgs if weighted else lib().hg_gs)
+    _check(fn(*args))
     return dict(levels=levels, nmse=nmse, field=field, replay=replay, weights=weights)
 
 
@@ -234,6 +242,14 @@ def hg_wgs(target, iters, slm_levels, seed=0, init_levels=None, init_field=None,
     """Weighted GS on the GPU; `weights` (float32, centred) is read and updated in place."""
     return _gs_call(True, target, iters, slm_levels, seed, init_levels, init_field, wavelength_m, pitch_m, z_m,
                     weights, want_field, want_replay, stream, workspace)
+
+
+def hg_lt(target, iters, slm_levels, lt_r0, lt_dr, seed=0, init_levels=None, init_field=None, wavelength_m=0.0,
+          pitch_m=0.0, z_m=0.0, want_field=False, want_replay=False, stream=None, workspace=None):
+    """Liu-Taghizadeh on the GPU (target square of radius lt_r0 + (k-1) lt_dr pixels at
+    iteration k); returns dict(levels, nmse, field, replay)."""
+    return _gs_call(False, target, iters, slm_levels, seed, init_levels, init_field, wavelength_m, pitch_m, z_m,
+                    None, want_field, want_replay, stream, workspace, lt=(lt_r0, lt_dr))
 
 
 def hg_ospr(target, subframes, adaptive, seed=0, want_accum=False, stream=None, workspace=None):
@@ -285,6 +301,9 @@ def _problem_array(problems):
                             p["nmse_out"].data_ptr() if p.get("nmse_out") is not None else None,
                             p["init_levels"].data_ptr() if p.get("init_levels") is not None else None,
                             p["replay_out"].data_ptr() if p.get("replay_out") is not None else None)
+        lt = p.get("lt")
+        if lt is not None:
+            arr[i].lt, arr[i].lt_r0, arr[i].lt_dr = 1, int(lt[0]), int(lt[1])
     return arr
 
 
@@ -294,7 +313,7 @@ def hg_gs_batched_workspace_size(problems):
 
 
 def hg_gs_batched(targets, iters, slm_levels, seeds=None, optics=None, weighted=False, init_levels=None,
-                  want_replay=False, stream=None, workspace=None):
+                  want_replay=False, stream=None, workspace=None, lt=None):
     """Many GS problems (possibly of different sizes) in one call.
 
     targets: list of float32 CUDA tensors; optics: optional list of
@@ -317,7 +336,8 @@ def hg_gs_batched(targets, iters, slm_levels, seeds=None, optics=None, weighted=
         lam, pit, z = optics[i] if optics is not None else (0.0, 0.0, 0.0)
         probs.append(dict(ny=ny, nx=nx, slm_levels=slm_levels, iters=iters,
                           seed=(seeds[i] if seeds is not None else 0), wavelength_m=lam, pitch_m=pit, z_m=z,
-                          target=t, levels_out=lv, nmse_out=nm, init_levels=il, replay_out=rp))
+                          target=t, levels_out=lv, nmse_out=nm, init_levels=il, replay_out=rp,
+                          lt=(lt[i] if lt is not None else None)))
         levels.append(lv)
         nmses.append(nm)
         replays.append(rp)

@@ -287,10 +287,12 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
   }
   const Cfg cfg = get_cfg(ny, nx, B);
   Batch bt = make_batch(ws, L, ny, nx, cfg.C);
+  bool any_lt = false;  // Liu-Taghizadeh: not in the single-launch small-problem kernel
+  for (const Desc& d : ds) any_lt |= (d.lt != 0);
   upload_descs(const_cast<Desc*>(bt.desc), ds, st);
   bool fresnel = false;
   for (double r : rates) fresnel |= (r != 0.0);
-  if (small_ok(ny, nx) && small_enabled()) {
+  if (small_ok(ny, nx) && small_enabled() && !any_lt) {
     // whole call in one launch, one workgroup per problem
     if (fresnel) launch_chirps(const_cast<float2*>(bt.chirp), ny, nx, rates, st);
     TimeScope ts(TC_COL, st);
@@ -350,12 +352,22 @@ bool optics_ok(double lambda, double pitch, double z) {
          (lambda > 0.0 && pitch > 0.0 && std::isfinite(lambda) && std::isfinite(pitch));
 }
 
+hg_status check_lt(bool weighted, int lt, int r0, int dr) {
+  if (!lt) return HG_OK;
+  if (weighted) return fail(HG_ERR_INVALID_ARG, "Liu-Taghizadeh is a GS variant (not weighted)");
+  if (r0 < 0 || dr < 0) return fail(HG_ERR_INVALID_ARG, "lt_r0=%d and lt_dr=%d must be >= 0", r0, dr);
+  return HG_OK;
+}
+
 hg_status gs_common(bool weighted, const float* target, int ny, int nx, int iters, int L, uint64_t seed,
                     const uint8_t* init_levels, const hg_complex* init_field, double lambda, double pitch,
                     double z, uint8_t* levels_out, hg_complex* field_out, hg_complex* replay_out,
-                    double* nmse_out, float* weights, void* ws, size_t ws_bytes, void* stream) {
+                    double* nmse_out, float* weights, void* ws, size_t ws_bytes, void* stream, int lt = 0,
+                    int lt_r0 = 0, int lt_dr = 0) {
   g_err[0] = 0;
   hg_status s = check_common(target, ny, nx, iters, L);
+  if (s != HG_OK) return s;
+  s = check_lt(weighted, lt, lt_r0, lt_dr);
   if (s != HG_OK) return s;
   if (L >= 2 && !levels_out) return fail(HG_ERR_INVALID_ARG, "levels_out is required when slm_levels >= 2");
   if (init_levels && L < 2) return fail(HG_ERR_INVALID_ARG, "init_levels needs slm_levels >= 2");
@@ -378,6 +390,9 @@ hg_status gs_common(bool weighted, const float* target, int ny, int nx, int iter
   d.item = 0;
   d.L = L;
   d.iters = iters;
+  d.lt = lt ? 1 : 0;
+  d.lt_r0 = lt_r0;
+  d.lt_dr = lt_dr;
   std::vector<Desc> ds{d};
   std::vector<double> rates{chirp_rate(lambda, pitch, z)};
   return run_gs_class(ny, nx, ds, rates, weighted, ws, Lo, static_cast<hipStream_t>(stream));
@@ -501,6 +516,15 @@ hg_status hg_wgs(const float* target, int ny, int nx, int iters, int slm_levels,
                    stream);
 }
 
+hg_status hg_lt(const float* target, int ny, int nx, int iters, int slm_levels, uint64_t seed,
+                const uint8_t* init_levels, const hg_complex* init_field, double wavelength_m, double pitch_m,
+                double z_m, int lt_r0, int lt_dr, uint8_t* levels_out, hg_complex* slm_field_out,
+                hg_complex* replay_out, double* nmse_out, void* workspace, size_t workspace_bytes, void* stream) {
+  return gs_common(false, target, ny, nx, iters, slm_levels, seed, init_levels, init_field, wavelength_m, pitch_m,
+                   z_m, levels_out, slm_field_out, replay_out, nmse_out, nullptr, workspace, workspace_bytes, stream,
+                   1, lt_r0, lt_dr);
+}
+
 hg_status hg_ospr(const float* target, int ny, int nx, int subframes, int adaptive, uint64_t seed,
                   uint8_t* levels_out, double* nmse_out, float* accum_out, void* workspace, size_t workspace_bytes,
                   void* stream) {
@@ -616,6 +640,11 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
       return fail(HG_ERR_INVALID_ARG, "problem %d: Fresnel needs wavelength_m > 0 and pitch_m > 0", i);
     if (p.init_levels && p.slm_levels < 2)
       return fail(HG_ERR_INVALID_ARG, "problem %d: init_levels needs slm_levels >= 2", i);
+    s = check_lt(weighted != 0, p.lt, p.lt_r0, p.lt_dr);
+    if (s != HG_OK) {
+      std::string msg = g_err;
+      return fail(s, "problem %d: %s", i, msg.c_str());
+    }
   }
   const size_t need = hg_gs_batched_workspace_size(probs, count);
   hg_status s = check_ws(workspace, workspace_bytes, need);
@@ -640,6 +669,9 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
       d.item = (uint32_t)i;
       d.L = p.slm_levels;
       d.iters = p.iters;
+      d.lt = p.lt ? 1 : 0;
+      d.lt_r0 = p.lt_r0;
+      d.lt_dr = p.lt_dr;
       ds.push_back(d);
       rates.push_back(chirp_rate(p.wavelength_m, p.pitch_m, p.z_m));
       kmax = std::max(kmax, p.iters);

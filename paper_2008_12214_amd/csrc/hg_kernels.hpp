@@ -35,7 +35,8 @@ struct Desc {
   int L;                      // SLM levels (0 = continuous)
   int iters;                  // GS iterations / OSPR subframes
   int user_weights;           // weights came from the caller
-  int pad_;
+  int lt;                     // Liu-Taghizadeh: constrain only the growing centred square
+  int lt_r0, lt_dr;           //   of radius lt_r0 + (k-1) lt_dr at iteration k
 };
 
 // Launch-uniform view of one size class of problems (passed by value).
@@ -70,6 +71,14 @@ __device__ __forceinline__ double* part_ptr(const Batch& bt, int b, int slot, in
 // (32-bit: a plane has at most 4096^2 elements.)
 __host__ __device__ __forceinline__ uint32_t tix(int y, int x, int nx) {
   return (((uint32_t)y >> 2) * ((uint32_t)nx >> 2) + ((uint32_t)x >> 2)) * 16u + (uint32_t)((y & 3) * 4 + (x & 3));
+}
+
+// Liu-Taghizadeh: whether centred replay index (v, u) lies in the target
+// square of iteration k (always, for other problems).
+__device__ __forceinline__ bool lt_inside(const Desc& d, int k, int v, int u, int ny, int nx) {
+  if (!d.lt) return true;
+  const long long r = (long long)d.lt_r0 + (long long)(k - 1) * d.lt_dr;
+  return abs(v - (ny >> 1)) <= r && abs(u - (nx >> 1)) <= r;
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
@@ -659,6 +668,9 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
           }
         }
         v[j] = a2 > 0.f ? cscale(Rr, amp * inv) : make_float2(amp, 0.f);
+        if constexpr (MODE == COL_GS) {  // Liu-Taghizadeh: amplitude free outside the square
+          if (!lt_inside(d, k, t + T * j, u, NY, NX)) v[j] = cscale(Rr, bt.fwd_scale);
+        }
       }
     }
     block_sum4<NT>(s_ta, s_aa, s_tt, s_w, red, tot);
@@ -853,6 +865,9 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
           }
         }
         mine[lds_pad(row)] = a2 > 0.f ? cscale(Rr, amp * inv) : make_float2(amp, 0.f);
+        if constexpr (MODE == COL_GS) {  // Liu-Taghizadeh: amplitude free outside the square
+          if (!lt_inside(d, k, row, u, NY, NX)) mine[lds_pad(row)] = cscale(Rr, bt.fwd_scale);
+        }
       }
     }
     block_sum4<NT>(s_ta, s_aa, s_tt, s_w, red, tot);  // ends with a barrier
@@ -1059,6 +1074,7 @@ __device__ __forceinline__ void colp_prefetch(const Batch& bt, int vt, int tpp, 
 // and weight columns.
 template <int E> struct ColpIn {
   int active;
+  int lt_r;     // Liu-Taghizadeh: radius of this iteration's target square (-1: whole plane)
   float inv_m;
   float* wout;
   float tv[E], wv[E];
@@ -1073,6 +1089,10 @@ __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int
   const Desc& d = bt.desc[b];
   in.active = d.iters >= k;
   if (!in.active) return;
+  in.lt_r = -1;
+  if constexpr (MODE == COL_GS) {
+    if (d.lt) in.lt_r = (int)min((long long)d.lt_r0 + (long long)(k - 1) * d.lt_dr, (long long)(NY + bt.nx));
+  }
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int u = blk * C + c;
   const int NX = bt.nx;
@@ -1144,6 +1164,10 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
         }
       }
       v[j] = a2 > 0.f ? cscale(Rr, amp * inv) : make_float2(amp, 0.f);
+      if constexpr (MODE == COL_GS) {  // Liu-Taghizadeh: amplitude free outside the square
+        if (in.lt_r >= 0 && max(abs(t + T * j - (NY >> 1)), abs(u - (NX >> 1))) > in.lt_r)
+          v[j] = cscale(Rr, bt.fwd_scale);
+      }
     }
     // the tile's partial sums: one FP64 sum per wave into this tile's LDS
     // slots now, added over the waves after the inverse transform, whose

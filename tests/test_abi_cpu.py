@@ -141,3 +141,20 @@ def test_committed_network_weights_match_the_layout():
     v = np.load(learned.WEIGHTS, allow_pickle=False)
     assert v.dtype == np.float32 and v.shape == (hg.hg_nn_param_count(),)
     assert np.isfinite(v).all()
+
+
+def test_lt_validation():
+    """Liu-Taghizadeh arguments are checked on the host before any launch."""
+    args = lambda r0, dr, lev=FAKE: (FAKE, 64, 64, 3, 8, 1, None, None, 0.0, 0.0, 0.0, r0, dr, lev, None, None, None,
+                                     FAKE, 1 << 30, None)
+    assert L.hg_lt(*args(-1, 2)) == hg.HG_ERR_INVALID_ARG
+    assert "lt_r0" in hg.hg_last_error()
+    assert L.hg_lt(*args(4, -2)) == hg.HG_ERR_INVALID_ARG
+    assert L.hg_lt(*args(4, 2, None)) == hg.HG_ERR_INVALID_ARG  # levels_out required at 8 levels
+    probs = (hg._binding.hg_problem * 1)()
+    probs[0] = hg._binding.hg_problem(64, 64, 8, 3, 1, 0, 0, 0, 0x10000, 0x10000, None)
+    probs[0].lt, probs[0].lt_r0, probs[0].lt_dr = 1, 8, 4
+    assert L.hg_gs_batched(probs, 1, 1, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG  # not weighted
+    assert "weighted" in hg.hg_last_error()
+    probs[0].lt_r0 = -3
+    assert L.hg_gs_batched(probs, 1, 0, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG

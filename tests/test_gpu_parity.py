@@ -228,6 +228,74 @@ def test_small_single_launch_lockstep(ny, nx, weighted, L, optics):
     say(f"  worst nmse rel err {worst:.2e}, exempt level flips {ex}")
 
 
+# ---------------------------------------------------------------------------
+# Liu-Taghizadeh: growing target square, amplitude free outside it
+# ---------------------------------------------------------------------------
+def _lt_lockstep(T, L, r0, dr, steps, optics=None):
+    lam, p, z = optics if optics else (0.0, 0.0, 0.0)
+    lev, worst, exempt = None, 0.0, 0
+    for k in range(steps):
+        r = r0 + k * dr  # iteration k + 1 of the schedule, as a single iteration
+        out = hg.hg_lt(dev(T), 1, L, r, 0, seed=1, init_levels=None if lev is None else dev(lev.astype(np.uint8)),
+                       wavelength_m=lam, pitch_m=p, z_m=z)
+        ref = hologram.gs(T, 1, L, seed=1, init_levels=lev, optics=optics, lt=(r, 0))
+        g_lev = host(out["levels"])
+        bad, ex = level_check(g_lev, ref["levels"], ref["g"], L)
+        exempt += ex
+        assert bad == 0, f"step {k}: {bad} non-exempt level mismatches"
+        e = rel_max(host(out["nmse"]), ref["nmse"])
+        worst = max(worst, e)
+        assert e < NMSE_TOL, f"step {k}: nmse rel err {e}"
+        lev = g_lev.astype(np.int64)
+    return worst, exempt
+
+
+@pytest.mark.parametrize("n,L,r0,dr,steps,optics", [(256, 8, 40, 16, 6, None),
+                                                    (1024, 2, 200, 100, 2, (532e-9, 8e-6, 0.3))])
+def test_lt_lockstep(n, L, r0, dr, steps, optics):
+    say("Liu-Taghizadeh lock-step", n, L, r0, dr, steps, optics)
+    T = synth.gaussian_target(n, seed=8)
+    worst, ex = _lt_lockstep(T, L, r0, dr, steps, optics)
+    say(f"  worst nmse rel err {worst:.2e}, exempt level flips {ex}")
+
+
+def test_lt_continuous_free_running():
+    say("Liu-Taghizadeh L=0 free-running 128x256")
+    T = synth.gaussian_target(256, seed=9, ny=128)
+    out = hg.hg_lt(dev(T), 8, 0, 20, 12, seed=1, want_field=True)
+    ref = hologram.gs(T, 8, 0, seed=1, lt=(20, 12))
+    assert rel_max(host(out["nmse"]), ref["nmse"]) < NMSE_TOL
+    out = hg.hg_lt(dev(T), 3, 0, 20, 12, seed=1, want_field=True, want_replay=True)
+    ref = hologram.gs(T, 3, 0, seed=1, lt=(20, 12))
+    assert rel_l2(host(out["field"]), ref["field"]) < FIELD_TOL
+    assert rel_l2(host(out["replay"]), ref["replay"]) < FIELD_TOL
+
+
+def test_lt_call_equals_chained_iterations_and_batch():
+    say("Liu-Taghizadeh: 6 iterations == 6 chained single iterations == batched")
+    T = synth.gaussian_target(256, seed=10)
+    full = hg.hg_lt(dev(T), 6, 8, 30, 20, seed=5)
+    lev, nms = None, []
+    for k in range(6):
+        o = hg.hg_lt(dev(T), 1, 8, 30 + 20 * k, 0, seed=5, init_levels=lev)
+        lev = o["levels"].clone()
+        nms.append(host(o["nmse"]))
+    np.testing.assert_array_equal(host(full["levels"]), host(lev))
+    assert rel_max(host(full["nmse"])[1:], np.array([n[1] for n in nms])) < 1e-8
+    # a batch mixing Liu-Taghizadeh and plain GS problems of one size
+    Ts = [dev(synth.gaussian_target(256, seed=10 + i)) for i in range(4)]
+    starts = [dev(np.random.default_rng(i).integers(0, 8, (256, 256)).astype(np.uint8)) for i in range(4)]
+    lts = [(30, 20), None, (0, 64), None]
+    lv, nm = hg.hg_gs_batched(Ts, 6, 8, init_levels=starts, lt=lts)
+    for i in range(4):
+        if lts[i] is None:
+            o = hg.hg_gs(Ts[i], 6, 8, init_levels=starts[i])
+        else:
+            o = hg.hg_lt(Ts[i], 6, 8, lts[i][0], lts[i][1], init_levels=starts[i])
+        np.testing.assert_array_equal(host(lv[i]), host(o["levels"]), err_msg=str(i))
+        assert rel_max(host(nm[i]), host(o["nmse"])) < 1e-8
+
+
 @pytest.mark.parametrize("rpb", [2, 4])
 def test_gs_fresnel_2048_rows(rpb):
     """2048-wide rows span two waves: a 4-row group staged through LDS with
