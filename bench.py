@@ -315,7 +315,7 @@ def main():
     global ITERS
     ITERS = args.iters
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.workload != "wgs1024":
         other_workload(args)

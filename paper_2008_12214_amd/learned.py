@@ -4,7 +4,7 @@ The iterative algorithms of the paper start from a random phase
 ("Iterative Fourier Transform Algorithms" section).  Here a network
 predicts the replay-plane phase of a target, the SLM start levels are the
 projection of the inverse transform of T e^{i psi}, and a few GS iterations
-refine them; plain GS from a random phase stays the reference and the judge
+refine them; plain GS from a random phase stays the reference and the arbiter
 of NMSE.  Every step runs in the library's kernels (hg_gs_batched,
 hg_replay_phase_init, hg_nn_forward / hg_nn_backward / hg_nn_adam); this
 module only sequences the calls and holds the tensors.
