@@ -125,7 +125,8 @@ def test_propagate_4096_properties():
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("ny,nx,iters,optics", [(64, 64, 50, None), (128, 256, 20, None),
                                                 (256, 128, 10, (532e-9, 8e-6, 0.1)), (1024, 1024, 5, None),
-                                                (128, 128, 10, (532e-9, 8e-6, 0.15))])
+                                                (128, 128, 10, (532e-9, 8e-6, 0.15)), (512, 1024, 4, None),
+                                                (1024, 256, 4, (532e-9, 8e-6, 0.2))])
 def test_gs_continuous_free_running(ny, nx, iters, optics):
     """Free-running: NMSE of every iteration; fields while the trajectories
     have not yet drifted apart (zero-amplitude target regions leave the
