@@ -196,6 +196,26 @@ def other_workload(args):
         config = {"workload": "adaptive_ospr_binary_512x512_24sf", "grid": [n, n], "subframes": sub,
                   "slm_levels": 2, "target": "gaussian sum, 32 blobs, central window"}
         kernel = "column pass of adaptive OSPR (k_col<512,COL_OSPR>)"
+    elif wl == "ospr1024x32":
+        n, B, sub = 1024, 32, 24
+        tg = [torch.from_numpy(synth.gaussian_target(n, seed=3, batch_item=b)).to(dev) for b in range(B)]
+        lv = [torch.empty((sub, n, n), dtype=torch.uint8, device=dev) for _ in range(B)]
+        nm = [torch.empty(sub, dtype=torch.float64, device=dev) for _ in range(B)]
+        P = hg._binding.hg_ospr_problem
+        arr = (P * B)()
+        for b in range(B):
+            arr[b] = P(n, n, 3, tg[b].data_ptr(), lv[b].data_ptr(), nm[b].data_ptr(), None)
+        nb = lib.hg_ospr_batched_workspace_size(arr, B, sub)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+
+        def step():
+            check(lib.hg_ospr_batched(arr, B, sub, 1, ctypes.c_void_p(ws.data_ptr()), nb, cur_stream()))
+        px, units, unit = n * n * B, sub * B, "subframes/s"
+        bytes_col = px * (12 + 28 * (sub - 1) - 4 + 12)
+        bytes_row = px * 17 * sub
+        config = {"workload": "adaptive_ospr_binary_1024x1024_24sf_x32", "batch": B, "grid": [n, n],
+                  "subframes": sub, "slm_levels": 2, "target": "gaussian sum, 32 blobs, central window"}
+        kernel = "column pass of adaptive OSPR (k_colw<1024,4,COL_OSPR>)"
     elif wl == "lt1024":
         n, B, iters, levels = 1024, 32, 100, 2
         tg = [torch.from_numpy(synth.gaussian_target(n, seed=2, batch_item=b)).to(dev) for b in range(B)]
@@ -336,11 +356,13 @@ def main():
     ap.add_argument("--no-b1", action="store_true")
     ap.add_argument("--iters", type=int, default=100,
                     help="iterations per hologram (100 is the workload; fewer only for short profiles)")
-    ap.add_argument("--workload", default="wgs1024", choices=["wgs1024", "gs64", "ospr512", "uneven", "lt1024"],
+    ap.add_argument("--workload", default="wgs1024",
+                    choices=["wgs1024", "gs64", "ospr512", "ospr1024x32", "uneven", "lt1024"],
                     help="wgs1024 (default): the headline batch; gs64: one 64^2 8-level GS, latency; "
                          "ospr512: adaptive binary OSPR, 512^2, 24 subframes; uneven: 256 Fresnel problems "
                          "of four sizes, 8 levels, 50 iterations; lt1024: 32 binary Liu-Taghizadeh problems "
-                         "of 1024^2, 100 iterations, region radius 256 + 4 per iteration")
+                         "of 1024^2, 100 iterations, region radius 256 + 4 per iteration; ospr1024x32: 32 "
+                         "adaptive binary OSPR problems of 1024^2, 24 subframes, in one call")
     ap.add_argument("--context", action="store_true",
                     help="also time the same loop as unfused torch.fft (rocFFT) ops, for context")
     ap.add_argument("--copy-calibration", action="store_true",

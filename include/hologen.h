@@ -183,6 +183,24 @@ typedef struct hg_problem {
   int reserved_;                /* 0 */
 } hg_problem;
 
+/* Many OSPR / adaptive OSPR problems in one call (the same subframes
+ * for all; problems grouped by size as in hg_gs_batched, one batched
+ * launch per pass; Philox item = index in the array).  Per problem as
+ * hg_ospr: levels_out [subframes][ny][nx] required, nmse_out and
+ * accum_out nullable.                                                       */
+typedef struct hg_ospr_problem {
+  int ny, nx;
+  uint64_t seed;
+  const float* target;
+  uint8_t* levels_out;
+  double* nmse_out;
+  float* accum_out;
+} hg_ospr_problem;
+
+size_t hg_ospr_batched_workspace_size(const hg_ospr_problem* problems, int count, int subframes);
+hg_status hg_ospr_batched(const hg_ospr_problem* problems, int count, int subframes, int adaptive,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
 size_t hg_gs_batched_workspace_size(const hg_problem* problems, int count);
 hg_status hg_gs_batched(const hg_problem* problems, int count, int weighted,
                         void* workspace, size_t workspace_bytes, void* stream);

@@ -41,6 +41,11 @@ class hg_problem(ctypes.Structure):
                 ("lt", _i), ("lt_r0", _i), ("lt_dr", _i), ("reserved_", _i)]
 
 
+class hg_ospr_problem(ctypes.Structure):
+    _fields_ = [("ny", _i), ("nx", _i), ("seed", _u64), ("target", _vp), ("levels_out", _vp),
+                ("nmse_out", _vp), ("accum_out", _vp)]
+
+
 _LIB = None
 
 
@@ -72,6 +77,10 @@ def lib():
                             _vp]
         L.hg_ospr.restype = _i
         L.hg_ospr.argtypes = [_vp, _i, _i, _i, _i, _u64, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.hg_ospr_batched_workspace_size.restype = _sz
+        L.hg_ospr_batched_workspace_size.argtypes = [ctypes.POINTER(hg_ospr_problem), _i, _i]
+        L.hg_ospr_batched.restype = _i
+        L.hg_ospr_batched.argtypes = [ctypes.POINTER(hg_ospr_problem), _i, _i, _i, _vp, _sz, _vp]
         L.hg_fresnel_propagate.restype = _i
         L.hg_fresnel_propagate.argtypes = [_vp, _vp, _i, _i, _d, _d, _d, _i, _vp, _sz, _vp]
         L.hg_random_phase.restype = _i
@@ -265,6 +274,31 @@ def hg_ospr(target, subframes, adaptive, seed=0, want_accum=False, stream=None, 
     _check(lib().hg_ospr(_ptr(target), ny, nx, subframes, int(bool(adaptive)), seed & (2**64 - 1), _ptr(levels),
                          _ptr(nmse), _ptr(accum), _ptr(ws), ws.numel(), _stream(dev, stream)))
     return dict(levels=levels, nmse=nmse, accum=accum)
+
+
+def hg_ospr_batched(targets, subframes, adaptive, seeds=None, want_accum=False, stream=None, workspace=None):
+    """Many OSPR / adaptive OSPR problems (possibly of different sizes) in one call;
+    returns (levels, nmse, accum) lists (accum entries None unless want_accum)."""
+    torch = _torch()
+    dev = targets[0].device
+    arr = (hg_ospr_problem * len(targets))()
+    levels, nmses, accs = [], [], []
+    for i, t in enumerate(targets):
+        ny, nx = t.shape
+        _dev_tensor(t, torch.float32, (ny, nx), f"targets[{i}]")
+        lv = torch.empty((subframes, ny, nx), dtype=torch.uint8, device=dev)
+        nm = torch.empty(subframes, dtype=torch.float64, device=dev)
+        ac = torch.empty((ny, nx), dtype=torch.float32, device=dev) if want_accum else None
+        arr[i] = hg_ospr_problem(ny, nx, (seeds[i] if seeds is not None else 0) & (2**64 - 1), t.data_ptr(),
+                                 lv.data_ptr(), nm.data_ptr(), ac.data_ptr() if ac is not None else None)
+        levels.append(lv)
+        nmses.append(nm)
+        accs.append(ac)
+    nbytes = int(lib().hg_ospr_batched_workspace_size(arr, len(targets), subframes))
+    ws = _workspace(nbytes, dev, workspace)
+    _check(lib().hg_ospr_batched(arr, len(targets), subframes, int(bool(adaptive)), _ptr(ws), ws.numel(),
+                                 _stream(dev, stream)))
+    return levels, nmses, accs
 
 
 def hg_fresnel_propagate(field, wavelength_m=0.0, pitch_m=0.0, z_m=0.0, direction=1, out=None, stream=None,

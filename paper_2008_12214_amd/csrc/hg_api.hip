@@ -325,6 +325,26 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
   return check_launch();
 }
 
+// Whole OSPR / adaptive OSPR pipeline for one size class: B problems with
+// the same number of subframes, one batched launch per pass.
+hg_status run_ospr_class(int ny, int nx, const std::vector<Desc>& ds, int subframes, int adaptive, void* ws,
+                         const Layout& L, hipStream_t st) {
+  const int B = (int)ds.size();
+  const Cfg cfg = get_cfg(ny, nx, B);
+  Batch bt = make_batch(ws, L, ny, nx, cfg.C);
+  upload_descs(const_cast<Desc*>(bt.desc), ds, st);
+  launch_twiddles(const_cast<float2*>(bt.tw_x), nx, st);
+  if (ny != nx) launch_twiddles(const_cast<float2*>(bt.tw_y), ny, st);
+  launch_setup(bt, cfg.C, B, 0, st);
+  launch_col(bt, cfg.C, B, COL_OSPR_FIRST, 1, adaptive, nullptr, nullptr, st);
+  for (int n = 1; n <= subframes; ++n) {
+    launch_row(bt, cfg.RPB, B, false, LK_BIN, ROW_OSPR, n, nullptr, nullptr, st);
+    launch_col(bt, cfg.C, B, n == subframes ? COL_OSPR_FINAL : COL_OSPR, n + 1, adaptive, nullptr, nullptr, st);
+  }
+  hipLaunchKernelGGL(k_finish, dim3(B, (subframes + 255) / 256), dim3(256), 0, st, bt, B, 1);
+  return check_launch();
+}
+
 hg_status check_ws(void* ws, size_t bytes, size_t need) {
   if (!ws) return fail(HG_ERR_WORKSPACE, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(HG_ERR_WORKSPACE, "workspace not 256-byte aligned");
@@ -403,7 +423,8 @@ struct ClassPlan {
   std::vector<std::pair<int, int>> order;
   std::map<std::pair<int, int>, std::vector<int>> members;
 };
-ClassPlan plan_classes(const hg_problem* probs, int count) {
+template <class P>
+ClassPlan plan_classes(const P* probs, int count) {
   ClassPlan cp;
   for (int i = 0; i < count; ++i) {
     auto key = std::make_pair(probs[i].ny, probs[i].nx);
@@ -535,7 +556,6 @@ hg_status hg_ospr(const float* target, int ny, int nx, int subframes, int adapti
   const Layout Lo = make_layout(HG_OP_OSPR, ny, nx, 1, subframes);
   s = check_ws(workspace, workspace_bytes, Lo.total);
   if (s != HG_OK) return s;
-  hipStream_t st = static_cast<hipStream_t>(stream);
   Desc d{};
   d.target = target;
   d.levels_out = levels_out;
@@ -544,19 +564,59 @@ hg_status hg_ospr(const float* target, int ny, int nx, int subframes, int adapti
   d.seed = seed;
   d.L = 2;
   d.iters = subframes;
-  const Cfg cfg = get_cfg(ny, nx, 1);
-  Batch bt = make_batch(workspace, Lo, ny, nx, cfg.C);
-  upload_descs(const_cast<Desc*>(bt.desc), {d}, st);
-  launch_twiddles(const_cast<float2*>(bt.tw_x), nx, st);
-  if (ny != nx) launch_twiddles(const_cast<float2*>(bt.tw_y), ny, st);
-  launch_setup(bt, cfg.C, 1, 0, st);
-  launch_col(bt, cfg.C, 1, COL_OSPR_FIRST, 1, adaptive, nullptr, nullptr, st);
-  for (int n = 1; n <= subframes; ++n) {
-    launch_row(bt, cfg.RPB, 1, false, LK_BIN, ROW_OSPR, n, nullptr, nullptr, st);
-    launch_col(bt, cfg.C, 1, n == subframes ? COL_OSPR_FINAL : COL_OSPR, n + 1, adaptive, nullptr, nullptr, st);
+  return run_ospr_class(ny, nx, {d}, subframes, adaptive, workspace, Lo, static_cast<hipStream_t>(stream));
+}
+
+size_t hg_ospr_batched_workspace_size(const hg_ospr_problem* probs, int count, int subframes) {
+  if (!probs || count < 1 || subframes < 1) return 0;
+  for (int i = 0; i < count; ++i)
+    if (!pow2_in_range(probs[i].ny) || !pow2_in_range(probs[i].nx)) return 0;
+  const ClassPlan cp = plan_classes(probs, count);
+  size_t total = 0;
+  for (auto& key : cp.order)
+    total += make_layout(HG_OP_OSPR, key.first, key.second, (int)cp.members.at(key).size(), subframes).total;
+  return total;
+}
+
+hg_status hg_ospr_batched(const hg_ospr_problem* probs, int count, int subframes, int adaptive, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!probs || count < 1) return fail(HG_ERR_INVALID_ARG, "problems is NULL or count < 1");
+  for (int i = 0; i < count; ++i) {
+    hg_status s = check_common(probs[i].target, probs[i].ny, probs[i].nx, subframes, 2);
+    if (s != HG_OK) {
+      std::string msg = g_err;
+      return fail(s, "problem %d: %s", i, msg.c_str());
+    }
+    if (!probs[i].levels_out) return fail(HG_ERR_INVALID_ARG, "problem %d: levels_out is required", i);
   }
-  hipLaunchKernelGGL(k_finish, dim3(1, (subframes + 255) / 256), dim3(256), 0, st, bt, 1, 1);
-  return check_launch();
+  const size_t need = hg_ospr_batched_workspace_size(probs, count, subframes);
+  hg_status s = check_ws(workspace, workspace_bytes, need);
+  if (s != HG_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const ClassPlan cp = plan_classes(probs, count);
+  size_t off = 0;
+  for (auto& key : cp.order) {
+    const std::vector<int>& idx = cp.members.at(key);
+    std::vector<Desc> ds;
+    for (int i : idx) {
+      Desc d{};
+      d.target = probs[i].target;
+      d.levels_out = probs[i].levels_out;
+      d.nmse_out = probs[i].nmse_out;
+      d.accum_out = probs[i].accum_out;
+      d.seed = probs[i].seed;
+      d.item = (uint32_t)i;
+      d.L = 2;
+      d.iters = subframes;
+      ds.push_back(d);
+    }
+    const Layout Lo = make_layout(HG_OP_OSPR, key.first, key.second, (int)idx.size(), subframes);
+    s = run_ospr_class(key.first, key.second, ds, subframes, adaptive, static_cast<char*>(workspace) + off, Lo, st);
+    if (s != HG_OK) return s;
+    off += Lo.total;
+  }
+  return HG_OK;
 }
 
 hg_status hg_fresnel_propagate(const hg_complex* in, hg_complex* out, int ny, int nx, double wavelength_m,

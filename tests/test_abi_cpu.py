@@ -158,3 +158,20 @@ def test_lt_validation():
     assert "weighted" in hg.hg_last_error()
     probs[0].lt_r0 = -3
     assert L.hg_gs_batched(probs, 1, 0, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG
+
+
+def test_ospr_batched_validation():
+    P = hg._binding.hg_ospr_problem
+    probs = (P * 2)()
+    probs[0] = P(64, 64, 1, 0x10000, 0x10000, None, None)
+    probs[1] = P(64, 48, 1, 0x10000, 0x10000, None, None)
+    assert L.hg_ospr_batched_workspace_size(probs, 2, 4) == 0
+    assert L.hg_ospr_batched(probs, 2, 4, 1, FAKE, 1 << 30, None) == hg.HG_ERR_UNSUPPORTED_SIZE
+    assert "problem 1" in hg.hg_last_error()
+    probs[1] = P(128, 64, 1, 0x10000, None, None, None)
+    assert L.hg_ospr_batched(probs, 2, 4, 1, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG  # levels_out
+    probs[1] = P(128, 64, 1, 0x10000, 0x10000, None, None)
+    need = L.hg_ospr_batched_workspace_size(probs, 2, 4)
+    assert need >= L.hg_workspace_size(hg.HG_OP_OSPR, 64, 64, 4) + L.hg_workspace_size(hg.HG_OP_OSPR, 128, 64, 4)
+    assert L.hg_ospr_batched(probs, 2, 4, 1, FAKE, need - 256, None) == hg.HG_ERR_WORKSPACE
+    assert L.hg_ospr_batched(probs, 2, 0, 1, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG  # subframes

@@ -386,6 +386,35 @@ def test_ospr_lockstep(n, subframes, adaptive):
     say(f"  exempt flips {ex_total}, final nmse {nm[-1]:.4f}")
 
 
+def test_ospr_batched_lockstep_and_single_call():
+    """Many OSPR problems of two sizes in one call: sampled problems in lock-step
+    with the oracle (each draws its subframe phases with its own Philox item),
+    and problem 0 equals the single-problem call bit for bit."""
+    say("ospr batched")
+    sizes = [(256, 256)] * 3 + [(512, 256)] * 2
+    seeds = [31 + i for i in range(len(sizes))]
+    Ts = [synth.gaussian_target(nx, seed=3, batch_item=i, ny=ny) for i, (ny, nx) in enumerate(sizes)]
+    sub = 6
+    lv, nm, ac = hg.hg_ospr_batched([dev(T) for T in Ts], sub, True, seeds=seeds, want_accum=True)
+    for i in (0, 4):
+        T = hologram.prepare_target(Ts[i], 2)
+        A = np.zeros_like(T)
+        lev = host(lv[i]).astype(np.int64)
+        nmi = host(nm[i])
+        for n in range(sub):
+            k, g, _, _ = hologram.ospr_subframe(T, A, n + 1, True, seed=seeds[i], batch_item=i)
+            bad, _ = level_check(lev[n], k, g, 2)
+            assert bad == 0, (i, n, bad)
+            h = np.where(lev[n] == 1, -1.0, 1.0)
+            A = A + np.abs(hologram.forward(h)) ** 2
+            e = metrics.nmse(T, np.sqrt(A / (n + 1)))
+            assert abs(nmi[n] - e) / e < NMSE_TOL, (i, n, nmi[n], e)
+        assert rel_l2(host(ac[i]), A) < FIELD_TOL
+    one = hg.hg_ospr(dev(Ts[0]), sub, True, seed=seeds[0], want_accum=True)
+    np.testing.assert_array_equal(host(one["levels"]), host(lv[0]))
+    np.testing.assert_array_equal(host(one["nmse"]), host(nm[0]))
+
+
 # ---------------------------------------------------------------------------
 # batched uneven problems
 # ---------------------------------------------------------------------------
