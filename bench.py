@@ -195,7 +195,7 @@ def other_workload(args):
         bytes_row = px * 17 * sub
         config = {"workload": "adaptive_ospr_binary_512x512_24sf", "grid": [n, n], "subframes": sub,
                   "slm_levels": 2, "target": "gaussian sum, 32 blobs, central window"}
-        kernel = "column pass of adaptive OSPR (k_col<512,COL_OSPR>)"
+        kernel = "column pass of adaptive OSPR (one tile per workgroup, k_colq_ospr<512,8,COL_OSPR>)"
     elif wl == "ospr1024x32":
         n, B, sub = 1024, 32, 24
         tg = [torch.from_numpy(synth.gaussian_target(n, seed=3, batch_item=b)).to(dev) for b in range(B)]
@@ -215,7 +215,7 @@ def other_workload(args):
         bytes_row = px * 17 * sub
         config = {"workload": "adaptive_ospr_binary_1024x1024_24sf_x32", "batch": B, "grid": [n, n],
                   "subframes": sub, "slm_levels": 2, "target": "gaussian sum, 32 blobs, central window"}
-        kernel = "column pass of adaptive OSPR (k_colw<1024,4,COL_OSPR>)"
+        kernel = "column pass of adaptive OSPR (one tile per workgroup, k_colq_ospr<1024,4,COL_OSPR>)"
     elif wl == "lt1024":
         n, B, iters, levels = 1024, 32, 100, 2
         tg = [torch.from_numpy(synth.gaussian_target(n, seed=2, batch_item=b)).to(dev) for b in range(B)]
@@ -237,7 +237,7 @@ def other_workload(args):
         bytes_row = px * (8 + iters * 16 + 1)
         config = {"workload": "lt_binary_1024x1024_100it", "batch": B, "grid": [n, n], "iters": iters,
                   "slm_levels": levels, "lt_r0": 256, "lt_dr": 4, "target": "gaussian sum, 32 blobs, central window"}
-        kernel = "column pass of Liu-Taghizadeh (classic k_colw<1024,4,COL_GS>)"
+        kernel = "column pass of Liu-Taghizadeh (one tile per workgroup, k_colq<1024,4,COL_GS>)"
     else:
         sizes = synth.batch_mix()
         iters, levels = 50, 8

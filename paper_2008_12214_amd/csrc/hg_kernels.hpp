@@ -1258,6 +1258,121 @@ void k_colq(Batch bt, int k, int nprob) {
       bt, k, vt, total, total, tpp, FA, FA, launder(to_global(bt.tw_y)), red, tot, in);
 }
 
+// Element at a 32-bit byte offset from a wave-uniform base: lets the
+// compiler address with a scalar base plus one 32-bit VGPR offset.
+template <class T> __device__ __forceinline__ gptr<T> at_bytes(gptr<T> p, uint32_t b) {
+  return (gptr<T>)((__attribute__((address_space(1))) char*)p + b);
+}
+
+// OSPR column pass, one 4-column tile per workgroup (k_colq's scheme): for
+// subframe n, finish subframe n-1 (forward transform, accumulate A, NMSE
+// partials, feedback) and start subframe n (random replay phase, inverse
+// transform).  The arithmetic is the classic OSPR column pass's.
+template <int NY, int C, int MODE, int E = kColpE>
+__global__ __launch_bounds__(C * (NY / E))
+void k_colq_ospr(Batch bt, int n, int adaptive, int nprob) {
+  using S = ColpShape<NY, C, E>;
+  static_assert(S::NT == 256, "4-wave workgroups, several per CU");
+  static_assert(Plan<NY, E>::ns > 1, "the inverse transform's exchange orders the slot writes before the reads");
+  constexpr int T = S::T, NW = S::NT / 64;
+  constexpr bool FIRST = MODE == COL_OSPR_FIRST, FINAL = MODE == COL_OSPR_FINAL;
+  __shared__ float2 FA[S::FE];
+  __shared__ double red[kMaxWaves][4];
+  const int tpp = bt.nx / C, total = tpp * nprob;
+  const int vt = xcd_tile(blockIdx.x, gridDim.x);
+  if (vt >= total) return;  // uniform per block
+  const int b = vt / tpp, blk = vt - b * tpp;
+  const int c = threadIdx.x % C, t = threadIdx.x / C;
+  const int u = blk * C + c;
+  const int NX = bt.nx;
+  const size_t off = (size_t)b * NY * NX;
+  const Desc& d = bt.desc[b];
+  if constexpr (!FIRST) colp_prefetch<NY, C, E>(bt, vt, tpp, FA);
+  // uniform bases: per element one 32-bit offset serves every plane (rows
+  // t + T j of a 4x4-tiled plane lie j T NX elements apart)
+  static_assert(T % 4 == 0, "row step of whole 4-row groups");
+  gptr<const float> tp = to_global(uni_ptr(bt.tprep + off));
+  gptr<float> acc = to_global(uni_ptr(bt.accum + off));
+  const uint32_t b0 = 4u * tix(t, u, NX), bstep = 4u * (uint32_t)(T * NX);  // float byte offsets
+  float tv[E], av[E];
+  if constexpr (FIRST) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) tv[j] = *at_bytes(tp, b0 + bstep * j);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const auto tw = launder(to_global(bt.tw_y));
+  ColExL<C> ex{FA + c};
+  float2 v[E];
+  if constexpr (!FIRST) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = FA[colp_sidx<C>(t + T * j, c)];
+    fft_stage<NY, E, -1, 0>(v, t, tw, ex);
+    // target and A_{n-2} after the transform: fewer registers live across it
+#pragma unroll
+    for (int j = 0; j < E; ++j) tv[j] = *at_bytes(tp, b0 + bstep * j);
+    if (n == 2) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) av[j] = 0.f;
+    } else {
+#pragma unroll
+      for (int j = 0; j < E; ++j) av[j] = *at_bytes(acc, b0 + bstep * j);
+    }
+    const float inv_prev = 1.0f / (float)(n - 1);
+    float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const float2 R = cscale(v[j], bt.fwd_scale);
+      const float a = av[j] + (R.x * R.x + R.y * R.y);  // A_{n-1}
+      if constexpr (FINAL) {
+        if (d.accum_out) to_global(d.accum_out)[(size_t)(t + T * j) * NX + u] = a;
+      } else {
+        *at_bytes(acc, b0 + bstep * j) = a;
+      }
+      const float Tv = tv[j];
+      const float avg = a * inv_prev;
+      s_ta += Tv * __builtin_amdgcn_sqrtf(avg);
+      s_aa += avg;
+      s_tt += Tv * Tv;
+      if (adaptive) tv[j] = __builtin_amdgcn_sqrtf(fmaxf(0.f, (float)n * Tv * Tv - a));
+    }
+    const double d0 = wave_sum((double)s_ta), d1 = wave_sum((double)s_aa), d2 = wave_sum((double)s_tt);
+    if ((threadIdx.x & 63) == 0) {
+      double* slot = red[threadIdx.x >> 6];
+      slot[0] = d0; slot[1] = d1; slot[2] = d2;
+    }
+  }
+  if constexpr (!FINAL) {
+    // replay phase of subframe n: Philox words over column lines, element
+    // j = g + (E/4) q of this thread in block g's word q
+    int tr = t;
+    asm volatile("" : "+v"(tr));  // keep the generator after the forward transform (register pressure)
+#pragma unroll
+    for (int g = 0; g < E / 4; ++g) {
+      const U64x4 o = philox_line_block(d.seed, d.item, 0x100u + (uint32_t)n, (uint32_t)(tr + T * g), (uint32_t)u);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = g + (E / 4) * q;
+        v[j] = cscale(philox_phasor(u64x4_word(o, q)), tv[j]);
+      }
+    }
+    fft_stage<NY, E, +1, 0>(v, t, tw, ex);
+    gptr<float2> fld = to_global(uni_ptr(bt.field + off));
+#pragma unroll
+    for (int j = 0; j < E; ++j) *at_bytes(fld, 2u * (b0 + bstep * j)) = v[j];
+  } else {
+    __syncthreads();  // the per-wave sums are in
+  }
+  if constexpr (!FIRST) {
+    if (threadIdx.x < 3) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s += red[w][threadIdx.x];
+      part_ptr(bt, b, n - 2, blk)[threadIdx.x] = s;
+    }
+  }
+}
+
 // Copy the final weights of problems that passed their own weight array back
 // to it (natural order from the tiled workspace plane).
 static __global__ void k_weights_out(Batch bt) {

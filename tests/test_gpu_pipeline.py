@@ -1,4 +1,4 @@
-"""Column-pass kernels for GS / weighted GS at batch scale (GPU).
+"""Column-pass kernels for GS / weighted GS (and adaptive OSPR) at batch scale (GPU).
 
 Three kinds run these passes (hg_set_column_kernel): one column tile per
 workgroup (the default), a persistent software-pipelined pass for batches
@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import hologram, slm
+from oracle import hologram, metrics, slm
 
 pytestmark = pytest.mark.gpu
 
@@ -120,3 +120,64 @@ def test_batch_column_pass_matches_classic_single_calls(n, B, weighted, L, fresn
         assert err < NMSE_TOL, (b, err)
         assert flips < 1e-3, (b, flips)
         assert nm[b][-1] < nm[b][0]
+
+
+# ---------------------------------------------------------------------------
+# OSPR column passes at 1024^2 (the batched OSPR benchmark's class)
+# ---------------------------------------------------------------------------
+OSPR_KINDS = {"tile": hg.COLUMN_TILE, "classic": hg.COLUMN_CLASSIC}
+
+
+def _ospr_batch(kind, Ts, sub, seeds):
+    def run():
+        lv, nm, ac = hg.hg_ospr_batched([dev(T) for T in Ts], sub, True, seeds=seeds, want_accum=True)
+        return [host(x) for x in lv], [host(x) for x in nm], [host(x) for x in ac]
+    return _with_kind(kind, run)
+
+
+@pytest.mark.parametrize("kind", sorted(OSPR_KINDS))
+def test_ospr_1024_batch_lockstep(kind):
+    """Adaptive OSPR, 3 problems of 1024^2, 5 subframes: every subframe of
+    the first and last problem in lock-step with the oracle (continuing from
+    the GPU's own binary subframes), the accumulated intensity to the field
+    tolerance."""
+    say("ospr 1024 lock-step", kind)
+    n, B, sub = 1024, 3, 5
+    Ts = [synth.gaussian_target(n, seed=3, batch_item=b) for b in range(B)]
+    seeds = [70 + b for b in range(B)]
+    lv, nm, ac = _ospr_batch(OSPR_KINDS[kind], Ts, sub, seeds)
+    for b in (0, B - 1):
+        T = hologram.prepare_target(Ts[b], 2)
+        A = np.zeros_like(T)
+        lev = lv[b].astype(np.int64)
+        for i in range(sub):
+            k, g, _, _ = hologram.ospr_subframe(T, A, i + 1, True, seed=seeds[b], batch_item=b)
+            mism = lev[i] != k
+            margin = slm.boundary_margin(g, 2)
+            rms = np.sqrt(np.mean(np.abs(g) ** 2))
+            bad = int(np.sum(mism & (margin >= BAND) & (np.abs(g) >= ZERO * rms)))
+            assert bad == 0, (b, i, bad)
+            h = np.where(lev[i] == 1, -1.0, 1.0)
+            A = A + np.abs(hologram.forward(h)) ** 2
+            e = metrics.nmse(T, np.sqrt(A / (i + 1)))
+            assert abs(nm[b][i] - e) / e < NMSE_TOL, (b, i, nm[b][i], e)
+        rel = np.linalg.norm(ac[b] - A) / np.linalg.norm(A)
+        assert rel < 1e-4, (b, rel)
+        say(f"  problem {b}: final nmse {nm[b][-1]:.4f}, accum rel {rel:.2e}")
+
+
+def test_ospr_1024_tile_matches_classic():
+    """The tile and classic OSPR column kernels on the same batch: NMSE to the
+    parity tolerance, levels up to rare decision-boundary flips."""
+    say("ospr 1024 tile vs classic")
+    n, B, sub = 1024, 4, 8
+    Ts = [synth.gaussian_target(n, seed=5, batch_item=b) for b in range(B)]
+    seeds = [90 + b for b in range(B)]
+    lt, nt, at = _ospr_batch(hg.COLUMN_TILE, Ts, sub, seeds)
+    lc, nc, acc = _ospr_batch(hg.COLUMN_CLASSIC, Ts, sub, seeds)
+    for b in range(B):
+        err = np.max(np.abs(nt[b] - nc[b]) / nc[b])
+        flips = float(np.mean(lt[b] != lc[b]))
+        say(f"  problem {b}: nmse rel diff {err:.2e}, level differences {flips:.2e}")
+        assert err < NMSE_TOL, (b, err)
+        assert flips < 1e-3, (b, flips)
