@@ -1311,12 +1311,12 @@ void k_colq_ospr(Batch bt, int n, int adaptive, int nprob) {
     // target and A_{n-2} after the transform: fewer registers live across it
 #pragma unroll
     for (int j = 0; j < E; ++j) tv[j] = *at_bytes(tp, b0 + bstep * j);
-    if (n == 2) {
+    // A_{n-2}: zero for n = 2, where the plane holds no accumulation yet
+    // (loaded anyway and discarded by a select: no branch per element)
 #pragma unroll
-      for (int j = 0; j < E; ++j) av[j] = 0.f;
-    } else {
-#pragma unroll
-      for (int j = 0; j < E; ++j) av[j] = *at_bytes(acc, b0 + bstep * j);
+    for (int j = 0; j < E; ++j) {
+      const float x = *at_bytes(acc, b0 + bstep * j);
+      av[j] = n == 2 ? 0.f : x;
     }
     const float inv_prev = 1.0f / (float)(n - 1);
     float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f;
@@ -1334,7 +1334,9 @@ void k_colq_ospr(Batch bt, int n, int adaptive, int nprob) {
       s_ta += Tv * __builtin_amdgcn_sqrtf(avg);
       s_aa += avg;
       s_tt += Tv * Tv;
-      if (adaptive) tv[j] = __builtin_amdgcn_sqrtf(fmaxf(0.f, (float)n * Tv * Tv - a));
+      // feedback as a select: a branch here makes the compiler copy tv[] per element
+      const float tn = __builtin_amdgcn_sqrtf(fmaxf(0.f, (float)n * Tv * Tv - a));
+      tv[j] = adaptive ? tn : Tv;
     }
     const double d0 = wave_sum((double)s_ta), d1 = wave_sum((double)s_aa), d2 = wave_sum((double)s_tt);
     if ((threadIdx.x & 63) == 0) {
@@ -1345,11 +1347,9 @@ void k_colq_ospr(Batch bt, int n, int adaptive, int nprob) {
   if constexpr (!FINAL) {
     // replay phase of subframe n: Philox words over column lines, element
     // j = g + (E/4) q of this thread in block g's word q
-    int tr = t;
-    asm volatile("" : "+v"(tr));  // keep the generator after the forward transform (register pressure)
 #pragma unroll
     for (int g = 0; g < E / 4; ++g) {
-      const U64x4 o = philox_line_block(d.seed, d.item, 0x100u + (uint32_t)n, (uint32_t)(tr + T * g), (uint32_t)u);
+      const U64x4 o = philox_line_block(d.seed, d.item, 0x100u + (uint32_t)n, (uint32_t)(t + T * g), (uint32_t)u);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int j = g + (E / 4) * q;
