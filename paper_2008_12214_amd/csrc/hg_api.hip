@@ -289,6 +289,7 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
   Batch bt = make_batch(ws, L, ny, nx, cfg.C);
   bool any_lt = false;  // Liu-Taghizadeh: not in the single-launch small-problem kernel
   for (const Desc& d : ds) any_lt |= (d.lt != 0);
+  bt.any_lt = any_lt ? 1 : 0;  // the classic GS column kernels' window instantiation
   upload_descs(const_cast<Desc*>(bt.desc), ds, st);
   bool fresnel = false;
   for (double r : rates) fresnel |= (r != 0.0);

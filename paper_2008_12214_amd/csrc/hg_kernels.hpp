@@ -55,7 +55,7 @@ struct Batch {
   int nblk;             // column tiles per problem (= nx / C)
   int slots;            // partial slots per problem
   float fwd_scale;      // 1/sqrt(nx ny)
-  int pad_;
+  int any_lt;           // some problem of the batch has a Liu-Taghizadeh region
 };
 
 __device__ __forceinline__ double* part_ptr(const Batch& bt, int b, int slot, int blk) {
@@ -73,12 +73,13 @@ __host__ __device__ __forceinline__ uint32_t tix(int y, int x, int nx) {
   return (((uint32_t)y >> 2) * ((uint32_t)nx >> 2) + ((uint32_t)x >> 2)) * 16u + (uint32_t)((y & 3) * 4 + (x & 3));
 }
 
-// Liu-Taghizadeh: whether centred replay index (v, u) lies in the target
-// square of iteration k (always, for other problems).
-__device__ __forceinline__ bool lt_inside(const Desc& d, int k, int v, int u, int ny, int nx) {
-  if (!d.lt) return true;
+// Liu-Taghizadeh: half-width of the target square of iteration k: centred
+// replay index (v, u) is inside when max(|v - ny/2|, |u - nx/2|) is at most
+// this.  Problems without the region get ny + nx, which no index exceeds.
+__device__ __forceinline__ int lt_radius(const Desc& d, int k, int ny, int nx) {
+  if (!d.lt) return ny + nx;
   const long long r = (long long)d.lt_r0 + (long long)(k - 1) * d.lt_dr;
-  return abs(v - (ny >> 1)) <= r && abs(u - (nx >> 1)) <= r;
+  return (int)max(-1LL, min(r, (long long)(ny + nx)));
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
@@ -584,7 +585,9 @@ enum ColMode {
 // weighted GS: amplitude floor (unit-rms units), leak exponent, clamp
 constexpr float kWgsEps = 0.1f, kWgsGamma = 0.7f, kWMin = 1e-6f, kWMax = 1e6f;
 
-template <int NY, int C, int MODE>
+// LT: the GS pass also applies Liu-Taghizadeh regions (a separate instantiation,
+// so that plain GS does not carry the window test's registers).
+template <int NY, int C, int MODE, bool LT = false>
 __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int adaptive, const float2* pin,
                                                        float2* pout) {
   constexpr int E = kE;
@@ -637,6 +640,7 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
       inv_m = (float)((om > 0.0 ? om : 1.0) / wsum);
       w = to_global(bt.wbuf + off);
     }
+    const int ltr = LT ? uni(lt_radius(d, k, NY, NX)) : 0;
 #pragma unroll
     for (int j = 0; j < E; ++j) v[j] = fld[tix(t + T * j, u, NX)];
     fft<NY, E, -1>(v, t, bt.tw_y, ex);
@@ -668,8 +672,9 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
           }
         }
         v[j] = a2 > 0.f ? cscale(Rr, amp * inv) : make_float2(amp, 0.f);
-        if constexpr (MODE == COL_GS) {  // Liu-Taghizadeh: amplitude free outside the square
-          if (!lt_inside(d, k, t + T * j, u, NY, NX)) v[j] = cscale(Rr, bt.fwd_scale);
+        if constexpr (MODE == COL_GS && LT) {  // Liu-Taghizadeh: amplitude free outside the square
+          const bool out = max(abs(t + T * j - (NY >> 1)), abs(u - (NX >> 1))) > ltr;
+          v[j] = out ? cscale(Rr, bt.fwd_scale) : v[j];
         }
       }
     }
@@ -775,7 +780,7 @@ struct WaveColEx {
   __device__ void st(int e, float2 v) { s[e] = v; }
 };
 
-template <int NY, int C, int MODE>
+template <int NY, int C, int MODE, bool LT = false>  // LT as for k_col
 __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int adaptive, const float2* pin,
                                                         float2* pout) {
   constexpr int E = kE, T = NY / E, NT = C * T;
@@ -811,6 +816,7 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
     inv_m = (float)((om > 0.0 ? om : 1.0) / wsum);
     w = to_global(bt.wbuf + off);
   }
+  const int ltr = LT ? uni(lt_radius(d, k, NY, NX)) : 0;
   float2 v[E];
 
   // A + B: forward column transform of the field
@@ -865,8 +871,9 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
           }
         }
         mine[lds_pad(row)] = a2 > 0.f ? cscale(Rr, amp * inv) : make_float2(amp, 0.f);
-        if constexpr (MODE == COL_GS) {  // Liu-Taghizadeh: amplitude free outside the square
-          if (!lt_inside(d, k, row, u, NY, NX)) mine[lds_pad(row)] = cscale(Rr, bt.fwd_scale);
+        if constexpr (MODE == COL_GS && LT) {  // Liu-Taghizadeh: amplitude free outside the square
+          const bool out = max(abs(row - (NY >> 1)), abs(u - (NX >> 1))) > ltr;
+          if (out) mine[lds_pad(row)] = cscale(Rr, bt.fwd_scale);
         }
       }
     }
