@@ -329,6 +329,21 @@ __device__ __forceinline__ int level_index(float2 g, int L) {
   return k >= L ? k - L : k;
 }
 
+// The same decision for L = 4 or 8 without the arctangent: the nearest of
+// the levels k 2 pi / L follows from the signs of g and, inside a quadrant,
+// from comparing |y| with |x| (L = 4: boundary at pi/4) or with tan(pi/8) |x|
+// and |x| with tan(pi/8) |y| (L = 8: boundaries at pi/8 and 3 pi/8).  The
+// product's FP32 rounding moves a boundary by about 1e-7 rad.  g = 0 gives 0.
+__device__ __forceinline__ int level_index_quad(float2 g, int L) {
+  const float ax = fabsf(g.x), ay = fabsf(g.y);
+  constexpr float kTan8 = 0.414213562373095049f;  // tan(pi/8)
+  int q;  // level within the quadrant, 0 nearest the x axis
+  if (L == 8) q = ay <= kTan8 * ax ? 0 : (ax <= kTan8 * ay ? 2 : 1);
+  else q = ay <= ax ? 0 : 1;
+  const int up = g.x < 0.0f ? (L >> 1) - q : q;  // as if y >= 0
+  return g.y < 0.0f ? (L - up) & (L - 1) : up;
+}
+
 __device__ __forceinline__ float2 level_phasor(int k, int L) {
   if (L == 2) return make_float2(k ? -1.0f : 1.0f, 0.0f);
   float s, c;

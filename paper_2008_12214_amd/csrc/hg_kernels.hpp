@@ -408,7 +408,9 @@ __device__ __forceinline__ void lds_to_quad(const float2* lds, gptr<float2> q) {
 //       ROW_PROP_FWD / _BWD: scaled propagation between pin and pout.
 // Waves per SIMD asked of the compiler for the staged 4-row groups: within
 // 128 registers per lane, two 512-thread workgroups of 2048-wide rows (or
-// four 256-thread ones of 1024-wide rows) share a CU.
+// four 256-thread ones of 1024-wide rows) share a CU.  (Fresnel rows with a
+// general level set spill a little under this cap, and still run faster than
+// with one workgroup fewer per CU.)
 template <int NX, int RPB> constexpr int row_min_waves() { return ((NX == 2048 || NX == 1024) && RPB == 4) ? 4 : 1; }
 
 template <int NX, int RPB, bool FRESNEL, int MODE, int LK>
@@ -512,8 +514,9 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
       }
       fft<NX, E, +1>(v, t, bt.tw_x, ex);
       // projection onto the SLM set, one code path per kind of level set
-      // (uniform per block: 0 continuous, 2 binary, 3 any other L) and per
-      // iteration kind (only the last writes levels and the field)
+      // (uniform per block: 0 continuous, 2 binary, 4 four or eight levels,
+      // 3 any other L) and per iteration kind (only the last writes levels
+      // and the field)
       auto project = [&](auto kind, auto wr) {
         constexpr int KIND = decltype(kind)::value;
         constexpr bool WR = decltype(wr)::value;
@@ -526,7 +529,7 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
           if constexpr (KIND == 0) {
             f = unit_phase(g);
           } else {
-            const int k = level_index(g, KIND == 2 ? 2 : L);
+            const int k = KIND == 4 ? level_index_quad(g, L) : level_index(g, KIND == 2 ? 2 : L);
             if constexpr (KIND == 2) f = level_phasor(k, 2);
             else f = lvl[k];
             if constexpr (WR) {
@@ -543,6 +546,7 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
         if constexpr (TAB) {
           if (L == 2) project(std::integral_constant<int, 2>{}, wr);
           else if (L == 0) project(std::integral_constant<int, 0>{}, wr);
+          else if (L == 4 || L == 8) project(std::integral_constant<int, 4>{}, wr);
           else project(std::integral_constant<int, 3>{}, wr);
         } else {
           project(std::integral_constant<int, 2>{}, wr);  // every problem binary

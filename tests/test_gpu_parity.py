@@ -218,6 +218,17 @@ def test_gs_fresnel_lockstep():
     _lockstep(T, 8, 5, weighted=False, optics=(532e-9, 8e-6, synth.fresnel_z(4, 0)))
 
 
+@pytest.mark.parametrize("ny,nx,weighted,L,optics", [(256, 512, False, 4, None), (512, 256, True, 4, (532e-9, 8e-6, 0.15)),
+                                                    (512, 512, False, 8, None)])
+def test_four_and_eight_levels_lockstep(ny, nx, weighted, L, optics):
+    """Four and eight levels through the multi-launch pipeline, whose row pass
+    decides these level sets by quadrant comparisons instead of an angle."""
+    say("row-pass L=4/8 lock-step", ny, nx, "wgs" if weighted else "gs", L, optics)
+    T = synth.gaussian_target(nx, seed=6, ny=ny)
+    worst, ex, _ = _lockstep(T, L, 4, weighted=weighted, optics=optics)
+    say(f"  worst nmse rel err {worst:.2e}, exempt level flips {ex}")
+
+
 @pytest.mark.parametrize("ny,nx,weighted,L,optics", [
     (64, 128, True, 2, None), (128, 64, False, 4, (532e-9, 8e-6, 0.12)),
     (128, 128, True, 8, (532e-9, 8e-6, 0.2)), (128, 128, False, 3, None)])
