@@ -337,6 +337,16 @@ def test_gs_fresnel_2048_rows(rpb):
         hg.hg_set_launch_config(2048, 2048, 1, *saved)
 
 
+def test_wgs_binary_4096_lockstep():
+    """The largest supported plane (4096^2, two columns per tile, one row per
+    workgroup): one weighted binary iteration in lock-step with the FP64
+    oracle, every level and the NMSE values."""
+    say("wgs binary 4096^2 lock-step")
+    T = synth.gaussian_target(4096, seed=9)
+    worst, ex, _ = _lockstep(T, 2, 1, weighted=True)
+    say(f"  nmse rel err {worst:.2e}, exempt level flips {ex}")
+
+
 def test_wgs_binary_1024_full_size_sampled():
     """Headline workload (1024^2, binary, weighted, 100 iterations): lock-step
     on iterations 1-3, then the single 100-iteration call the bench times
