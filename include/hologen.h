@@ -183,11 +183,21 @@ typedef struct hg_problem {
   int reserved_;                /* 0 */
 } hg_problem;
 
-/* Many OSPR / adaptive OSPR problems in one call (the same subframes
- * for all; problems grouped by size as in hg_gs_batched, one batched
- * launch per pass; Philox item = index in the array).  Per problem as
- * hg_ospr: levels_out [subframes][ny][nx] required, nmse_out and
- * accum_out nullable.                                                       */
+/* Many OSPR / adaptive OSPR problems in one call ("Time-Averaged
+ * Algorithms" section; the paper's batch processing of independent
+ * holograms).  Every problem runs the same number of subframes and the same
+ * adaptive flag; the problems are grouped by (ny, nx) as in hg_gs_batched,
+ * one launch per pass for each size.  Problem i draws its subframe phases
+ * with Philox item i and its own seed, so its results equal an hg_ospr call
+ * with that seed only up to that item (problem 0 equals it bit for bit).
+ * Per problem as hg_ospr: levels_out [subframes][ny][nx] required,
+ * nmse_out (subframes doubles) and accum_out ([ny][nx], centred) nullable;
+ * all device pointers owned by the caller.  `problems` is a HOST array of
+ * `count` entries, read during the call only.  workspace: at least
+ * hg_ospr_batched_workspace_size(problems, count, subframes) bytes of device
+ * memory (HG_ERR_WORKSPACE otherwise).  Invalid sizes, count < 1,
+ * subframes < 1 or a missing target or levels_out give
+ * HG_ERR_INVALID_ARG / HG_ERR_UNSUPPORTED_SIZE before anything is enqueued. */
 typedef struct hg_ospr_problem {
   int ny, nx;
   uint64_t seed;
