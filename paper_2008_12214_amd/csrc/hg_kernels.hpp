@@ -318,6 +318,9 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_prepare(Batch bt, int weighte
   const size_t off = (size_t)b * bt.ny * bt.nx;
   float* w = bt.wbuf + off;  // caller's weights are copied in here
   float om = 0.f, ws = 0.f;
+  int rlo = NY, rhi = -1;  // this thread's first and last support row
+  __shared__ int srow[2];  // the tile's (LDS atomics)
+  if (threadIdx.x == 0) { srow[0] = NY; srow[1] = -1; }
   const int um = (bt.nx - u) & (bt.nx - 1);
 #pragma unroll
   for (int j = 0; j < kE; ++j) {
@@ -335,14 +338,22 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_prepare(Batch bt, int weighte
     if (weighted) {
       const float wv = d.user_weights ? d.weights[idx] : 1.0f;
       w[ti] = wv;
-      if (tv > 0.f) { om += 1.f; ws += wv; }
+      if (tv > 0.f) { om += 1.f; ws += wv; rlo = min(rlo, v); rhi = max(rhi, v); }
     }
   }
   if (weighted) {
-    // slot slots-1 field 1: |Omega|; slot 0 field 3: sum of w_0 over Omega
+    // slot slots-1 field 1: |Omega|, fields 2 and 3: the tile's first and
+    // last support row; slot 0 field 3: sum of w_0 over Omega
+    __syncthreads();  // srow initialised
+    atomicMin(&srow[0], rlo);
+    atomicMax(&srow[1], rhi);
     block_sum4<NT>(om, ws, 0.f, 0.f, red, tot);
+    __syncthreads();  // every thread's rows are in
     if (threadIdx.x == 0) {
-      part_ptr(bt, b, bt.slots - 1, blk)[1] = tot[0];
+      double* pp = part_ptr(bt, b, bt.slots - 1, blk);
+      pp[1] = tot[0];
+      pp[2] = (double)srow[0];
+      pp[3] = (double)srow[1];
       part_ptr(bt, b, 0, blk)[3] = tot[1];
     }
   }
@@ -1115,9 +1126,17 @@ __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int
     in.inv_m = bt.invm[b];
     in.wout = bt.wbuf + off;
     gptr<const float> w = to_global(in.wout);
-    if (part_ptr(bt, b, bt.slots - 1, blk)[1] > 0.0) {  // the tile meets the support
+    const double* ps = part_ptr(bt, b, bt.slots - 1, blk);
+    if (ps[1] > 0.0) {  // the tile meets the support
+      // rows outside the tile's support rows [y0, y1] need no weight: their
+      // lanes read row y0's element instead (an L2 hit), so HBM carries the
+      // weights of the support rows only
+      const int y0 = (int)ps[2], y1 = (int)ps[3];
 #pragma unroll
-      for (int j = 0; j < E; ++j) in.wv[j] = w[tix(t + T * j, u, NX)];
+      for (int j = 0; j < E; ++j) {
+        const int row = t + T * j;
+        in.wv[j] = w[tix(row >= y0 && row <= y1 ? row : y0, u, NX)];
+      }
     }
   }
 }
