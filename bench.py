@@ -28,12 +28,23 @@ HBM_PEAK_GBS = 8000.0
 N = 1024
 LEVELS = 2
 # algorithmic HBM bytes per pixel: weighted column pass = field r+w (16) +
-# target r (4) + weights r+w (8) on the target support only (weights
-# elsewhere are never used), i.e. 20 + 8 * support fraction; its final
-# launch (NMSE only) = field r (8) + target r (4); row pass = field r+w (16),
-# + levels w (1) on the last.
-COL_FIXED_BYTES, COL_WEIGHT_BYTES, COL_FINAL_BYTES, ROW_BYTES = 20, 8, 12, 16
+# target r (4) and weights r+w (8) on the target support only (the target is
+# zero elsewhere, which the set-up pass records per tile, and weights there
+# are never used), i.e. 16 + 12 * support fraction; its final launch (NMSE
+# only) = field r (8) + target r (4); row pass = field r+w (16), + levels w
+# (1) on the last.
+COL_FIELD_BYTES, COL_SUPPORT_BYTES, COL_FINAL_BYTES, ROW_BYTES = 16, 12, 12, 16
 ITERS = 100
+
+
+def support_of(T, binary):
+    """Fraction of pixels where the prepared target is nonzero (binary: T or its mirror, after symmetrisation)."""
+    import numpy as np
+    if binary:
+        n0, n1 = T.shape
+        mir = T[(-np.arange(n0)) % n0][:, (-np.arange(n1)) % n1]
+        return float(np.mean((T > 0) | (mir > 0)))
+    return float(np.mean(T > 0))
 
 
 def kernel_source_hash():
@@ -218,7 +229,8 @@ def other_workload(args):
         kernel = "column pass of adaptive OSPR (one tile per workgroup, k_colq_ospr<1024,4,COL_OSPR>)"
     elif wl == "lt1024":
         n, B, iters, levels = 1024, 32, 100, 2
-        tg = [torch.from_numpy(synth.gaussian_target(n, seed=2, batch_item=b)).to(dev) for b in range(B)]
+        tnp = [synth.gaussian_target(n, seed=2, batch_item=b) for b in range(B)]
+        tg = [torch.from_numpy(a).to(dev) for a in tnp]
         lv = [torch.empty((n, n), dtype=torch.uint8, device=dev) for _ in range(B)]
         nm = [torch.empty(iters + 1, dtype=torch.float64, device=dev) for _ in range(B)]
         arr = (hg_problem * B)()
@@ -233,7 +245,9 @@ def other_workload(args):
             check(lib.hg_gs_batched(arr, B, 0, ctypes.c_void_p(ws.data_ptr()), nb, cur_stream()))
         px = n * n * B
         units, unit = iters * B, "iter/s"
-        bytes_col = px * (iters * 20 + 12)
+        # tile column kernel: field r+w 16 + target 4 on its support (binary: symmetrised)
+        om = sum(support_of(a, True) for a in tnp) / B
+        bytes_col = px * (iters * (16 + 4 * om) + 12)
         bytes_row = px * (8 + iters * 16 + 1)
         config = {"workload": "lt_binary_1024x1024_100it", "batch": B, "grid": [n, n], "iters": iters,
                   "slm_levels": levels, "lt_r0": 256, "lt_dr": 4, "target": "gaussian sum, 32 blobs, central window"}
@@ -242,7 +256,8 @@ def other_workload(args):
         sizes = synth.batch_mix()
         iters, levels = 50, 8
         B = len(sizes)
-        tg = [torch.from_numpy(synth.gaussian_target(s, seed=4, batch_item=b)).to(dev) for b, s in enumerate(sizes)]
+        tnp = [synth.gaussian_target(s, seed=4, batch_item=b) for b, s in enumerate(sizes)]
+        tg = [torch.from_numpy(a).to(dev) for a in tnp]
         lv = [torch.empty((s, s), dtype=torch.uint8, device=dev) for s in sizes]
         nm = [torch.empty(iters + 1, dtype=torch.float64, device=dev) for _ in sizes]
         arr = (hg_problem * B)()
@@ -256,7 +271,12 @@ def other_workload(args):
             check(lib.hg_gs_batched(arr, B, 0, ctypes.c_void_p(ws.data_ptr()), nb, cur_stream()))
         px = sum(s * s for s in sizes)
         units, unit = iters, "batch-iter/s"
-        bytes_col = px * (iters * 20 + 12)
+        # 512^2 and 1024^2 run the tile column kernel (target read on its
+        # support only: 16 + 4 omega B/px); 256^2 and 2048^2 the classic
+        # kernels (target read everywhere: 20 B/px)
+        per_iter = sum(s * s * ((16 + 4 * support_of(tnp[b], False)) if s in (512, 1024) else 20)
+                       for b, s in enumerate(sizes))
+        bytes_col = iters * per_iter + 12 * px
         bytes_row = px * (8 + iters * 16 + 1)
         config = {"workload": "batched_uneven_fresnel_8level_50it", "problems": B,
                   "sizes": {str(s): sizes.count(s) for s in sorted(set(sizes))}, "pixels": px, "iters": iters,
@@ -444,7 +464,7 @@ def main():
     hg.hg_timing_enable(False)
     px = N * N * B
     omega = support_fraction(B)
-    col_px_bytes = COL_FIXED_BYTES + COL_WEIGHT_BYTES * omega
+    col_px_bytes = COL_FIELD_BYTES + COL_SUPPORT_BYTES * omega
     col_bytes = args.steps * (ITERS * col_px_bytes + COL_FINAL_BYTES) * px
     # row launches: one initial pass (writes the field, 8 B/px) + ITERS passes
     row_bytes = args.steps * (8 + ITERS * ROW_BYTES + 1) * px

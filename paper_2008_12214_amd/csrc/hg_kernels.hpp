@@ -338,24 +338,24 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_prepare(Batch bt, int weighte
     if (weighted) {
       const float wv = d.user_weights ? d.weights[idx] : 1.0f;
       w[ti] = wv;
-      if (tv > 0.f) { om += 1.f; ws += wv; rlo = min(rlo, v); rhi = max(rhi, v); }
+      if (tv > 0.f) ws += wv;
     }
+    if (tv > 0.f) { om += 1.f; rlo = min(rlo, v); rhi = max(rhi, v); }
   }
-  if (weighted) {
-    // slot slots-1 field 1: |Omega|, fields 2 and 3: the tile's first and
-    // last support row; slot 0 field 3: sum of w_0 over Omega
-    __syncthreads();  // srow initialised
-    atomicMin(&srow[0], rlo);
-    atomicMax(&srow[1], rhi);
-    block_sum4<NT>(om, ws, 0.f, 0.f, red, tot);
-    __syncthreads();  // every thread's rows are in
-    if (threadIdx.x == 0) {
-      double* pp = part_ptr(bt, b, bt.slots - 1, blk);
-      pp[1] = tot[0];
-      pp[2] = (double)srow[0];
-      pp[3] = (double)srow[1];
-      part_ptr(bt, b, 0, blk)[3] = tot[1];
-    }
+  // slot slots-1 field 1: |Omega| of the tile, fields 2 and 3: its first and
+  // last support row (the column passes read no target or weights outside
+  // them); weighted: slot 0 field 3, the sum of w_0 over Omega
+  __syncthreads();  // srow initialised
+  atomicMin(&srow[0], rlo);
+  atomicMax(&srow[1], rhi);
+  block_sum4<NT>(om, ws, 0.f, 0.f, red, tot);
+  __syncthreads();  // every thread's rows are in
+  if (threadIdx.x == 0) {
+    double* pp = part_ptr(bt, b, bt.slots - 1, blk);
+    pp[1] = tot[0];
+    pp[2] = (double)srow[0];
+    pp[3] = (double)srow[1];
+    if (weighted) part_ptr(bt, b, 0, blk)[3] = tot[1];
   }
 }
 
@@ -1120,18 +1120,30 @@ __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int
   const int NX = bt.nx;
   const size_t off = (size_t)b * NY * NX;
   gptr<const float> tp = to_global(bt.tprep + off);
+  // The target is zero outside its support Omega, whose rows in this tile the
+  // set-up pass recorded: a tile that misses Omega reads no target or
+  // weights, one that meets it reads those of its support rows [y0, y1]
+  // (other lanes read row y0's element, an L2 hit, and take 0)
+  const double* ps = part_ptr(bt, b, bt.slots - 1, blk);
+  const bool meets = ps[1] > 0.0;
+  const int y0 = meets ? (int)ps[2] : 0, y1 = meets ? (int)ps[3] : -1;
+  if (meets) {
 #pragma unroll
-  for (int j = 0; j < E; ++j) in.tv[j] = tp[tix(t + T * j, u, NX)];
+    for (int j = 0; j < E; ++j) {
+      const int row = t + T * j;
+      const bool sup = row >= y0 && row <= y1;
+      const float x = tp[tix(sup ? row : y0, u, NX)];
+      in.tv[j] = sup ? x : 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < E; ++j) in.tv[j] = 0.f;
+  }
   if constexpr (MODE == COL_WGS) {
     in.inv_m = bt.invm[b];
     in.wout = bt.wbuf + off;
     gptr<const float> w = to_global(in.wout);
-    const double* ps = part_ptr(bt, b, bt.slots - 1, blk);
-    if (ps[1] > 0.0) {  // the tile meets the support
-      // rows outside the tile's support rows [y0, y1] need no weight: their
-      // lanes read row y0's element instead (an L2 hit), so HBM carries the
-      // weights of the support rows only
-      const int y0 = (int)ps[2], y1 = (int)ps[3];
+    if (meets) {  // weights matter only where the target is nonzero
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         const int row = t + T * j;
