@@ -200,9 +200,12 @@ def other_workload(args):
                               ctypes.c_void_p(nm.data_ptr()), None, ctypes.c_void_p(ws.data_ptr()), nb,
                               cur_stream()))
         px, units, unit = n * n, sub, "subframes/s"
-        # column launches: first (T r 4, field w 8), subframes 2..N (field r+w 16, T 4, accumulator
-        # r+w 8; no read for subframe 2), final (field r 8, T 4); row: field r+w 16 + levels w 1
-        bytes_col = px * (12 + 28 * (sub - 1) - 4 + 12)
+        # column launches: first (T r 4 omega, field w 8), subframes 2..N (field r+w 16, T 4 omega,
+        # accumulator r+w 8; no read for subframe 2), final (field r 8, T 4 omega); T is read on its
+        # support only (omega: support fraction of the symmetrised binary target); row: field r+w 16
+        # + levels w 1
+        om = support_of(T.cpu().numpy(), True)
+        bytes_col = px * (8 + 24 * (sub - 1) - 4 + 8 + 4 * om * (sub + 1))
         bytes_row = px * 17 * sub
         config = {"workload": "adaptive_ospr_binary_512x512_24sf", "grid": [n, n], "subframes": sub,
                   "slm_levels": 2, "target": "gaussian sum, 32 blobs, central window"}
@@ -222,7 +225,8 @@ def other_workload(args):
         def step():
             check(lib.hg_ospr_batched(arr, B, sub, 1, ctypes.c_void_p(ws.data_ptr()), nb, cur_stream()))
         px, units, unit = n * n * B, sub * B, "subframes/s"
-        bytes_col = px * (12 + 28 * (sub - 1) - 4 + 12)
+        om = sum(support_of(x.cpu().numpy(), True) for x in tg) / B  # as for ospr512
+        bytes_col = px * (8 + 24 * (sub - 1) - 4 + 8 + 4 * om * (sub + 1))
         bytes_row = px * 17 * sub
         config = {"workload": "adaptive_ospr_binary_1024x1024_24sf_x32", "batch": B, "grid": [n, n],
                   "subframes": sub, "slm_levels": 2, "target": "gaussian sum, 32 blobs, central window"}

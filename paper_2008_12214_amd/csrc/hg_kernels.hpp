@@ -1336,11 +1336,28 @@ void k_colq_ospr(Batch bt, int n, int adaptive, int nprob) {
   gptr<const float> tp = to_global(uni_ptr(bt.tprep + off));
   gptr<float> acc = to_global(uni_ptr(bt.accum + off));
   const uint32_t b0 = 4u * tix(t, u, NX), bstep = 4u * (uint32_t)(T * NX);  // float byte offsets
+  // the target is zero off its support, whose rows in this tile the set-up
+  // pass recorded: read it on those rows only (other lanes read row y0's
+  // element, an L2 hit, and take 0; a tile off the support reads none)
+  const double* ps = part_ptr(bt, b, bt.slots - 1, blk);
+  const bool meets = ps[1] > 0.0;
+  const int y0 = meets ? (int)ps[2] : 0, y1 = meets ? (int)ps[3] : -1;
+  const uint32_t by0 = 4u * tix(y0, u, NX);
   float tv[E], av[E];
-  if constexpr (FIRST) {
+  auto load_target = [&]() {
+    if (meets) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) tv[j] = *at_bytes(tp, b0 + bstep * j);
-  }
+      for (int j = 0; j < E; ++j) {
+        const bool sup = t + T * j >= y0 && t + T * j <= y1;
+        const float x = *at_bytes(tp, sup ? b0 + bstep * j : by0);
+        tv[j] = sup ? x : 0.f;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < E; ++j) tv[j] = 0.f;
+    }
+  };
+  if constexpr (FIRST) load_target();
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   const auto tw = launder(to_global(bt.tw_y));
@@ -1351,8 +1368,7 @@ void k_colq_ospr(Batch bt, int n, int adaptive, int nprob) {
     for (int j = 0; j < E; ++j) v[j] = FA[colp_sidx<C>(t + T * j, c)];
     fft_stage<NY, E, -1, 0>(v, t, tw, ex);
     // target and A_{n-2} after the transform: fewer registers live across it
-#pragma unroll
-    for (int j = 0; j < E; ++j) tv[j] = *at_bytes(tp, b0 + bstep * j);
+    load_target();
     // A_{n-2}: zero for n = 2, where the plane holds no accumulation yet
     // (loaded anyway and discarded by a select: no branch per element)
 #pragma unroll
