@@ -337,6 +337,20 @@ def test_gs_fresnel_2048_rows(rpb):
         hg.hg_set_launch_config(2048, 2048, 1, *saved)
 
 
+@pytest.mark.parametrize("weighted,L", [(True, 2), (False, 8)])
+def test_sparse_target_lockstep(weighted, L):
+    """A target of a few isolated points at 1024^2: most column tiles miss its
+    support (they read no target), the others meet it on one or two rows.
+    Two iterations in lock-step with the FP64 oracle."""
+    say("sparse target 1024^2 lock-step", "wgs" if weighted else "gs", L)
+    rng = np.random.default_rng(21)
+    T = np.zeros((1024, 1024))
+    ys, xs = rng.integers(0, 1024, 6), rng.integers(0, 1024, 6)
+    T[ys, xs] = rng.uniform(0.5, 1.0, 6)
+    worst, ex, _ = _lockstep(T.astype(np.float32), L, 2, weighted=weighted)
+    say(f"  worst nmse rel err {worst:.2e}, exempt level flips {ex}")
+
+
 def test_wgs_binary_4096_lockstep():
     """The largest supported plane (4096^2, two columns per tile, one row per
     workgroup): one weighted binary iteration in lock-step with the FP64
