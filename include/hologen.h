@@ -47,8 +47,11 @@
  *    must be ordered on one stream.
  *  - Errors: argument checks run on the host before any HIP call; on error
  *    nothing is enqueued and hg_last_error() holds a thread-local message.
- *    A HIP launch failure returns HG_ERR_HIP.  Non-finite results are not
- *    detected asynchronously: they appear as NaN in nmse_out.
+ *    A HIP launch failure returns HG_ERR_HIP.  Non-finite values (a NaN or
+ *    Inf in a target or in caller weights) cannot be reported by the call,
+ *    which returns before the kernels run: the NMSE finisher writes NaN to
+ *    nmse_out and raises a status word in the workspace, which
+ *    hg_numeric_status() reads after the call (HG_ERR_NUMERIC).
  */
 #ifndef HOLOGEN_H
 #define HOLOGEN_H
@@ -67,7 +70,8 @@ typedef enum hg_status {
   HG_ERR_INVALID_ARG = 1,      /* null/inconsistent pointer, bad level count, iters < 1, ... */
   HG_ERR_UNSUPPORTED_SIZE = 2, /* ny or nx not a power of two in [64, 4096]                 */
   HG_ERR_WORKSPACE = 3,        /* workspace null, misaligned or smaller than the query      */
-  HG_ERR_HIP = 4               /* a HIP runtime call or kernel launch failed                */
+  HG_ERR_HIP = 4,              /* a HIP runtime call or kernel launch failed                */
+  HG_ERR_NUMERIC = 5           /* the NMSE sums of a finished call were non-finite          */
 } hg_status;
 
 enum hg_op { HG_OP_GS = 1, HG_OP_WGS = 2, HG_OP_OSPR = 3, HG_OP_PROPAGATE = 4 };
@@ -118,6 +122,32 @@ hg_status hg_wgs(const float* target, int ny, int nx, int iters, int slm_levels,
                  uint8_t* levels_out, hg_complex* slm_field_out, hg_complex* replay_out,
                  double* nmse_out, float* weights_inout,
                  void* workspace, size_t workspace_bytes, void* stream);
+
+/* One iteration from a caller-supplied state, with the intermediate fields
+ * exposed for lock-step comparison ("Iterative Fourier Transform
+ * Algorithms" section: GS, weighted GS or Liu-Taghizadeh).  From the SLM
+ * field f_{k-1} (levels_in for slm_levels >= 2, or field_in; exactly one of
+ * the two) and, when weighted, the weights w_{k-1} in weights_inout (the
+ * lagged mean m_{k-1} is their mean over T > 0, as in hg_wgs), it computes
+ * R_k = forward(f_{k-1}), the replay constraint, g = backward(R'_k) and
+ * f_k = P_L(g), with the kernels of hg_gs / hg_wgs / hg_lt (the column pass
+ * in the instantiation that also stores R_k).
+ *   lt_radius     >= 0: Liu-Taghizadeh square of this radius (GS only);
+ *                 < 0: none
+ *   weights_inout [ny][nx] float, required when weighted: w_{k-1} in, w_k out
+ *   r_out         nullable [ny][nx] complex: R_k, centred, before the constraint
+ *   g_out         nullable [ny][nx] complex: g, SLM plane, before projection
+ *   levels_out    [ny][nx] uint8 levels of f_k (required for slm_levels >= 2)
+ *   field_out     nullable [ny][nx] complex f_k
+ *   nmse_out      nullable 2 doubles: NMSE of R_k and of the replay of f_k
+ * Other arguments, workspace (hg_workspace_size(op, ny, nx, 1)) and errors
+ * as hg_gs / hg_wgs.                                                         */
+hg_status hg_gs_step(const float* target, int ny, int nx, int slm_levels, int weighted,
+                     const uint8_t* levels_in, const hg_complex* field_in,
+                     double wavelength_m, double pitch_m, double z_m, int lt_radius,
+                     float* weights_inout, hg_complex* r_out, hg_complex* g_out,
+                     uint8_t* levels_out, hg_complex* field_out, double* nmse_out,
+                     void* workspace, size_t workspace_bytes, void* stream);
 
 /* Liu-Taghizadeh ("Iterative Fourier Transform Algorithms" section: part of
  * the replay field is targeted first and the part grows every iteration;
@@ -181,6 +211,9 @@ typedef struct hg_problem {
   int lt;                       /* nonzero: Liu-Taghizadeh as hg_lt (GS only) */
   int lt_r0, lt_dr;             /* its region radius and growth, pixels >= 0 */
   int reserved_;                /* 0 */
+  float* weights;               /* weighted calls: nullable [ny][nx] centred weights, read as w_0 and
+                                   overwritten with w_K (as hg_wgs); NULL starts from 1. Ignored
+                                   (may be set) when the call is not weighted */
 } hg_problem;
 
 /* Many OSPR / adaptive OSPR problems in one call ("Time-Averaged
@@ -266,6 +299,15 @@ typedef struct hg_kernel_times {
 } hg_kernel_times;
 void hg_timing_enable(int on);
 hg_status hg_timing_read(hg_kernel_times* out);
+
+/* Numeric status of the last GS / WGS / LT / OSPR call (single or batched)
+ * that used `workspace`: synchronises `stream` (the call's stream), then
+ * returns HG_ERR_NUMERIC if that call's NMSE finisher saw non-finite sums
+ * (its nmse_out holds NaN there), else HG_OK.  The word lives in the first
+ * bytes of the workspace; each call clears it on the stream before its
+ * kernels run, so the answer belongs to the latest call enqueued with that
+ * workspace.  NULL or misaligned workspace: HG_ERR_INVALID_ARG.            */
+hg_status hg_numeric_status(const void* workspace, void* stream);
 
 /* Static text for a status code, and the thread-local detail of the last
  * error raised on this thread ("" if none). */

@@ -159,22 +159,13 @@ def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
     if lt is not None and weighted:
         raise ValueError("Liu-Taghizadeh is a GS variant: weighted=False")
     for it in range(iters):
-        R = forward(f, Q)
-        ph, A = _phase_of(R)
-        nm.append(_m.nmse(T, A))
-        fe.append(fienup_error(T, A))
-        if lt is not None:
-            inside = lt_window(ny, nx, lt[0] + it * lt[1])
-            Rp = np.where(inside, T * ph, R)
-        elif weighted:
-            ratio = np.maximum(T, WGS_EPS) / np.maximum(A, WGS_EPS)
-            w = np.where(omega, np.clip(w * ratio / m, W_MIN, W_MAX) ** WGS_GAMMA, w)
-            m = float(np.mean(w[omega]))
-            Rp = w * T * ph
-        else:
-            Rp = T * ph
-        g = backward(Rp, Q)
-        f, levels = _slm.project(g, L)
+        st = _iterate(T, L, f, Q, weighted, w, m, None if lt is None else lt[0] + it * lt[1])
+        nm.append(_m.nmse(T, st["A"]))
+        fe.append(fienup_error(T, st["A"]))
+        g, f, levels = st["g"], st["field"], st["levels"]
+        if weighted:
+            w = st["weights"]
+            m = float(np.mean(w[omega])) if np.any(omega) else 1.0
     R = forward(f, Q)
     A = np.abs(R)
     nm.append(_m.nmse(T, A))
@@ -183,21 +174,82 @@ def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
                 fienup=np.array(fe), weights=w, m=m, target=T)
 
 
+def ospr_target(T, A_prev, n, adaptive):
+    """Replay amplitude T_n asked of subframe n >= 1 (Time-Averaged Algorithms
+    section: adaptive OSPR feeds back the error accumulated so far).
+
+    Reading: subframe n asks for the intensity still missing once it is
+    added to the n - 1 subframes already shown, so that their average would
+    equal the target: T_n^2 = max(0, n T^2 - A_{n-1}).  Plain OSPR (and the
+    first subframe, A_0 = 0, of either) asks for T itself.
+    """
+    if adaptive and n > 1:
+        return np.sqrt(np.maximum(0.0, n * T * T - A_prev))
+    return np.asarray(T, dtype=np.float64)
+
+
 def ospr_subframe(T, A_prev, n, adaptive, seed=0, batch_item=0):
     """Subframe n >= 1 of (adaptive) OSPR from the accumulated intensity A_{n-1}.
 
     T is the prepared target.  Returns (levels_n, g_n, A_n, nmse_n).
     """
     ny, nx = T.shape
-    if adaptive and n > 1:
-        Tn = np.sqrt(np.maximum(0.0, n * T * T - A_prev))
-    else:
-        Tn = T
+    Tn = ospr_target(T, A_prev, n, adaptive)
     phi = _ph.phase_field(seed, _ph.TAG_OSPR + n, ny, nx, batch_item)
     g = backward(Tn * np.exp(1j * phi))
     h, k = _slm.project(g, 2)
     A = A_prev + np.abs(forward(h)) ** 2
     return k, g, A, _m.nmse(T, np.sqrt(A / n))
+
+
+def gs_step(T, L, f_prev, weighted=False, w_prev=None, optics=None, lt_r=None, next_nmse=True):
+    """One GS / weighted GS / Liu-Taghizadeh iteration from a given state.
+
+    T is the PREPARED target (prepare_target), f_prev the SLM field f_{k-1}
+    and, for weighted GS, w_prev the weights w_{k-1}; the lagged mean
+    m_{k-1} is the mean of w_prev over Omega = {T > 0} (see gs()).  lt_r is
+    the Liu-Taghizadeh square's radius for this iteration (None: no region).
+    Returns a dict: replay (R_k = forward(f_{k-1}), before the constraint),
+    g (backward of the constrained replay, before projection), field (f_k),
+    levels (None for L = 0), weights (w_k or None), nmse (NMSE of R_k) and
+    nmse_next (NMSE of the replay of f_k; None when next_nmse is False, which
+    saves its transform).
+    """
+    T = np.asarray(T, dtype=np.float64)
+    ny, nx = T.shape
+    Q = fresnel_chirp(ny, nx, *optics) if optics is not None else None
+    m = None
+    if weighted:
+        w_prev = np.asarray(w_prev, dtype=np.float64)
+        omega = T > 0
+        m = float(np.mean(w_prev[omega])) if np.any(omega) else 1.0
+    st = _iterate(T, L, np.asarray(f_prev, dtype=np.complex128), Q, weighted, w_prev, m, lt_r)
+    return dict(replay=st["R"], g=st["g"], field=st["field"], levels=st["levels"],
+                weights=st["weights"] if weighted else None, nmse=_m.nmse(T, st["A"]),
+                nmse_next=_m.nmse(T, np.abs(forward(st["field"], Q))) if next_nmse else None)
+
+
+def _iterate(T, L, f, Q, weighted, w, m, lt_r):
+    """The body of one iteration (Iterative Fourier Transform Algorithms
+    section): R = forward(f); replay constraint (GS: R' = T R/|R|, R = 0
+    gives T; weighted GS: the weight update, then R' = w T R/|R|;
+    Liu-Taghizadeh: R' = T R/|R| inside the square of radius lt_r, R' = R
+    outside); g = backward(R'); f_next = P_L(g).  m is the lagged mean
+    m_{k-1} of the weights over Omega."""
+    ny, nx = T.shape
+    R = forward(f, Q)
+    ph, A = _phase_of(R)
+    if lt_r is not None:
+        Rp = np.where(lt_window(ny, nx, lt_r), T * ph, R)
+    elif weighted:
+        ratio = np.maximum(T, WGS_EPS) / np.maximum(A, WGS_EPS)
+        w = np.where(T > 0, np.clip(w * ratio / m, W_MIN, W_MAX) ** WGS_GAMMA, w)
+        Rp = w * T * ph
+    else:
+        Rp = T * ph
+    g = backward(Rp, Q)
+    f_next, levels = _slm.project(g, L)
+    return dict(R=R, A=A, g=g, field=f_next, levels=levels, weights=w)
 
 
 def ospr(T_raw, subframes, adaptive, seed=0, batch_item=0):

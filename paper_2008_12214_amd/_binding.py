@@ -8,7 +8,7 @@ call is enqueued on torch's current stream of that device (or ``stream``).
 import ctypes
 import os
 
-HG_OK, HG_ERR_INVALID_ARG, HG_ERR_UNSUPPORTED_SIZE, HG_ERR_WORKSPACE, HG_ERR_HIP = range(5)
+HG_OK, HG_ERR_INVALID_ARG, HG_ERR_UNSUPPORTED_SIZE, HG_ERR_WORKSPACE, HG_ERR_HIP, HG_ERR_NUMERIC = range(6)
 HG_OP_GS, HG_OP_WGS, HG_OP_OSPR, HG_OP_PROPAGATE = 1, 2, 3, 4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -38,7 +38,7 @@ class hg_problem(ctypes.Structure):
                 ("wavelength_m", _d), ("pitch_m", _d), ("z_m", _d),
                 ("target", _vp), ("levels_out", _vp), ("nmse_out", _vp),
                 ("init_levels", _vp), ("replay_out", _vp),
-                ("lt", _i), ("lt_r0", _i), ("lt_dr", _i), ("reserved_", _i)]
+                ("lt", _i), ("lt_r0", _i), ("lt_dr", _i), ("reserved_", _i), ("weights", _vp)]
 
 
 class hg_ospr_problem(ctypes.Structure):
@@ -72,6 +72,9 @@ def lib():
         L.hg_wgs.restype = _i
         L.hg_wgs.argtypes = [_vp, _i, _i, _i, _i, _u64, _vp, _vp, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                              _vp]
+        L.hg_gs_step.restype = _i
+        L.hg_gs_step.argtypes = [_vp, _i, _i, _i, _i, _vp, _vp, _d, _d, _d, _i, _vp, _vp, _vp, _vp, _vp, _vp,
+                                 _vp, _sz, _vp]
         L.hg_lt.restype = _i
         L.hg_lt.argtypes = [_vp, _i, _i, _i, _i, _u64, _vp, _vp, _d, _d, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz,
                             _vp]
@@ -105,6 +108,8 @@ def lib():
         L.hg_timing_enable.argtypes = [_i]
         L.hg_timing_read.restype = _i
         L.hg_timing_read.argtypes = [ctypes.POINTER(hg_kernel_times)]
+        L.hg_numeric_status.restype = _i
+        L.hg_numeric_status.argtypes = [_vp, _vp]
         L.hg_status_string.restype = ctypes.c_char_p
         L.hg_status_string.argtypes = [_i]
         L.hg_last_error.restype = ctypes.c_char_p
@@ -125,6 +130,12 @@ def hg_last_error():
 def _check(status):
     if status != HG_OK:
         raise HologenError(status, hg_last_error() or hg_status_string(status))
+
+
+def hg_numeric_status(workspace, stream=None):
+    """Raise HologenError(HG_ERR_NUMERIC) if the last call that used `workspace`
+    (a torch uint8 device tensor passed as workspace=...) saw non-finite NMSE sums."""
+    _check(lib().hg_numeric_status(_ptr(workspace), _stream(workspace.device, stream)))
 
 
 def hg_autotune(ny, nx, batch=1, device="cuda", stream=None):
@@ -253,6 +264,38 @@ def hg_wgs(target, iters, slm_levels, seed=0, init_levels=None, init_field=None,
                     weights, want_field, want_replay, stream, workspace)
 
 
+def hg_gs_step(target, slm_levels, levels_in=None, field_in=None, weights=None, lt_radius=-1, wavelength_m=0.0,
+               pitch_m=0.0, z_m=0.0, stream=None, workspace=None):
+    """One GS (weights None) or weighted GS iteration from a given state.
+
+    Returns dict(replay=R_k before the constraint, g=field before projection,
+    levels, field=f_k, nmse=[NMSE of R_k, NMSE of f_k's replay], weights=w_k
+    (the `weights` tensor, updated in place)).
+    """
+    torch = _torch()
+    ny, nx = target.shape
+    _dev_tensor(target, torch.float32, (ny, nx), "target")
+    dev = target.device
+    if levels_in is not None:
+        _dev_tensor(levels_in, torch.uint8, (ny, nx), "levels_in")
+    if field_in is not None:
+        _dev_tensor(field_in, torch.complex64, (ny, nx), "field_in")
+    weighted = weights is not None
+    if weighted:
+        _dev_tensor(weights, torch.float32, (ny, nx), "weights")
+    op = HG_OP_WGS if weighted else HG_OP_GS
+    ws = _workspace(hg_workspace_size(op, ny, nx, 1), dev, workspace)
+    c64 = dict(dtype=torch.complex64, device=dev)
+    r, g, f = torch.empty((ny, nx), **c64), torch.empty((ny, nx), **c64), torch.empty((ny, nx), **c64)
+    levels = torch.empty((ny, nx), dtype=torch.uint8, device=dev) if slm_levels >= 2 else None
+    nmse = torch.empty(2, dtype=torch.float64, device=dev)
+    _check(lib().hg_gs_step(_ptr(target), ny, nx, slm_levels, int(weighted), _ptr(levels_in), _ptr(field_in),
+                            float(wavelength_m), float(pitch_m), float(z_m), int(lt_radius), _ptr(weights),
+                            _ptr(r), _ptr(g), _ptr(levels), _ptr(f), _ptr(nmse), _ptr(ws), ws.numel(),
+                            _stream(dev, stream)))
+    return dict(replay=r, g=g, levels=levels, field=f, nmse=nmse, weights=weights)
+
+
 def hg_lt(target, iters, slm_levels, lt_r0, lt_dr, seed=0, init_levels=None, init_field=None, wavelength_m=0.0,
           pitch_m=0.0, z_m=0.0, want_field=False, want_replay=False, stream=None, workspace=None):
     """Liu-Taghizadeh on the GPU (target square of radius lt_r0 + (k-1) lt_dr pixels at
@@ -338,6 +381,8 @@ def _problem_array(problems):
         lt = p.get("lt")
         if lt is not None:
             arr[i].lt, arr[i].lt_r0, arr[i].lt_dr = 1, int(lt[0]), int(lt[1])
+        if p.get("weights") is not None:
+            arr[i].weights = p["weights"].data_ptr()
     return arr
 
 
@@ -347,13 +392,15 @@ def hg_gs_batched_workspace_size(problems):
 
 
 def hg_gs_batched(targets, iters, slm_levels, seeds=None, optics=None, weighted=False, init_levels=None,
-                  want_replay=False, stream=None, workspace=None, lt=None):
+                  want_replay=False, stream=None, workspace=None, lt=None, weights=None):
     """Many GS problems (possibly of different sizes) in one call.
 
     targets: list of float32 CUDA tensors; optics: optional list of
     (wavelength_m, pitch_m, z_m) per problem; init_levels: optional list of
-    uint8 start levels (entries may be None).  Returns (levels, nmse) lists,
-    plus the list of final centred replays when want_replay.
+    uint8 start levels (entries may be None); weights: optional list of
+    float32 weight tensors (weighted calls read w_0 and write w_K in place;
+    entries may be None).  Returns (levels, nmse) lists, plus the list of
+    final centred replays when want_replay.
     """
     torch = _torch()
     dev = targets[0].device
@@ -367,11 +414,14 @@ def hg_gs_batched(targets, iters, slm_levels, seeds=None, optics=None, weighted=
         il = init_levels[i] if init_levels is not None else None
         if il is not None:
             _dev_tensor(il, torch.uint8, (ny, nx), f"init_levels[{i}]")
+        wt = weights[i] if weights is not None else None
+        if wt is not None:
+            _dev_tensor(wt, torch.float32, (ny, nx), f"weights[{i}]")
         lam, pit, z = optics[i] if optics is not None else (0.0, 0.0, 0.0)
         probs.append(dict(ny=ny, nx=nx, slm_levels=slm_levels, iters=iters,
                           seed=(seeds[i] if seeds is not None else 0), wavelength_m=lam, pitch_m=pit, z_m=z,
                           target=t, levels_out=lv, nmse_out=nm, init_levels=il, replay_out=rp,
-                          lt=(lt[i] if lt is not None else None)))
+                          lt=(lt[i] if lt is not None else None), weights=wt))
         levels.append(lv)
         nmses.append(nm)
         replays.append(rp)

@@ -138,7 +138,7 @@ Cfg get_cfg(int ny, int nx, int B) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t desc, field, tprep, wbuf, accum, twx, twy, chirp, part, invm, total;
+  size_t status, desc, field, tprep, wbuf, accum, twx, twy, chirp, part, invm, total;
   int max_nblk, slots;
 };
 
@@ -149,6 +149,7 @@ Layout make_layout(int op, int ny, int nx, int B, int kmax) {
   L.slots = (op == HG_OP_OSPR ? kmax : kmax + 1) + 1;  // + energy slot
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  L.status = take(sizeof(int));  // the call's numeric status word (first size class of a call)
   L.desc = take(sizeof(Desc) * B);
   L.field = take(px * sizeof(float2));
   L.tprep = take(px * sizeof(float));
@@ -187,9 +188,10 @@ bool is_fresnel(double lambda, double pitch, double z) { return chirp_rate(lambd
 // whole sequence stays on the stream and is graph-capturable)
 // ---------------------------------------------------------------------------
 struct DescPack { Desc d[8]; int count; };
-__global__ void k_set_desc(Desc* dst, DescPack pk) {
+__global__ void k_set_desc(Desc* dst, DescPack pk, int* clear_status) {
   const int i = threadIdx.x;
   if (i < pk.count) dst[i] = pk.d[i];
+  if (clear_status && i == 0) *clear_status = 0;
 }
 
 __global__ void k_fill(float* p, size_t n, float v) {
@@ -203,12 +205,14 @@ hg_status check_launch() {
   return HG_OK;
 }
 
-void upload_descs(Desc* dst, const std::vector<Desc>& ds, hipStream_t st) {
+// Descriptor upload; the first launch also clears the call's status word
+// when clear_status is given (the first size class of a call).
+void upload_descs(Desc* dst, const std::vector<Desc>& ds, hipStream_t st, int* clear_status = nullptr) {
   for (size_t i = 0; i < ds.size(); i += 8) {
     DescPack pk{};
     pk.count = (int)std::min<size_t>(8, ds.size() - i);
     for (int j = 0; j < pk.count; ++j) pk.d[j] = ds[i + j];
-    hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, st, dst + i, pk);
+    hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, st, dst + i, pk, i == 0 ? clear_status : nullptr);
   }
 }
 
@@ -276,8 +280,9 @@ Batch make_batch(void* ws, const Layout& L, int ny, int nx, int C) {
 }
 
 // Whole GS / WGS pipeline for one size class.
+// status: the call's status word; cleared here when `first` (the call's first size class).
 hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::vector<double>& rates, bool weighted,
-                       void* ws, const Layout& L, hipStream_t st) {
+                       void* ws, const Layout& L, hipStream_t st, int* status, bool first) {
   const int B = (int)ds.size();
   int kmax = 0;
   bool all_bin = true;
@@ -289,8 +294,10 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
   Batch bt = make_batch(ws, L, ny, nx, cfg.C);
   bool any_lt = false;  // Liu-Taghizadeh: not in the single-launch small-problem kernel
   for (const Desc& d : ds) any_lt |= (d.lt != 0);
+  for (const Desc& d : ds) bt.dump |= (d.r_out != nullptr) ? 1 : 0;
   bt.any_lt = any_lt ? 1 : 0;  // the classic GS column kernels' window instantiation
-  upload_descs(const_cast<Desc*>(bt.desc), ds, st);
+  bt.status = status;
+  upload_descs(const_cast<Desc*>(bt.desc), ds, st, first ? status : nullptr);
   bool fresnel = false;
   for (double r : rates) fresnel |= (r != 0.0);
   if (small_ok(ny, nx) && small_enabled() && !any_lt) {
@@ -329,11 +336,12 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
 // Whole OSPR / adaptive OSPR pipeline for one size class: B problems with
 // the same number of subframes, one batched launch per pass.
 hg_status run_ospr_class(int ny, int nx, const std::vector<Desc>& ds, int subframes, int adaptive, void* ws,
-                         const Layout& L, hipStream_t st) {
+                         const Layout& L, hipStream_t st, int* status, bool first) {
   const int B = (int)ds.size();
   const Cfg cfg = get_cfg(ny, nx, B);
   Batch bt = make_batch(ws, L, ny, nx, cfg.C);
-  upload_descs(const_cast<Desc*>(bt.desc), ds, st);
+  bt.status = status;
+  upload_descs(const_cast<Desc*>(bt.desc), ds, st, first ? status : nullptr);
   launch_twiddles(const_cast<float2*>(bt.tw_x), nx, st);
   if (ny != nx) launch_twiddles(const_cast<float2*>(bt.tw_y), ny, st);
   launch_setup(bt, cfg.C, B, 0, st);
@@ -384,7 +392,7 @@ hg_status gs_common(bool weighted, const float* target, int ny, int nx, int iter
                     const uint8_t* init_levels, const hg_complex* init_field, double lambda, double pitch,
                     double z, uint8_t* levels_out, hg_complex* field_out, hg_complex* replay_out,
                     double* nmse_out, float* weights, void* ws, size_t ws_bytes, void* stream, int lt = 0,
-                    int lt_r0 = 0, int lt_dr = 0) {
+                    int lt_r0 = 0, int lt_dr = 0, hg_complex* r_out = nullptr, hg_complex* g_out = nullptr) {
   g_err[0] = 0;
   hg_status s = check_common(target, ny, nx, iters, L);
   if (s != HG_OK) return s;
@@ -414,9 +422,12 @@ hg_status gs_common(bool weighted, const float* target, int ny, int nx, int iter
   d.lt = lt ? 1 : 0;
   d.lt_r0 = lt_r0;
   d.lt_dr = lt_dr;
+  d.r_out = reinterpret_cast<float2*>(r_out);
+  d.g_out = reinterpret_cast<float2*>(g_out);
   std::vector<Desc> ds{d};
   std::vector<double> rates{chirp_rate(lambda, pitch, z)};
-  return run_gs_class(ny, nx, ds, rates, weighted, ws, Lo, static_cast<hipStream_t>(stream));
+  return run_gs_class(ny, nx, ds, rates, weighted, ws, Lo, static_cast<hipStream_t>(stream), at<int>(ws, Lo.status),
+                      true);
 }
 
 // Size classes of a batched call in order of first appearance.
@@ -473,11 +484,25 @@ const char* hg_status_string(hg_status s) {
     case HG_ERR_UNSUPPORTED_SIZE: return "unsupported size";
     case HG_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
     case HG_ERR_HIP: return "HIP runtime error";
+    case HG_ERR_NUMERIC: return "non-finite values in the NMSE sums";
   }
   return "unknown status";
 }
 
 const char* hg_last_error(void) { return g_err; }
+
+hg_status hg_numeric_status(const void* workspace, void* stream) {
+  g_err[0] = 0;
+  if (!workspace) return fail(HG_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(HG_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
+    return fail(HG_ERR_HIP, "hipStreamSynchronize failed");
+  int flag = 0;
+  if (hipMemcpy(&flag, workspace, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(HG_ERR_HIP, "hipMemcpy of the status word failed");
+  if (flag) return fail(HG_ERR_NUMERIC, "a finisher saw non-finite NMSE sums (NaN or Inf in the target or weights)");
+  return HG_OK;
+}
 
 void hg_timing_enable(int on) { g_timing.on = on != 0; }
 
@@ -538,6 +563,22 @@ hg_status hg_wgs(const float* target, int ny, int nx, int iters, int slm_levels,
                    stream);
 }
 
+hg_status hg_gs_step(const float* target, int ny, int nx, int slm_levels, int weighted, const uint8_t* levels_in,
+                     const hg_complex* field_in, double wavelength_m, double pitch_m, double z_m, int lt_radius,
+                     float* weights_inout, hg_complex* r_out, hg_complex* g_out, uint8_t* levels_out,
+                     hg_complex* field_out, double* nmse_out, void* workspace, size_t workspace_bytes,
+                     void* stream) {
+  g_err[0] = 0;
+  if ((levels_in == nullptr) == (field_in == nullptr))
+    return fail(HG_ERR_INVALID_ARG, "exactly one of levels_in and field_in gives the start state");
+  if (weighted && !weights_inout) return fail(HG_ERR_INVALID_ARG, "weighted step needs weights_inout (w_{k-1})");
+  if (weighted && lt_radius >= 0) return fail(HG_ERR_INVALID_ARG, "Liu-Taghizadeh is a GS variant (not weighted)");
+  const bool lt = lt_radius >= 0;
+  return gs_common(weighted != 0, target, ny, nx, 1, slm_levels, 0, levels_in, field_in, wavelength_m, pitch_m, z_m,
+                   levels_out, field_out, nullptr, nmse_out, weighted ? weights_inout : nullptr, workspace,
+                   workspace_bytes, stream, lt ? 1 : 0, lt ? lt_radius : 0, 0, r_out, g_out);
+}
+
 hg_status hg_lt(const float* target, int ny, int nx, int iters, int slm_levels, uint64_t seed,
                 const uint8_t* init_levels, const hg_complex* init_field, double wavelength_m, double pitch_m,
                 double z_m, int lt_r0, int lt_dr, uint8_t* levels_out, hg_complex* slm_field_out,
@@ -565,7 +606,8 @@ hg_status hg_ospr(const float* target, int ny, int nx, int subframes, int adapti
   d.seed = seed;
   d.L = 2;
   d.iters = subframes;
-  return run_ospr_class(ny, nx, {d}, subframes, adaptive, workspace, Lo, static_cast<hipStream_t>(stream));
+  return run_ospr_class(ny, nx, {d}, subframes, adaptive, workspace, Lo, static_cast<hipStream_t>(stream),
+                        at<int>(workspace, Lo.status), true);
 }
 
 size_t hg_ospr_batched_workspace_size(const hg_ospr_problem* probs, int count, int subframes) {
@@ -613,7 +655,8 @@ hg_status hg_ospr_batched(const hg_ospr_problem* probs, int count, int subframes
       ds.push_back(d);
     }
     const Layout Lo = make_layout(HG_OP_OSPR, key.first, key.second, (int)idx.size(), subframes);
-    s = run_ospr_class(key.first, key.second, ds, subframes, adaptive, static_cast<char*>(workspace) + off, Lo, st);
+    s = run_ospr_class(key.first, key.second, ds, subframes, adaptive, static_cast<char*>(workspace) + off, Lo, st,
+                       at<int>(workspace, 0), off == 0);
     if (s != HG_OK) return s;
     off += Lo.total;
   }
@@ -733,12 +776,15 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
       d.lt = p.lt ? 1 : 0;
       d.lt_r0 = p.lt_r0;
       d.lt_dr = p.lt_dr;
+      d.weights = weighted ? p.weights : nullptr;
+      d.user_weights = (weighted && p.weights) ? 1 : 0;
       ds.push_back(d);
       rates.push_back(chirp_rate(p.wavelength_m, p.pitch_m, p.z_m));
       kmax = std::max(kmax, p.iters);
     }
     const Layout Lo = make_layout(HG_OP_WGS, key.first, key.second, (int)idx.size(), kmax);
-    s = run_gs_class(key.first, key.second, ds, rates, weighted != 0, static_cast<char*>(workspace) + off, Lo, st);
+    s = run_gs_class(key.first, key.second, ds, rates, weighted != 0, static_cast<char*>(workspace) + off, Lo, st,
+                     at<int>(workspace, 0), off == 0);
     if (s != HG_OK) return s;
     off += Lo.total;
   }

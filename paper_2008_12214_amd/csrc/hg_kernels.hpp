@@ -37,6 +37,8 @@ struct Desc {
   int user_weights;           // weights came from the caller
   int lt;                     // Liu-Taghizadeh: constrain only the growing centred square
   int lt_r0, lt_dr;           //   of radius lt_r0 + (k-1) lt_dr at iteration k
+  float2* r_out;              // one-iteration calls: replay of the start field, before the constraint (nullable)
+  float2* g_out;              // one-iteration calls: SLM-plane field before the projection (nullable)
 };
 
 // Launch-uniform view of one size class of problems (passed by value).
@@ -56,6 +58,8 @@ struct Batch {
   int slots;            // partial slots per problem
   float fwd_scale;      // 1/sqrt(nx ny)
   int any_lt;           // some problem of the batch has a Liu-Taghizadeh region
+  int* status;          // the call's numeric status word: nonzero once a finisher saw non-finite sums
+  int dump;             // some problem asks for r_out: the first column pass runs its dumping instantiation
 };
 
 __device__ __forceinline__ double* part_ptr(const Batch& bt, int b, int slot, int blk) {
@@ -335,12 +339,16 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_prepare(Batch bt, int weighte
     tv *= scale;
     const uint32_t ti = tix(v, u, bt.nx);
     bt.tprep[off + ti] = tv;
+    // support: every pixel whose target is not exactly zero (a NaN or
+    // negative value counts, so the column passes read it and the NMSE
+    // turns non-finite as it does in every kernel)
+    const bool sup = !(tv == 0.f);
     if (weighted) {
       const float wv = d.user_weights ? d.weights[idx] : 1.0f;
       w[ti] = wv;
-      if (tv > 0.f) ws += wv;
+      if (sup) ws += wv;
     }
-    if (tv > 0.f) { om += 1.f; rlo = min(rlo, v); rhi = max(rhi, v); }
+    if (sup) { om += 1.f; rlo = min(rlo, v); rhi = max(rhi, v); }
   }
   // slot slots-1 field 1: |Omega| of the tile, fields 2 and 3: its first and
   // last support row (the column passes read no target or weights outside
@@ -507,6 +515,7 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
       const bool last = (MODE == ROW_OSPR) || (arg == iters);
       gptr<uint8_t> lev = to_global(uni_ptr(d.levels_out));
       gptr<float2> fout = to_global(uni_ptr(d.field_out));
+      gptr<float2> gdump = to_global(uni_ptr(d.g_out));
       if (MODE == ROW_OSPR) lev += (size_t)(arg - 1) * bt.ny * NX;
       if constexpr (TAB) {
         if (L > 2) {  // uniform per block
@@ -549,6 +558,7 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
           }
           if constexpr (WR && MODE == ROW_ITER) {
             if (fout) fout[(size_t)y * NX + x] = f;
+            if (gdump) gdump[(size_t)y * NX + x] = g;
           }
           v[j] = md.fwd(f);
         }
@@ -602,7 +612,9 @@ constexpr float kWgsEps = 0.1f, kWgsGamma = 0.7f, kWMin = 1e-6f, kWMax = 1e6f;
 
 // LT: the GS pass also applies Liu-Taghizadeh regions (a separate instantiation,
 // so that plain GS does not carry the window test's registers).
-template <int NY, int C, int MODE, bool LT = false>
+// DUMP: GS / WGS pass that also writes each problem's replay before the
+// constraint to its r_out (one-iteration calls only; a separate instantiation).
+template <int NY, int C, int MODE, bool LT = false, bool DUMP = false>
 __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int adaptive, const float2* pin,
                                                        float2* pout) {
   constexpr int E = kE;
@@ -675,6 +687,9 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
       if constexpr (MODE == COL_FINAL) {
         if (d.replay_out) to_global(d.replay_out)[idx] = cscale(Rr, bt.fwd_scale);
       } else {
+        if constexpr (DUMP) {
+          if (d.r_out) to_global(d.r_out)[idx] = cscale(Rr, bt.fwd_scale);
+        }
         float amp = Tv;
         if constexpr (MODE == COL_WGS) {
           if (Tv > 0.f) {
@@ -795,7 +810,7 @@ struct WaveColEx {
   __device__ void st(int e, float2 v) { s[e] = v; }
 };
 
-template <int NY, int C, int MODE, bool LT = false>  // LT as for k_col
+template <int NY, int C, int MODE, bool LT = false, bool DUMP = false>  // LT, DUMP as for k_col
 __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int adaptive, const float2* pin,
                                                         float2* pout) {
   constexpr int E = kE, T = NY / E, NT = C * T;
@@ -874,6 +889,9 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
       if constexpr (MODE == COL_FINAL) {
         if (d.replay_out) to_global(d.replay_out)[idx] = cscale(Rr, bt.fwd_scale);
       } else {
+        if constexpr (DUMP) {
+          if (d.r_out) to_global(d.r_out)[idx] = cscale(Rr, bt.fwd_scale);
+        }
         float amp = Tv;
         if constexpr (MODE == COL_WGS) {
           if (Tv > 0.f) {
@@ -1158,7 +1176,7 @@ __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int
 // wait for everything (each wave for its own loads) before the barrier.
 // LATE: this tile's target and weights are loaded here, after the forward
 // transform, instead of ahead (in.active set by the caller).
-template <int NY, int C, int MODE, int E, int PAR, class TWP, bool LATE = false>
+template <int NY, int C, int MODE, int E, int PAR, class TWP, bool LATE = false, bool DUMP = false>
 __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vtn, int total, int tpp,
                                           float2* __restrict__ Fc, float2* __restrict__ Fn, TWP tw,
                                           double (&red)[kMaxWaves][4], double (&tot)[4], ColpIn<E>& in) {
@@ -1194,6 +1212,10 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
       s_ta += Tv * A;
       s_aa += A * A;
       s_tt += Tv * Tv;
+      if constexpr (DUMP) {  // one-iteration calls: the replay before the constraint
+        const Desc& dd = bt.desc[b];
+        if (dd.r_out) to_global(dd.r_out)[(size_t)row * NX + u] = cscale(Rr, bt.fwd_scale);
+      }
       float amp = Tv;
       if constexpr (WGS) {
         if (Tv > 0.f) {
@@ -1280,7 +1302,7 @@ void k_colp(Batch bt, int k, int nprob) {
 // (plain GS) workgroups share a CU and hide each other's loads.  Capping the
 // weighted kernel at 128 registers to fit four spills, and measured 9%
 // slower.
-template <int NY, int C, int MODE, int E = kColpE>
+template <int NY, int C, int MODE, int E = kColpE, bool DUMP = false>
 __global__ __launch_bounds__(C * (NY / E))
 void k_colq(Batch bt, int k, int nprob) {
   using S = ColpShape<NY, C, E>;
@@ -1296,7 +1318,7 @@ void k_colq(Batch bt, int k, int nprob) {
   colp_load_in<NY, C, MODE, E>(bt, k, vt, tpp, in);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  colp_tile<NY, C, MODE, E, 0, decltype(launder(to_global(bt.tw_y))), false>(
+  colp_tile<NY, C, MODE, E, 0, decltype(launder(to_global(bt.tw_y))), false, DUMP>(
       bt, k, vt, total, total, tpp, FA, FA, launder(to_global(bt.tw_y)), red, tot, in);
 }
 
@@ -1457,6 +1479,17 @@ static __global__ __launch_bounds__(64) void k_wgs_invm(Batch bt, int k) {
   if (threadIdx.x == 0) bt.invm[b] = (float)((om > 0.0 ? om : 1.0) / ws);
 }
 
+// NMSE = 1 - sta^2 / (stt saa) from the FP64 sums; a replay or target of
+// zero energy gives 1.  Non-finite sums give NaN and raise the call's
+// status word (read by hg_numeric_status).
+__device__ __forceinline__ double nmse_from_sums(double sta, double saa, double stt, int* status) {
+  if (!(__builtin_isfinite(sta) && __builtin_isfinite(saa) && __builtin_isfinite(stt))) {
+    if (status) *status = 1;
+    return __builtin_nan("");
+  }
+  return (saa > 0.0 && stt > 0.0) ? 1.0 - sta * sta / (stt * saa) : 1.0;
+}
+
 // nmse[k] = 1 - sta^2 / (stt saa) from the block partials of slot k; a GS
 // problem has iters + 1 values, an OSPR problem `iters` (= subframes).
 static __global__ void k_finish(Batch bt, int count, int ospr) {
@@ -1470,7 +1503,7 @@ static __global__ void k_finish(Batch bt, int count, int ospr) {
     const double* pp = part_ptr(bt, b, k, i);
     sta += pp[0]; saa += pp[1]; stt += pp[2];
   }
-  d.nmse_out[k] = (saa > 0.0 && stt > 0.0) ? 1.0 - sta * sta / (stt * saa) : 1.0;
+  d.nmse_out[k] = nmse_from_sums(sta, saa, stt, bt.status);
 }
 
 }  // namespace hg

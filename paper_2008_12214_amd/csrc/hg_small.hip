@@ -78,6 +78,8 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
   double* nmse = uni_ptr(d.nmse_out);
   gptr<float2> fout = to_global(uni_ptr(d.field_out));
   gptr<float2> rout = to_global(uni_ptr(d.replay_out));
+  gptr<float2> rdump = to_global(uni_ptr(d.r_out));  // one-iteration calls: replay before the constraint
+  gptr<float2> gdump = to_global(uni_ptr(d.g_out));  // and the field before the projection
   const uint8_t* init_l = uni_ptr(d.init_levels);
   const float2* init_f = uni_ptr(d.init_field);
   const size_t off = (size_t)b * NY * NX;
@@ -195,6 +197,7 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
       if (fin) {
         if (rout) rout[idx] = cscale(Rr, bt.fwd_scale);
       } else {
+        if (rdump) rdump[idx] = cscale(Rr, bt.fwd_scale);
         float amp = Tv;
         if constexpr (WEIGHTED) {
           if (Tv > 0.f) {
@@ -210,8 +213,10 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
       }
     }
     block_sum4<NT>(s_ta, s_aa, s_tt, s_w, red, tot);
-    if (threadIdx.x == 0 && nmse)
-      nmse[k - 1] = (tot[1] > 0.0 && tot[2] > 0.0) ? 1.0 - tot[0] * tot[0] / (tot[2] * tot[1]) : 1.0;
+    if (threadIdx.x == 0) {
+      const double e = nmse_from_sums(tot[0], tot[1], tot[2], bt.status);
+      if (nmse) nmse[k - 1] = e;
+    }
     if constexpr (WEIGHTED) wsum = tot[3];
     if (fin) break;
     fft_lds<NY, E, +1>(v, ct, twy, cex);
@@ -246,6 +251,7 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
         }
         if constexpr (WR) {
           if (fout) fout[ry * NX + x] = f;
+          if (gdump) gdump[ry * NX + x] = g;
         }
         v[j] = md.fwd(f);
       }

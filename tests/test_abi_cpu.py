@@ -26,9 +26,17 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_status_strings():
-    for s in range(5):
-        assert hg.hg_status_string(s)
+    for s in range(6):
+        assert hg.hg_status_string(s) != "unknown status"
     assert hg.hg_status_string(99) == "unknown status"
+
+
+def test_numeric_status_argument_checks():
+    """hg_numeric_status validates its workspace before any HIP call."""
+    assert L.hg_numeric_status(None, None) == hg.HG_ERR_INVALID_ARG
+    assert "NULL" in hg.hg_last_error()
+    assert L.hg_numeric_status(ctypes.c_void_p(0x10010), None) == hg.HG_ERR_INVALID_ARG
+    assert "aligned" in hg.hg_last_error()
 
 
 def test_workspace_queries():
@@ -175,3 +183,4 @@ def test_ospr_batched_validation():
     assert need >= L.hg_workspace_size(hg.HG_OP_OSPR, 64, 64, 4) + L.hg_workspace_size(hg.HG_OP_OSPR, 128, 64, 4)
     assert L.hg_ospr_batched(probs, 2, 4, 1, FAKE, need - 256, None) == hg.HG_ERR_WORKSPACE
     assert L.hg_ospr_batched(probs, 2, 0, 1, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG  # subframes
+

@@ -14,6 +14,7 @@ import pytest
 
 import synth
 from oracle import hologram, philox, slm, metrics
+from parity import FIELD_TOL, NMSE_TOL, level_check, rel_l2, rel_max, say
 
 pytestmark = pytest.mark.gpu
 
@@ -21,17 +22,6 @@ torch = pytest.importorskip("torch")
 import paper_2008_12214_amd as hg  # noqa: E402
 
 DEV = "cuda:0"
-FIELD_TOL = 1e-4
-NMSE_TOL = 1e-4
-BAND = 1e-5
-# |g| below this fraction of its rms is zero to FP32 transform precision
-# (about 16 FP32 ulps, the error growth of a 1024-point FFT): no phase, and
-# so no level, is defined there
-ZERO = 1e-6
-
-
-def say(*a):
-    print("[gpu]", *a, flush=True)
 
 
 def dev(a, dtype=None):
@@ -44,30 +34,6 @@ def dev(a, dtype=None):
 def host(t):
     torch.cuda.synchronize()
     return t.cpu().numpy()
-
-
-def rel_l2(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
-
-
-def rel_max(a, b):
-    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
-    return float(np.max(np.abs(a - b) / np.abs(b)))
-
-
-def level_check(gpu_lev, ref_lev, g_ref, L):
-    """(non-exempt mismatches, exempt mismatches); prints each non-exempt one."""
-    mism = np.asarray(gpu_lev, np.int64) != np.asarray(ref_lev, np.int64)
-    margin = slm.boundary_margin(g_ref, L)
-    rms = np.sqrt(np.mean(np.abs(g_ref) ** 2))
-    exempt = mism & ((margin < BAND) | (np.abs(g_ref) < ZERO * rms))
-    bad = mism & ~exempt
-    if bad.any():
-        for y, x in zip(*np.nonzero(bad)):
-            a = abs(g_ref[y, x])
-            say(f"  mismatch at ({y},{x}): margin {margin[y, x]:.3e} rad, |g|/rms {a / rms:.3e}, "
-                f"distance/rms {a * np.sin(margin[y, x]) / rms:.3e}")
-    return int(bad.sum()), int(exempt.sum())
 
 
 # ---------------------------------------------------------------------------
@@ -184,7 +150,7 @@ def _lockstep(T, L, steps, weighted, seed=1, optics=None, start=None):
         ref = hologram.gs(T, 1, L, seed=seed, init_levels=lev, weighted=weighted,
                           weights=None if w is None else w, optics=optics)
         g_lev = host(out["levels"])
-        bad, ex = level_check(g_lev, ref["levels"], ref["g"], L)
+        bad, ex = level_check(g_lev, ref["levels"], ref["g"], L, where=f"step {k}")
         exempt_total += ex
         assert bad == 0, f"step {k}: {bad} non-exempt level mismatches ({ex} exempt)"
         e = rel_max(host(out["nmse"]), ref["nmse"])

@@ -16,6 +16,7 @@ import pytest
 
 import synth
 from oracle import hologram, metrics, slm
+from parity import NMSE_TOL, level_check
 
 pytestmark = pytest.mark.gpu
 
@@ -23,9 +24,6 @@ torch = pytest.importorskip("torch")
 import paper_2008_12214_amd as hg  # noqa: E402
 
 DEV = "cuda:0"
-NMSE_TOL = 1e-4
-BAND = 1e-5
-ZERO = 1e-6  # |g| / rms below which the field is zero to FP32 transform precision
 
 
 def say(*a):
@@ -87,19 +85,11 @@ def test_batch_column_pass_first_iteration_lockstep(n, B, weighted, L, fresnel, 
         T, start, optics = probs[b]
         ref = hologram.gs(T, 1, L, init_levels=start.astype(np.int64), weighted=weighted,
                           optics=optics if fresnel else None)
-        mism = lv[b].astype(np.int64) != ref["levels"]
-        margin = slm.boundary_margin(ref["g"], L)
-        rms = np.sqrt(np.mean(np.abs(ref["g"]) ** 2))
-        badm = mism & (margin >= BAND) & (np.abs(ref["g"]) >= ZERO * rms)
-        for y, x in zip(*np.nonzero(badm)):
-            a = abs(ref["g"][y, x])
-            say(f"  mismatch ({y},{x}): margin {margin[y, x]:.3e} rad, |g|/rms {a / rms:.3e}, "
-                f"distance/rms {a * np.sin(margin[y, x]) / rms:.3e}")
-        bad = int(np.sum(badm))
+        bad, ex = level_check(lv[b], ref["levels"], ref["g"], L, where=f"problem {b}")
         assert bad == 0, f"problem {b}: {bad} non-exempt level mismatches"
         err = np.max(np.abs(nm[b] - ref["nmse"]) / ref["nmse"])
         assert err < NMSE_TOL, (b, err)
-        say(f"  problem {b}: nmse rel err {err:.2e}, exempt flips {int(np.sum(mism))}")
+        say(f"  problem {b}: nmse rel err {err:.2e}, exempt flips {ex}")
 
 
 @pytest.mark.parametrize("kind", sorted(KINDS))
@@ -152,10 +142,7 @@ def test_ospr_1024_batch_lockstep(kind):
         lev = lv[b].astype(np.int64)
         for i in range(sub):
             k, g, _, _ = hologram.ospr_subframe(T, A, i + 1, True, seed=seeds[b], batch_item=b)
-            mism = lev[i] != k
-            margin = slm.boundary_margin(g, 2)
-            rms = np.sqrt(np.mean(np.abs(g) ** 2))
-            bad = int(np.sum(mism & (margin >= BAND) & (np.abs(g) >= ZERO * rms)))
+            bad, _ = level_check(lev[i], k, g, 2, where=f"problem {b} subframe {i + 1}")
             assert bad == 0, (b, i, bad)
             h = np.where(lev[i] == 1, -1.0, 1.0)
             A = A + np.abs(hologram.forward(h)) ** 2

@@ -225,3 +225,27 @@ def test_lt_becomes_gs_once_the_window_covers_the_plane():
     # and the growing window differs from plain GS early on
     gs = hologram.gs(T, 5, 4, seed=9)
     assert gs["nmse"][1] != full["nmse"][1]
+
+
+@pytest.mark.parametrize("L,weighted,lt_r,optics", [(2, True, None, None), (8, False, None, (532e-9, 8e-6, 0.1)),
+                                                     (0, False, 5, None), (4, True, None, None)])
+def test_gs_step_is_one_iteration_of_gs(L, weighted, lt_r, optics):
+    """gs_step (one iteration from a caller's state, the lock-step interface)
+    gives the iteration gs() takes from that state; its pre-constraint replay
+    is the forward transform of the state."""
+    T_raw = synth.gaussian_target(32, seed=4)
+    T = hologram.prepare_target(T_raw, L)
+    rng = np.random.default_rng(L)
+    lev = rng.integers(0, max(L, 2), T.shape)
+    f = np.exp(1j * rng.uniform(0, 2 * np.pi, T.shape)) if L == 0 else slm.level_phasor(lev, L)
+    w = rng.uniform(0.5, 2.0, T.shape) if weighted else None
+    st = hologram.gs_step(T, L, f, weighted=weighted, w_prev=w, optics=optics, lt_r=lt_r)
+    ref = hologram.gs(T_raw, 1, L, init_field=f, weighted=weighted, weights=w, optics=optics,
+                      lt=None if lt_r is None else (lt_r, 0))
+    np.testing.assert_array_equal(st["g"], ref["g"])
+    np.testing.assert_array_equal(st["field"], ref["field"])
+    assert st["nmse"] == ref["nmse"][0] and st["nmse_next"] == ref["nmse"][1]
+    if weighted:
+        np.testing.assert_array_equal(st["weights"], ref["weights"])
+    Q = hologram.fresnel_chirp(32, 32, *optics) if optics else None
+    np.testing.assert_allclose(st["replay"], hologram.forward(f, Q), rtol=0, atol=1e-13)

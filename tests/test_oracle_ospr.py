@@ -57,3 +57,24 @@ def test_adaptive_beats_plain_ospr():
     adapt = hologram.ospr(T, 24, adaptive=True, seed=3)
     assert adapt["nmse"][-1] < plain["nmse"][-1]
     assert np.mean(adapt["accum"] / 24) == pytest.approx(1.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("n", [2, 3, 7, 24])
+def test_adaptive_feedback_completes_the_target(n):
+    """Adaptive OSPR's feedback (the reading of the Time-Averaged Algorithms
+    section): subframe n asks for exactly the intensity that, added to the
+    n - 1 subframes already accumulated, makes their average the target,
+    (A_{n-1} + T_n^2) / n = T^2, wherever that is possible (deficit >= 0),
+    and for nothing where the pixel is already too bright.  A_{n-1} is drawn
+    independently of T; an off-by-one in n fails this."""
+    rng = np.random.default_rng(n)
+    T = rng.uniform(0.0, 2.0, (24, 24))
+    A = rng.uniform(0.0, 2.0 * n, (24, 24))
+    Tn = hologram.ospr_target(T, A, n, adaptive=True)
+    deficit = n * T * T - A
+    ok = deficit >= 0
+    assert 0.2 < ok.mean() < 0.95
+    np.testing.assert_allclose(((A + Tn ** 2) / n)[ok], (T * T)[ok], rtol=1e-12)
+    assert np.all(Tn[~ok] == 0.0)
+    np.testing.assert_array_equal(hologram.ospr_target(T, A, n, adaptive=False), T)
+    np.testing.assert_array_equal(hologram.ospr_target(T, np.zeros_like(T), 1, adaptive=True), T)

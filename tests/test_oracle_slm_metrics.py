@@ -88,3 +88,38 @@ def test_nmse_is_scale_optimal_mse():
     assert metrics.nmse(T, A) == pytest.approx(res.fun, rel=1e-7)
     assert metrics.nmse(T, 3.0 * T) == pytest.approx(0.0, abs=1e-14)
     assert 0.0 <= metrics.nmse(T, rng.random((16, 16))) <= 1.0
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 8, 16, 256])
+def test_boundary_margin_against_brute_force(L):
+    """The parity exemption's margin: the angular distance from arg g to the
+    nearest decision boundary (2m + 1) pi / L of the nearest-level rule,
+    found here by brute force over all L boundaries on the circle."""
+    rng = np.random.default_rng(100 + L)
+    g = (rng.standard_normal(3000) + 1j * rng.standard_normal(3000)) * rng.uniform(0.01, 10.0, 3000)
+    theta = np.arctan2(g.imag, g.real)
+    b = (2 * np.arange(L) + 1) * np.pi / L
+    d = np.abs(theta[:, None] - b[None, :]) % (2 * np.pi)
+    brute = np.min(np.minimum(d, 2 * np.pi - d), axis=1)
+    np.testing.assert_allclose(slm.boundary_margin(g, L), brute, rtol=0, atol=1e-12)
+    assert np.all(slm.boundary_margin(np.zeros(3, complex), L) == 0.0)
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 8, 16, 256])
+def test_boundary_margin_is_the_distance_to_a_level_change(L):
+    """Rotating g towards its nearest boundary by just less than the margin
+    keeps its level; by just more, it changes the level."""
+    rng = np.random.default_rng(200 + L)
+    g = rng.standard_normal(2000) + 1j * rng.standard_normal(2000)
+    m = slm.boundary_margin(g, L)
+    keep = m > 1e-6
+    g, m = g[keep], m[keep]
+    theta = np.arctan2(g.imag, g.real)
+    b = (2 * np.arange(L) + 1) * np.pi / L
+    d = (b[None, :] - theta[:, None] + np.pi) % (2 * np.pi) - np.pi  # signed, in [-pi, pi)
+    sgn = np.sign(d[np.arange(len(g)), np.argmin(np.abs(d), axis=1)])
+    k0 = slm.level_index(g, L)
+    inside = slm.level_index(g * np.exp(1j * sgn * (m - 1e-9)), L)
+    across = slm.level_index(g * np.exp(1j * sgn * (m + 1e-9)), L)
+    np.testing.assert_array_equal(inside, k0)
+    assert np.all(across != k0)
