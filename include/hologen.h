@@ -51,7 +51,9 @@
  *    Inf in a target or in caller weights) cannot be reported by the call,
  *    which returns before the kernels run: the NMSE finisher writes NaN to
  *    nmse_out and raises a status word in the workspace, which
- *    hg_numeric_status() reads after the call (HG_ERR_NUMERIC).
+ *    hg_numeric_status() reads after the call (HG_ERR_NUMERIC).  A
+ *    non-finite caller weight makes the set-up pass mark its pixel's
+ *    prepared target NaN, so it is reported the same way.
  */
 #ifndef HOLOGEN_H
 #define HOLOGEN_H

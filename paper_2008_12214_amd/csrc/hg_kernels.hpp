@@ -338,13 +338,16 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_prepare(Batch bt, int weighte
     }
     tv *= scale;
     const uint32_t ti = tix(v, u, bt.nx);
+    const float wv = (weighted && d.user_weights) ? d.weights[idx] : 1.0f;
+    // a non-finite caller weight poisons its pixel's target, so the NMSE
+    // turns NaN as for a non-finite target
+    if (!__builtin_isfinite(wv)) tv = __builtin_nanf("");
     bt.tprep[off + ti] = tv;
     // support: every pixel whose target is not exactly zero (a NaN or
     // negative value counts, so the column passes read it and the NMSE
     // turns non-finite as it does in every kernel)
     const bool sup = !(tv == 0.f);
     if (weighted) {
-      const float wv = d.user_weights ? d.weights[idx] : 1.0f;
       w[ti] = wv;
       if (sup) ws += wv;
     }
@@ -558,7 +561,7 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
           }
           if constexpr (WR && MODE == ROW_ITER) {
             if (fout) fout[(size_t)y * NX + x] = f;
-            if (gdump) gdump[(size_t)y * NX + x] = g;
+            if (gdump) gdump[(size_t)y * NX + x] = cscale(g, bt.fwd_scale);  // unitary backward
           }
           v[j] = md.fwd(f);
         }
@@ -609,6 +612,12 @@ enum ColMode {
 
 // weighted GS: amplitude floor (unit-rms units), leak exponent, clamp
 constexpr float kWgsEps = 0.1f, kWgsGamma = 0.7f, kWMin = 1e-6f, kWMax = 1e6f;
+
+// Weight clamp to [kWMin, kWMax] that keeps a NaN (fminf/fmaxf would replace
+// it by a bound and so hide a non-finite caller weight from the finisher).
+__device__ __forceinline__ float clamp_w(float x) {
+  return x < kWMin ? kWMin : (x > kWMax ? kWMax : x);
+}
 
 // LT: the GS pass also applies Liu-Taghizadeh regions (a separate instantiation,
 // so that plain GS does not carry the window test's registers).
@@ -694,7 +703,7 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
         if constexpr (MODE == COL_WGS) {
           if (Tv > 0.f) {
             const float ratio = fmaxf(Tv, kWgsEps) * __builtin_amdgcn_rcpf(fmaxf(A, kWgsEps));
-            const float wc = fminf(fmaxf(w[ti] * ratio * inv_m, kWMin), kWMax);
+            const float wc = clamp_w(w[ti] * ratio * inv_m);
             const float wn = __builtin_amdgcn_exp2f(kWgsGamma * __builtin_amdgcn_logf(wc));
             w[ti] = wn;
             s_w += wn;
@@ -896,7 +905,7 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
         if constexpr (MODE == COL_WGS) {
           if (Tv > 0.f) {
             const float ratio = fmaxf(Tv, kWgsEps) * __builtin_amdgcn_rcpf(fmaxf(A, kWgsEps));
-            const float wc = fminf(fmaxf(w[ti] * ratio * inv_m, kWMin), kWMax);
+            const float wc = clamp_w(w[ti] * ratio * inv_m);
             const float wn = __builtin_amdgcn_exp2f(kWgsGamma * __builtin_amdgcn_logf(wc));
             w[ti] = wn;
             s_w += wn;
@@ -1220,7 +1229,7 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
       if constexpr (WGS) {
         if (Tv > 0.f) {
           const float ratio = fmaxf(Tv, kWgsEps) * __builtin_amdgcn_rcpf(fmaxf(A, kWgsEps));
-          const float wc = fminf(fmaxf(in.wv[j] * ratio * in.inv_m, kWMin), kWMax);
+          const float wc = clamp_w(in.wv[j] * ratio * in.inv_m);
           const float wn = __builtin_amdgcn_exp2f(kWgsGamma * __builtin_amdgcn_logf(wc));
           w[tix(row, u, NX)] = wn;
           s_w += wn;

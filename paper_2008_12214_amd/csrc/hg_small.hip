@@ -127,6 +127,11 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
       tv = sqrtf(0.5f * (tv * tv + tm * tm));
     }
     tv *= scale;
+    if constexpr (WEIGHTED) {
+      // a non-finite caller weight poisons its pixel's target, so the NMSE
+      // turns NaN as for a non-finite target
+      if (user_w && !__builtin_isfinite(w[idx])) tv = __builtin_nanf("");
+    }
     tp[idx] = tv;
     if constexpr (WEIGHTED) {
       float wv = 1.0f;
@@ -202,7 +207,7 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
         if constexpr (WEIGHTED) {
           if (Tv > 0.f) {
             const float ratio = fmaxf(Tv, kWgsEps) * __builtin_amdgcn_rcpf(fmaxf(A, kWgsEps));
-            const float wc = fminf(fmaxf(w[idx] * ratio * inv_m, kWMin), kWMax);
+            const float wc = clamp_w(w[idx] * ratio * inv_m);
             const float wn = __builtin_amdgcn_exp2f(kWgsGamma * __builtin_amdgcn_logf(wc));
             w[idx] = wn;
             s_w += wn;
@@ -251,7 +256,7 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
         }
         if constexpr (WR) {
           if (fout) fout[ry * NX + x] = f;
-          if (gdump) gdump[ry * NX + x] = g;
+          if (gdump) gdump[ry * NX + x] = cscale(g, bt.fwd_scale);  // unitary backward
         }
         v[j] = md.fwd(f);
       }
