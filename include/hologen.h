@@ -311,6 +311,33 @@ hg_status hg_timing_read(hg_kernel_times* out);
  * workspace.  NULL or misaligned workspace: HG_ERR_INVALID_ARG.            */
 hg_status hg_numeric_status(const void* workspace, void* stream);
 
+/* Weighted GS with no workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc).  Arguments, results and errors as hg_wgs; the
+ * scratch that hg_wgs takes as `workspace` is instead a file-scope device
+ * array of HG_STATIC_SCRATCH_BYTES (32 MiB) in the library, one copy per GPU
+ * the library runs on, held until the process ends.  Its device address is
+ * looked up once per device (hipGetSymbolAddress) on the first call made
+ * with that device current; the current device must be the stream's.
+ *  - Sizes: a call whose hg_workspace_size(HG_OP_WGS, ny, nx, iters)
+ *    exceeds HG_STATIC_SCRATCH_BYTES is rejected with HG_ERR_WORKSPACE
+ *    before any HIP call (a 1024 x 1024 grid fits up to about 1700
+ *    iterations, 2048 x 2048 does not fit).
+ *  - The call allocates nothing: no hipMalloc, hipFree or allocating
+ *    library routine.
+ *  - Every call on one GPU shares that GPU's array, which keeps the last
+ *    call's contents (each call initialises what it reads).  Calls that
+ *    overlap on one GPU (different streams, or host threads without
+ *    ordering) race on it and give undefined results.
+ *  - The numeric status word sits in the shared array too; a non-finite
+ *    input is reported by NaN in nmse_out.                                 */
+#define HG_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+hg_status hg_wgs_static(const float* target, int ny, int nx, int iters, int slm_levels, uint64_t seed,
+                        const uint8_t* init_levels, const hg_complex* init_field,
+                        double wavelength_m, double pitch_m, double z_m,
+                        uint8_t* levels_out, hg_complex* slm_field_out, hg_complex* replay_out,
+                        double* nmse_out, float* weights_inout, void* stream);
+
 /* Static text for a status code, and the thread-local detail of the last
  * error raised on this thread ("" if none). */
 const char* hg_status_string(hg_status status);

@@ -72,6 +72,8 @@ def lib():
         L.hg_wgs.restype = _i
         L.hg_wgs.argtypes = [_vp, _i, _i, _i, _i, _u64, _vp, _vp, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                              _vp]
+        L.hg_wgs_static.restype = _i
+        L.hg_wgs_static.argtypes = [_vp, _i, _i, _i, _i, _u64, _vp, _vp, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp]
         L.hg_gs_step.restype = _i
         L.hg_gs_step.argtypes = [_vp, _i, _i, _i, _i, _vp, _vp, _d, _d, _d, _i, _vp, _vp, _vp, _vp, _vp, _vp,
                                  _vp, _sz, _vp]
@@ -219,7 +221,7 @@ def _workspace(nbytes, dev, workspace):
 
 
 def _gs_call(weighted, target, iters, slm_levels, seed, init_levels, init_field, wavelength_m, pitch_m, z_m,
-             weights, want_field, want_replay, stream, workspace, lt=None):
+             weights, want_field, want_replay, stream, workspace, lt=None, static_scratch=False):
     torch = _torch()
     ny, nx = target.shape
     _dev_tensor(target, torch.float32, (ny, nx), "target")
@@ -231,8 +233,7 @@ def _gs_call(weighted, target, iters, slm_levels, seed, init_levels, init_field,
     if weights is not None:
         _dev_tensor(weights, torch.float32, (ny, nx), "weights")
     op = HG_OP_WGS if weighted else HG_OP_GS
-    nbytes = hg_workspace_size(op, ny, nx, iters)
-    ws = _workspace(nbytes, dev, workspace)
+    ws = None if static_scratch else _workspace(hg_workspace_size(op, ny, nx, iters), dev, workspace)
     levels = torch.empty((ny, nx), dtype=torch.uint8, device=dev) if slm_levels >= 2 else None
     nmse = torch.empty(iters + 1, dtype=torch.float64, device=dev)
     field = torch.empty((ny, nx), dtype=torch.complex64, device=dev) if want_field else None
@@ -244,8 +245,12 @@ def _gs_call(weighted, target, iters, slm_levels, seed, init_levels, init_field,
     args += [_ptr(levels), _ptr(field), _ptr(replay), _ptr(nmse)]
     if weighted:
         args.append(_ptr(weights))
-    args += [_ptr(ws), ws.numel(), _stream(dev, stream)]
-    fn = lib().hg_lt if lt is not None else (lib().hg_wgs if weighted else lib().hg_gs)
+    if static_scratch:
+        args.append(_stream(dev, stream))
+        fn = lib().hg_wgs_static
+    else:
+        args += [_ptr(ws), ws.numel(), _stream(dev, stream)]
+        fn = lib().hg_lt if lt is not None else (lib().hg_wgs if weighted else lib().hg_gs)
     _check(fn(*args))
     return dict(levels=levels, nmse=nmse, field=field, replay=replay, weights=weights)
 
@@ -262,6 +267,17 @@ def hg_wgs(target, iters, slm_levels, seed=0, init_levels=None, init_field=None,
     """Weighted GS on the GPU; `weights` (float32, centred) is read and updated in place."""
     return _gs_call(True, target, iters, slm_levels, seed, init_levels, init_field, wavelength_m, pitch_m, z_m,
                     weights, want_field, want_replay, stream, workspace)
+
+
+def hg_wgs_static(target, iters, slm_levels, seed=0, init_levels=None, init_field=None, wavelength_m=0.0,
+                  pitch_m=0.0, z_m=0.0, weights=None, want_field=False, want_replay=False, stream=None):
+    """hg_wgs without a workspace: the library's static per-GPU scratch
+    (at most HG_STATIC_SCRATCH_BYTES; calls overlapping on one GPU race)."""
+    return _gs_call(True, target, iters, slm_levels, seed, init_levels, init_field, wavelength_m, pitch_m, z_m,
+                    weights, want_field, want_replay, stream, None, static_scratch=True)
+
+
+HG_STATIC_SCRATCH_BYTES = 32 << 20
 
 
 def hg_gs_step(target, slm_levels, levels_in=None, field_in=None, weights=None, lt_radius=-1, wavelength_m=0.0,

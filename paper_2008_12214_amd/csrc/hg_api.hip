@@ -21,6 +21,11 @@
 #include "hologen.h"
 #include "hg_launch.hpp"
 
+// Scratch of hg_wgs_static: one copy of this array per GPU.  Host code uses
+// it only through the per-device address that hipGetSymbolAddress returns
+// (static_scratch below), never by its name.
+static __device__ __align__(256) unsigned char scratch[HG_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 using namespace hg;
@@ -388,12 +393,10 @@ hg_status check_lt(bool weighted, int lt, int r0, int dr) {
   return HG_OK;
 }
 
-hg_status gs_common(bool weighted, const float* target, int ny, int nx, int iters, int L, uint64_t seed,
-                    const uint8_t* init_levels, const hg_complex* init_field, double lambda, double pitch,
-                    double z, uint8_t* levels_out, hg_complex* field_out, hg_complex* replay_out,
-                    double* nmse_out, float* weights, void* ws, size_t ws_bytes, void* stream, int lt = 0,
-                    int lt_r0 = 0, int lt_dr = 0, hg_complex* r_out = nullptr, hg_complex* g_out = nullptr) {
-  g_err[0] = 0;
+// Host-side checks of a GS / WGS / LT call's arguments (no HIP call).
+hg_status check_gs_args(bool weighted, const float* target, int ny, int nx, int iters, int L,
+                        const uint8_t* init_levels, const uint8_t* levels_out, double lambda, double pitch, double z,
+                        int lt, int lt_r0, int lt_dr) {
   hg_status s = check_common(target, ny, nx, iters, L);
   if (s != HG_OK) return s;
   s = check_lt(weighted, lt, lt_r0, lt_dr);
@@ -401,6 +404,18 @@ hg_status gs_common(bool weighted, const float* target, int ny, int nx, int iter
   if (L >= 2 && !levels_out) return fail(HG_ERR_INVALID_ARG, "levels_out is required when slm_levels >= 2");
   if (init_levels && L < 2) return fail(HG_ERR_INVALID_ARG, "init_levels needs slm_levels >= 2");
   if (!optics_ok(lambda, pitch, z)) return fail(HG_ERR_INVALID_ARG, "Fresnel needs wavelength_m > 0 and pitch_m > 0");
+  return HG_OK;
+}
+
+hg_status gs_common(bool weighted, const float* target, int ny, int nx, int iters, int L, uint64_t seed,
+                    const uint8_t* init_levels, const hg_complex* init_field, double lambda, double pitch,
+                    double z, uint8_t* levels_out, hg_complex* field_out, hg_complex* replay_out,
+                    double* nmse_out, float* weights, void* ws, size_t ws_bytes, void* stream, int lt = 0,
+                    int lt_r0 = 0, int lt_dr = 0, hg_complex* r_out = nullptr, hg_complex* g_out = nullptr) {
+  g_err[0] = 0;
+  hg_status s = check_gs_args(weighted, target, ny, nx, iters, L, init_levels, levels_out, lambda, pitch, z, lt,
+                              lt_r0, lt_dr);
+  if (s != HG_OK) return s;
   const int op = weighted ? HG_OP_WGS : HG_OP_GS;
   const Layout Lo = make_layout(op, ny, nx, 1, iters);
   s = check_ws(ws, ws_bytes, Lo.total);
@@ -444,6 +459,30 @@ ClassPlan plan_classes(const P* probs, int count) {
     cp.members[key].push_back(i);
   }
   return cp;
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hg_status static_scratch(void** out) {
+  int dev = -1;
+  const hipError_t ge = hipGetDevice(&dev);
+  if (ge != hipSuccess) return fail(HG_ERR_HIP, "hipGetDevice failed: %s", hipGetErrorString(ge));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HG_ERR_HIP, "device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(HG_ERR_HIP, "hipGetSymbolAddress of the static scratch failed on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HG_OK;
 }
 
 }  // namespace
@@ -560,6 +599,27 @@ hg_status hg_wgs(const float* target, int ny, int nx, int iters, int slm_levels,
                  double* nmse_out, float* weights_inout, void* workspace, size_t workspace_bytes, void* stream) {
   return gs_common(true, target, ny, nx, iters, slm_levels, seed, init_levels, init_field, wavelength_m, pitch_m,
                    z_m, levels_out, slm_field_out, replay_out, nmse_out, weights_inout, workspace, workspace_bytes,
+                   stream);
+}
+
+hg_status hg_wgs_static(const float* target, int ny, int nx, int iters, int slm_levels, uint64_t seed,
+                        const uint8_t* init_levels, const hg_complex* init_field, double wavelength_m,
+                        double pitch_m, double z_m, uint8_t* levels_out, hg_complex* slm_field_out,
+                        hg_complex* replay_out, double* nmse_out, float* weights_inout, void* stream) {
+  g_err[0] = 0;
+  hg_status s = check_gs_args(true, target, ny, nx, iters, slm_levels, init_levels, levels_out, wavelength_m, pitch_m,
+                              z_m, 0, 0, 0);
+  if (s != HG_OK) return s;
+  const size_t need = make_layout(HG_OP_WGS, ny, nx, 1, iters).total;
+  if (need > HG_STATIC_SCRATCH_BYTES)
+    return fail(HG_ERR_WORKSPACE, "hg_wgs_static: %d x %d with %d iterations needs %zu bytes of scratch, "
+                "beyond the static scratch of %zu bytes (use hg_wgs with a workspace)", ny, nx, iters, need,
+                (size_t)HG_STATIC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  s = static_scratch(&ws);
+  if (s != HG_OK) return s;
+  return gs_common(true, target, ny, nx, iters, slm_levels, seed, init_levels, init_field, wavelength_m, pitch_m,
+                   z_m, levels_out, slm_field_out, replay_out, nmse_out, weights_inout, ws, HG_STATIC_SCRATCH_BYTES,
                    stream);
 }
 

@@ -184,3 +184,19 @@ def test_ospr_batched_validation():
     assert L.hg_ospr_batched(probs, 2, 4, 1, FAKE, need - 256, None) == hg.HG_ERR_WORKSPACE
     assert L.hg_ospr_batched(probs, 2, 0, 1, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG  # subframes
 
+
+
+def test_static_scratch_variant_rejects_oversize_before_any_hip_call():
+    """hg_wgs_static checks its arguments and the static scratch's capacity on
+    the host: a 2048^2 problem needs more than HG_STATIC_SCRATCH_BYTES."""
+    def call(ny=64, nx=64, iters=5, levels=2, target=FAKE, levels_out=FAKE):
+        return L.hg_wgs_static(target, ny, nx, iters, levels, 1, None, None, 0.0, 0.0, 0.0, levels_out, None, None,
+                               None, None, None)
+    need = hg.hg_workspace_size(hg.HG_OP_WGS, 2048, 2048, 100)
+    assert need > hg.HG_STATIC_SCRATCH_BYTES
+    assert call(ny=2048, nx=2048, iters=100) == hg.HG_ERR_WORKSPACE
+    assert "static scratch" in hg.hg_last_error()
+    assert hg.hg_workspace_size(hg.HG_OP_WGS, 1024, 1024, 100) <= hg.HG_STATIC_SCRATCH_BYTES
+    assert call(ny=100) == hg.HG_ERR_UNSUPPORTED_SIZE
+    assert call(target=None) == hg.HG_ERR_INVALID_ARG
+    assert call(levels_out=None) == hg.HG_ERR_INVALID_ARG
