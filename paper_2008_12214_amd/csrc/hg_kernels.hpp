@@ -1059,6 +1059,12 @@ __device__ __forceinline__ const float* pin_uniform_ptr(const float* p) {
   return reinterpret_cast<const float*>(((uint64_t)hi << 32) | lo);
 }
 
+// Element at a 32-bit byte offset from a wave-uniform base: lets the
+// compiler address with a scalar base plus one 32-bit VGPR offset.
+template <class T> __device__ __forceinline__ gptr<T> at_bytes(gptr<T> p, uint32_t b) {
+  return (gptr<T>)((__attribute__((address_space(1))) char*)p + b);
+}
+
 // Elements per thread of the tile transforms of k_colp / k_colq (the 16 of
 // every other pass).
 constexpr int kColpE = 16;
@@ -1119,21 +1125,28 @@ __device__ __forceinline__ void colp_prefetch(const Batch& bt, int vt, int tpp, 
   }
 }
 
-// Register-held per-tile inputs: activity, 1/m, the weight array, target
+// Register-held per-tile inputs: activity, 1/m, the weight plane, target
 // and weight columns.
 template <int E> struct ColpIn {
   int active;
   int lt_r;     // Liu-Taghizadeh: radius of this iteration's target square (-1: whole plane)
   float inv_m;
-  float* wout;
+  float* wout;  // the problem's weight plane (wave-uniform)
   float tv[E], wv[E];
 };
+
+// Byte offset of element (t, u) of a 4-byte plane in the 4 x 4 tiled layout;
+// rows t + T j of a tile column lie j T nx elements further on (T a multiple
+// of 4), so one 32-bit offset per element addresses every plane from a
+// wave-uniform base.
+__device__ __forceinline__ uint32_t colp_b0(int t, int u, int nx) { return 4u * tix(t, u, nx); }
 
 // Load tile vt's inputs.  Issued at the end of the previous tile, after its
 // stores, so these loads and that tile's prefetch complete under one wait.
 template <int NY, int C, int MODE, int E>
 __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int tpp, ColpIn<E>& in) {
   constexpr int T = NY / E;
+  static_assert(T % 4 == 0, "row step of whole 4-row groups");
   const int b = vt / tpp, blk = vt - b * tpp;
   const Desc& d = bt.desc[b];
   in.active = d.iters >= k;
@@ -1146,7 +1159,8 @@ __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int
   const int u = blk * C + c;
   const int NX = bt.nx;
   const size_t off = (size_t)b * NY * NX;
-  gptr<const float> tp = to_global(bt.tprep + off);
+  gptr<const float> tp = to_global(uni_ptr(bt.tprep + off));
+  const uint32_t b0 = colp_b0(t, u, NX), bstep = 4u * (uint32_t)(T * NX);
   // The target is zero outside its support Omega, whose rows in this tile the
   // set-up pass recorded: a tile that misses Omega reads no target or
   // weights, one that meets it reads those of its support rows [y0, y1]
@@ -1154,12 +1168,12 @@ __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int
   const double* ps = part_ptr(bt, b, bt.slots - 1, blk);
   const bool meets = ps[1] > 0.0;
   const int y0 = meets ? (int)ps[2] : 0, y1 = meets ? (int)ps[3] : -1;
+  const uint32_t by0 = colp_b0(y0, u, NX);
   if (meets) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const int row = t + T * j;
-      const bool sup = row >= y0 && row <= y1;
-      const float x = tp[tix(sup ? row : y0, u, NX)];
+      const bool sup = t + T * j >= y0 && t + T * j <= y1;
+      const float x = *at_bytes(tp, sup ? b0 + bstep * j : by0);
       in.tv[j] = sup ? x : 0.f;
     }
   } else {
@@ -1168,13 +1182,13 @@ __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int
   }
   if constexpr (MODE == COL_WGS) {
     in.inv_m = bt.invm[b];
-    in.wout = bt.wbuf + off;
+    in.wout = uni_ptr(bt.wbuf + off);
     gptr<const float> w = to_global(in.wout);
     if (meets) {  // weights matter only where the target is nonzero
 #pragma unroll
       for (int j = 0; j < E; ++j) {
-        const int row = t + T * j;
-        in.wv[j] = w[tix(row >= y0 && row <= y1 ? row : y0, u, NX)];
+        const bool sup = t + T * j >= y0 && t + T * j <= y1;
+        in.wv[j] = *at_bytes(w, sup ? b0 + bstep * j : by0);
       }
     }
   }
@@ -1207,6 +1221,7 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
     ColExL<C> ex{Fc + c};
     fft_stage<NY, E, -1, 0>(v, t, tw, ex);
     if constexpr (LATE) colp_load_in<NY, C, MODE, E>(bt, k, vt, tpp, in);
+    const uint32_t b0 = colp_b0(t, u, NX), bstep = 4u * (uint32_t)(T * NX);
     float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f, s_w = 0.f;
     gptr<float> w = nullptr;
     if constexpr (WGS) w = to_global(in.wout);
@@ -1231,7 +1246,7 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
           const float ratio = fmaxf(Tv, kWgsEps) * __builtin_amdgcn_rcpf(fmaxf(A, kWgsEps));
           const float wc = clamp_w(in.wv[j] * ratio * in.inv_m);
           const float wn = __builtin_amdgcn_exp2f(kWgsGamma * __builtin_amdgcn_logf(wc));
-          w[tix(row, u, NX)] = wn;
+          *at_bytes(w, b0 + bstep * j) = wn;
           s_w += wn;
           amp = wn * Tv;
         }
@@ -1262,9 +1277,9 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
       if (threadIdx.x < 3) part_ptr(bt, b, k - 1, blk)[threadIdx.x] = acc;
       else if (WGS) part_ptr(bt, b, k, blk)[3] = acc;
     }
-    gptr<float2> fld = to_global(bt.field + off);
+    gptr<float2> fld = to_global(uni_ptr(bt.field + off));
 #pragma unroll
-    for (int j = 0; j < E; ++j) fld[tix(t + T * j, u, NX)] = v[j];
+    for (int j = 0; j < E; ++j) *at_bytes(fld, 2u * (b0 + bstep * j)) = v[j];
   }
   if (vtn < total) colp_load_in<NY, C, MODE, E>(bt, k, vtn, tpp, in);
   __builtin_amdgcn_s_waitcnt(0);
@@ -1331,11 +1346,6 @@ void k_colq(Batch bt, int k, int nprob) {
       bt, k, vt, total, total, tpp, FA, FA, launder(to_global(bt.tw_y)), red, tot, in);
 }
 
-// Element at a 32-bit byte offset from a wave-uniform base: lets the
-// compiler address with a scalar base plus one 32-bit VGPR offset.
-template <class T> __device__ __forceinline__ gptr<T> at_bytes(gptr<T> p, uint32_t b) {
-  return (gptr<T>)((__attribute__((address_space(1))) char*)p + b);
-}
 
 // OSPR column pass, one 4-column tile per workgroup (k_colq's scheme): for
 // subframe n, finish subframe n-1 (forward transform, accumulate A, NMSE
