@@ -234,10 +234,12 @@ template <class T> __device__ __forceinline__ gptr<T> launder(gptr<T> p) {
 }
 #endif
 
-// Unscaled length-N transform of the data held by this thread group.
+// Unscaled length-N transform of the data held by this thread group, with
+// twiddles from a table in global memory (read as global, not flat, loads:
+// flat loads would also count against LDS completion waits).
 template <int N, int E, int DIR, class Ex>
 __device__ __forceinline__ void fft(float2 (&v)[E], int t, const float2* __restrict__ tw, Ex& ex) {
-  fft_stage<N, E, DIR, 0>(v, t, launder(tw), ex);
+  fft_stage<N, E, DIR, 0>(v, t, launder(to_global(tw)), ex);
 }
 
 // LDS-resident twiddles (kept in the LDS address space so no table read

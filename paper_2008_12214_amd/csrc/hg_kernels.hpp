@@ -1132,6 +1132,7 @@ template <int E> struct ColpIn {
   int lt_r;     // Liu-Taghizadeh: radius of this iteration's target square (-1: whole plane)
   float inv_m;
   float* wout;  // the problem's weight plane (wave-uniform)
+  int y0, y1;   // the tile's first and last support row (y1 < y0: none)
   float tv[E], wv[E];
 };
 
@@ -1168,6 +1169,8 @@ __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int
   const double* ps = part_ptr(bt, b, bt.slots - 1, blk);
   const bool meets = ps[1] > 0.0;
   const int y0 = meets ? (int)ps[2] : 0, y1 = meets ? (int)ps[3] : -1;
+  in.y0 = y0;
+  in.y1 = y1;
   const uint32_t by0 = colp_b0(y0, u, NX);
   if (meets) {
 #pragma unroll
@@ -1223,12 +1226,26 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
     if constexpr (LATE) colp_load_in<NY, C, MODE, E>(bt, k, vt, tpp, in);
     const uint32_t b0 = colp_b0(t, u, NX), bstep = 4u * (uint32_t)(T * NX);
     float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f, s_w = 0.f;
+    float s_off = 0.f;  // unscaled |R|^2 of the elements in row blocks off the support
     gptr<float> w = nullptr;
     if constexpr (WGS) w = to_global(in.wout);
+    // This wave's lanes hold rows tw0 .. tw0 + 64/C - 1 (+ T j).  A block of
+    // rows outside the tile's support rows has T = 0 throughout, so R' = 0
+    // there (weights unused) and only |R|^2 enters the NMSE sums: a
+    // wave-uniform branch skips the constraint (not for Liu-Taghizadeh, whose
+    // free region keeps R, nor for the dumping pass).
+    static_assert(64 % C == 0, "whole columns of lanes per wave");
+    const int tw0 = uni((int)(threadIdx.x >> 6) * (64 / C));
+    const bool all_rows = DUMP || in.lt_r >= 0;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int row = t + T * j;
       const float2 Rr = v[j];  // unscaled replay, centred index (row, u)
+      if (!all_rows && (tw0 + T * j > in.y1 || tw0 + 64 / C - 1 + T * j < in.y0)) {
+        s_off = fmaf(Rr.x, Rr.x, fmaf(Rr.y, Rr.y, s_off));
+        v[j] = make_float2(0.f, 0.f);
+        continue;
+      }
       const float a2 = Rr.x * Rr.x + Rr.y * Rr.y;
       const float inv = a2 > 0.f ? __builtin_amdgcn_rsqf(a2) : 0.f;
       const float A = a2 * inv * bt.fwd_scale;
@@ -1257,6 +1274,7 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
           v[j] = cscale(Rr, bt.fwd_scale);
       }
     }
+    s_aa = fmaf(s_off, bt.fwd_scale * bt.fwd_scale, s_aa);
     // the tile's partial sums: one FP64 sum per wave into this tile's LDS
     // slots now, added over the waves after the inverse transform, whose
     // barriers order the slot writes before those reads (alternate tiles use

