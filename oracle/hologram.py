@@ -36,6 +36,15 @@ Readings where the paper is silent (each is restated in the design notes):
   * Fresnel: single-transform Fresnel with chirp
     Q[y][x] = exp(i pi p^2 ((x - Nx/2)^2 + (y - Ny/2)^2) / (lambda z));
     forward R = centre(DFT(f Q)), backward f = IDFT(uncentre(R)) conj(Q).
+  * Amplitude-modulating SLMs (Background section, the binary and
+    multi-level amplitude schemes): the SLM shows real transmissions
+    k / (L - 1) (slm.project_amplitude).  A non-negative transmission always
+    sends mean(f) sqrt(Nx Ny) into the zero-order pixel (the DC of the
+    centred replay, index (Ny/2, Nx/2)), which no amplitude hologram can
+    control; that pixel is therefore left free (R' = R there, the amplitude
+    freedom of the Algorithms section) and out of the NMSE.  The replay of a
+    real field is centro-symmetric, so the target is symmetrised for every L
+    as for binary phase.  Liu-Taghizadeh and OSPR stay phase-only.
   * OSPR: subframe n draws a uniform random replay phase phi_n, takes the
     binary projection of IDFT(T_n e^{i phi_n}), accumulates |R_n|^2 and
     reports the NMSE of the running-average amplitude sqrt(A_n / n).
@@ -67,12 +76,14 @@ def mirror(T):
     return T[np.ix_(iy, ix)]
 
 
-def prepare_target(T_raw, L):
-    """Target preparation (automatic scaling; binary symmetrisation)."""
+def prepare_target(T_raw, L, amplitude=False):
+    """Target preparation (automatic scaling; symmetrisation for binary phase
+    and for every amplitude SLM, whose real field has a centro-symmetric
+    replay)."""
     T = np.asarray(T_raw, dtype=np.float64)
     if np.any(~np.isfinite(T)) or np.any(T < 0):
         raise ValueError("target amplitude must be finite and non-negative")
-    if L == 2:
+    if L == 2 or amplitude:
         T = np.sqrt(0.5 * (T * T + mirror(T) ** 2))
     e = float(np.sum(T * T))
     if e <= 0.0:
@@ -113,9 +124,18 @@ def _phase_of(R):
     return np.where(A > 0, R / np.where(A > 0, A, 1.0), 1.0 + 0j), A
 
 
-def fienup_error(T, A):
-    """Unscaled replay error sum (|R| - T)^2, the quantity GS never increases."""
-    return float(np.sum((np.asarray(A) - np.asarray(T)) ** 2))
+def fienup_error(T, A, exclude=None):
+    """Unscaled replay error sum (|R| - T)^2, the quantity GS never increases
+    (exclude: a pixel left free, e.g. an amplitude SLM's zero order)."""
+    d = (np.asarray(A, dtype=np.float64) - np.asarray(T, dtype=np.float64)) ** 2
+    if exclude is not None:
+        d[exclude] = 0.0
+    return float(np.sum(d))
+
+
+def zero_order(ny, nx):
+    """Index of the zero-order (DC) pixel of the centred replay plane."""
+    return (ny // 2, nx // 2)
 
 
 def lt_window(ny, nx, r):
@@ -130,24 +150,29 @@ def lt_window(ny, nx, r):
 
 
 def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
-       weighted=False, weights=None, optics=None, batch_item=0, lt=None):
+       weighted=False, weights=None, optics=None, batch_item=0, lt=None, amplitude=False):
     """Gerchberg-Saxton / weighted GS / Liu-Taghizadeh.  Returns a dict of final state.
 
     optics = (wavelength_m, pitch_m, z_m) selects a Fresnel hologram.
     lt = (r0, dr) selects Liu-Taghizadeh (GS only): iteration i = 1..K
     constrains the replay amplitude only inside lt_window(r0 + (i-1) dr)
     and leaves it free (R' = R) outside.
+    amplitude selects an L-level amplitude SLM (GS or weighted GS).
     Keys: field (f_K), levels (k_K or None), g (the last field before
     projection), replay (R_K), nmse (K+1), fienup (K+1), weights (w_K),
     m (mean of w_K on Omega), target (prepared T).
     """
-    T = prepare_target(T_raw, L)
+    if amplitude and (L < 2 or lt is not None):
+        raise ValueError("an amplitude SLM has L >= 2 levels and runs GS or weighted GS")
+    T = prepare_target(T_raw, L, amplitude)
     ny, nx = T.shape
+    dc = zero_order(ny, nx) if amplitude else None
     Q = fresnel_chirp(ny, nx, *optics) if optics is not None else None
     if init_field is not None:
         f = np.asarray(init_field, dtype=np.complex128)
     elif init_levels is not None:
-        f = _slm.level_phasor(np.asarray(init_levels, dtype=np.int64), L)
+        k0 = np.asarray(init_levels, dtype=np.int64)
+        f = _slm.amplitude_value(k0, L) + 0j if amplitude else _slm.level_phasor(k0, L)
     else:
         f = np.exp(1j * _ph.phase_field(seed, _ph.TAG_INIT, ny, nx, batch_item))
     levels = None if init_levels is None else np.asarray(init_levels, np.int64)
@@ -159,17 +184,17 @@ def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
     if lt is not None and weighted:
         raise ValueError("Liu-Taghizadeh is a GS variant: weighted=False")
     for it in range(iters):
-        st = _iterate(T, L, f, Q, weighted, w, m, None if lt is None else lt[0] + it * lt[1])
-        nm.append(_m.nmse(T, st["A"]))
-        fe.append(fienup_error(T, st["A"]))
+        st = _iterate(T, L, f, Q, weighted, w, m, None if lt is None else lt[0] + it * lt[1], amplitude)
+        nm.append(_m.nmse(T, st["A"], dc))
+        fe.append(fienup_error(T, st["A"], dc))
         g, f, levels = st["g"], st["field"], st["levels"]
         if weighted:
             w = st["weights"]
             m = float(np.mean(w[omega])) if np.any(omega) else 1.0
     R = forward(f, Q)
     A = np.abs(R)
-    nm.append(_m.nmse(T, A))
-    fe.append(fienup_error(T, A))
+    nm.append(_m.nmse(T, A, dc))
+    fe.append(fienup_error(T, A, dc))
     return dict(field=f, levels=levels, g=g, replay=R, nmse=np.array(nm),
                 fienup=np.array(fe), weights=w, m=m, target=T)
 
@@ -202,7 +227,7 @@ def ospr_subframe(T, A_prev, n, adaptive, seed=0, batch_item=0):
     return k, g, A, _m.nmse(T, np.sqrt(A / n))
 
 
-def gs_step(T, L, f_prev, weighted=False, w_prev=None, optics=None, lt_r=None, next_nmse=True):
+def gs_step(T, L, f_prev, weighted=False, w_prev=None, optics=None, lt_r=None, next_nmse=True, amplitude=False):
     """One GS / weighted GS / Liu-Taghizadeh iteration from a given state.
 
     T is the PREPARED target (prepare_target), f_prev the SLM field f_{k-1}
@@ -213,29 +238,32 @@ def gs_step(T, L, f_prev, weighted=False, w_prev=None, optics=None, lt_r=None, n
     g (backward of the constrained replay, before projection), field (f_k),
     levels (None for L = 0), weights (w_k or None), nmse (NMSE of R_k) and
     nmse_next (NMSE of the replay of f_k; None when next_nmse is False, which
-    saves its transform).
+    saves its transform).  amplitude: an L-level amplitude SLM (zero order
+    free and out of the NMSE).
     """
     T = np.asarray(T, dtype=np.float64)
     ny, nx = T.shape
+    dc = zero_order(ny, nx) if amplitude else None
     Q = fresnel_chirp(ny, nx, *optics) if optics is not None else None
     m = None
     if weighted:
         w_prev = np.asarray(w_prev, dtype=np.float64)
         omega = T > 0
         m = float(np.mean(w_prev[omega])) if np.any(omega) else 1.0
-    st = _iterate(T, L, np.asarray(f_prev, dtype=np.complex128), Q, weighted, w_prev, m, lt_r)
+    st = _iterate(T, L, np.asarray(f_prev, dtype=np.complex128), Q, weighted, w_prev, m, lt_r, amplitude)
     return dict(replay=st["R"], g=st["g"], field=st["field"], levels=st["levels"],
-                weights=st["weights"] if weighted else None, nmse=_m.nmse(T, st["A"]),
-                nmse_next=_m.nmse(T, np.abs(forward(st["field"], Q))) if next_nmse else None)
+                weights=st["weights"] if weighted else None, nmse=_m.nmse(T, st["A"], dc),
+                nmse_next=_m.nmse(T, np.abs(forward(st["field"], Q)), dc) if next_nmse else None)
 
 
-def _iterate(T, L, f, Q, weighted, w, m, lt_r):
+def _iterate(T, L, f, Q, weighted, w, m, lt_r, amplitude=False):
     """The body of one iteration (Iterative Fourier Transform Algorithms
     section): R = forward(f); replay constraint (GS: R' = T R/|R|, R = 0
     gives T; weighted GS: the weight update, then R' = w T R/|R|;
     Liu-Taghizadeh: R' = T R/|R| inside the square of radius lt_r, R' = R
-    outside); g = backward(R'); f_next = P_L(g).  m is the lagged mean
-    m_{k-1} of the weights over Omega."""
+    outside; an amplitude SLM keeps R' = R at the zero order);
+    g = backward(R'); f_next = P_L(g) (phase) or the nearest transmission
+    (amplitude).  m is the lagged mean m_{k-1} of the weights over Omega."""
     ny, nx = T.shape
     R = forward(f, Q)
     ph, A = _phase_of(R)
@@ -247,8 +275,11 @@ def _iterate(T, L, f, Q, weighted, w, m, lt_r):
         Rp = w * T * ph
     else:
         Rp = T * ph
+    if amplitude:
+        dc = zero_order(ny, nx)
+        Rp[dc] = R[dc]
     g = backward(Rp, Q)
-    f_next, levels = _slm.project(g, L)
+    f_next, levels = _slm.project_amplitude(g, L) if amplitude else _slm.project(g, L)
     return dict(R=R, A=A, g=g, field=f_next, levels=levels, weights=w)
 
 

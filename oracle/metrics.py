@@ -13,7 +13,8 @@ normalised by the target energy,
     NMSE(T, A) = min_s sum (T - s A)^2 / sum T^2
                = 1 - (sum T A)^2 / (sum T^2 * sum A^2)
 
-over the whole replay plane, with s = sum T A / sum A^2.
+over the whole replay plane, with s = sum T A / sum A^2.  For an
+amplitude-modulating SLM the zero-order pixel is left out (see hologram).
 """
 import numpy as np
 
@@ -26,10 +27,14 @@ def mse(T, R):
     return float(np.sum((np.abs(T) - np.abs(R)) ** 2) / (nx * ny))
 
 
-def nmse(T, A):
-    """Scale-optimal normalised MSE of replay amplitude A against target T."""
-    T = np.asarray(T, dtype=np.float64)
-    A = np.asarray(A, dtype=np.float64)
+def nmse(T, A, exclude=None):
+    """Scale-optimal normalised MSE of replay amplitude A against target T;
+    exclude: optional (row, column) of one pixel left out of the sums."""
+    T = np.array(T, dtype=np.float64)
+    A = np.array(A, dtype=np.float64)
+    if exclude is not None:
+        T[exclude] = 0.0
+        A[exclude] = 0.0
     sta = float(np.sum(T * A))
     saa = float(np.sum(A * A))
     stt = float(np.sum(T * T))

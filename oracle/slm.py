@@ -11,6 +11,15 @@ index is k = floor(theta L / (2 pi) + 1/2) mod L with theta = atan2(Im, Re)
 in (-pi, pi].  The listing rounds half away from zero; the two rules only
 differ at exact ties, which parity treats as exempt.  L = 2 is binary phase
 {0, pi}; L = 0 means continuous phase g/|g| (g = 0 maps to 1).
+
+Amplitude-modulating SLMs (Background section: binary and multi-level
+amplitude schemes; the listing's nearest-neighbour rule applied to the
+transmission instead of the phase).  Reading: L uniform transmissions
+a_k = k / (L - 1) in [0, 1] (binary: {0, 1}); the displayed field is real, so
+the nearest a_k to a complex g in the Euclidean sense is the nearest to
+Re g, k = clamp(floor(Re(g) (L - 1) + 1/2), 0, L - 1).  The field g is taken
+at the scale of the unit-rms target (unitary transforms), with no further
+normalisation.
 """
 import numpy as np
 
@@ -49,3 +58,28 @@ def boundary_margin(g, L):
     x = np.mod(theta + half, 2.0 * half)  # position inside the decision cell
     m = np.minimum(x, 2.0 * half - x)
     return np.where(np.abs(g) > 0, m, 0.0)
+
+
+def amplitude_index(g, L):
+    """Nearest transmission level index k in [0, L) of an amplitude SLM."""
+    x = np.real(np.asarray(g, dtype=np.complex128)) * (L - 1)
+    return np.clip(np.floor(x + 0.5), 0, L - 1).astype(np.int64)
+
+
+def amplitude_value(k, L):
+    """Transmission k / (L - 1) of level k of an L-level amplitude SLM."""
+    return np.asarray(k, dtype=np.float64) / (L - 1)
+
+
+def project_amplitude(g, L):
+    """Projection onto an L-level amplitude SLM: (real field as complex, levels)."""
+    k = amplitude_index(g, L)
+    return amplitude_value(k, L) + 0j, k
+
+
+def amplitude_margin(g, L):
+    """Distance (in field units) from Re g to the nearest decision boundary
+    (m + 1/2) / (L - 1), m = 0 .. L - 2, of the amplitude projection."""
+    x = np.real(np.asarray(g, dtype=np.complex128)) * (L - 1)
+    m = np.clip(np.floor(x), 0, L - 2)  # the boundary m + 1/2 below or above x is the nearest
+    return np.abs(x - (m + 0.5)) / (L - 1)

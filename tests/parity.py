@@ -52,16 +52,22 @@ def exempt_bounds(npx, L):
     return dist + int(np.ceil(1e-5 * npx)), dist
 
 
-def level_check(gpu_lev, ref_lev, g_ref, L, where=""):
+def level_check(gpu_lev, ref_lev, g_ref, L, where="", amplitude=False):
     """(non-exempt mismatches, exempt mismatches) of GPU levels against the
     oracle's; prints each non-exempt mismatch and asserts the exempt counts
-    are within exempt_bounds."""
+    are within exempt_bounds.  amplitude: levels of an amplitude SLM, whose
+    decision boundaries are values of Re g (only the distance band applies)."""
     mism = np.asarray(gpu_lev, np.int64) != np.asarray(ref_lev, np.int64)
-    margin = slm.boundary_margin(g_ref, L)
     rms = np.sqrt(np.mean(np.abs(g_ref) ** 2))
-    # Euclidean distance to the nearest boundary ray (margin <= pi/L <= pi/2)
-    zero = mism & (np.abs(g_ref) * np.sin(margin) < DIST * rms)
-    band = mism & (margin < BAND) & ~zero
+    if amplitude:
+        margin = slm.amplitude_margin(g_ref, L)  # a distance in field units
+        zero = mism & (margin < DIST * rms)
+        band = np.zeros_like(mism)
+    else:
+        margin = slm.boundary_margin(g_ref, L)
+        # Euclidean distance to the nearest boundary ray (margin <= pi/L <= pi/2)
+        zero = mism & (np.abs(g_ref) * np.sin(margin) < DIST * rms)
+        band = mism & (margin < BAND) & ~zero
     bad = mism & ~(band | zero)
     if bad.any():
         for y, x in list(zip(*np.nonzero(bad)))[:20]:
