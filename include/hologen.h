@@ -83,11 +83,27 @@ enum hg_op { HG_OP_GS = 1, HG_OP_WGS = 2, HG_OP_OSPR = 3, HG_OP_PROPAGATE = 4 };
  * HG_OP_PROPAGATE.  Returns 0 for unsupported arguments. */
 size_t hg_workspace_size(int op, int ny, int nx, int iters);
 
+/* SLM modulation (Background section: binary and multi-level phase or
+ * amplitude schemes).  slm_levels = L alone selects a phase SLM: 0 is
+ * continuous phase, 2..256 the uniform phases 2 pi k / L (L = 2 is binary
+ * {0, pi}).  slm_levels = L | HG_SLM_AMPLITUDE (2 <= L <= 256) selects an
+ * amplitude SLM with the uniform transmissions k / (L - 1) in [0, 1]
+ * (binary {0, 1}); the projection takes the nearest transmission to Re g, g
+ * at the unit-rms scale of the prepared target.  A non-negative
+ * transmission always sends its mean into the zero-order (DC) pixel of the
+ * replay, centred index (ny/2, nx/2), which no amplitude hologram controls:
+ * for an amplitude SLM that pixel keeps R' = R and is left out of every
+ * NMSE, and the target is symmetrised for every L as for binary phase (a
+ * real field's replay is centro-symmetric).  Amplitude SLMs run in hg_gs,
+ * hg_wgs, hg_gs_step, hg_wgs_static and hg_gs_batched (not Liu-Taghizadeh
+ * or OSPR).  Levels out are the indices k.                                 */
+#define HG_SLM_AMPLITUDE 0x10000
+
 /* Gerchberg-Saxton ("Iterative Fourier Transform Algorithms" section).
  *   target        [ny][nx] float, centred replay-plane amplitude, >= 0, not all 0
  *   iters         >= 1 iterations of: forward transform, replay constraint
  *                 R' = T R/|R| (R = 0 -> T), inverse transform, SLM projection
- *   slm_levels    0 or 2..256
+ *   slm_levels    0 or 2..256 (phase), or L | HG_SLM_AMPLITUDE (see above)
  *   seed          Philox seed of the initial phase (used when both init
  *                 pointers are NULL); the initial field is unquantised
  *   init_levels   nullable [ny][nx] uint8 start levels (< slm_levels, L >= 2)

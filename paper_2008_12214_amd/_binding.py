@@ -278,6 +278,8 @@ def hg_wgs_static(target, iters, slm_levels, seed=0, init_levels=None, init_fiel
 
 
 HG_STATIC_SCRATCH_BYTES = 32 << 20
+# slm_levels flag: an amplitude SLM with the L transmissions k / (L - 1)
+HG_SLM_AMPLITUDE = 0x10000
 
 
 def hg_gs_step(target, slm_levels, levels_in=None, field_in=None, weights=None, lt_radius=-1, wavelength_m=0.0,
@@ -411,7 +413,9 @@ def hg_gs_batched(targets, iters, slm_levels, seeds=None, optics=None, weighted=
                   want_replay=False, stream=None, workspace=None, lt=None, weights=None):
     """Many GS problems (possibly of different sizes) in one call.
 
-    targets: list of float32 CUDA tensors; optics: optional list of
+    targets: list of float32 CUDA tensors; slm_levels: one value for every
+    problem or a list of one per problem (levels, with HG_SLM_AMPLITUDE or-ed
+    in for an amplitude SLM); optics: optional list of
     (wavelength_m, pitch_m, z_m) per problem; init_levels: optional list of
     uint8 start levels (entries may be None); weights: optional list of
     float32 weight tensors (weighted calls read w_0 and write w_K in place;
@@ -421,10 +425,11 @@ def hg_gs_batched(targets, iters, slm_levels, seeds=None, optics=None, weighted=
     torch = _torch()
     dev = targets[0].device
     probs, levels, nmses, replays = [], [], [], []
+    per = list(slm_levels) if isinstance(slm_levels, (list, tuple)) else [slm_levels] * len(targets)
     for i, t in enumerate(targets):
         ny, nx = t.shape
         _dev_tensor(t, torch.float32, (ny, nx), f"targets[{i}]")
-        lv = torch.empty((ny, nx), dtype=torch.uint8, device=dev) if slm_levels >= 2 else None
+        lv = torch.empty((ny, nx), dtype=torch.uint8, device=dev) if per[i] >= 2 else None
         nm = torch.empty(iters + 1, dtype=torch.float64, device=dev)
         rp = torch.empty((ny, nx), dtype=torch.complex64, device=dev) if want_replay else None
         il = init_levels[i] if init_levels is not None else None
@@ -434,7 +439,7 @@ def hg_gs_batched(targets, iters, slm_levels, seeds=None, optics=None, weighted=
         if wt is not None:
             _dev_tensor(wt, torch.float32, (ny, nx), f"weights[{i}]")
         lam, pit, z = optics[i] if optics is not None else (0.0, 0.0, 0.0)
-        probs.append(dict(ny=ny, nx=nx, slm_levels=slm_levels, iters=iters,
+        probs.append(dict(ny=ny, nx=nx, slm_levels=per[i], iters=iters,
                           seed=(seeds[i] if seeds is not None else 0), wavelength_m=lam, pitch_m=pit, z_m=z,
                           target=t, levels_out=lv, nmse_out=nm, init_levels=il, replay_out=rp,
                           lt=(lt[i] if lt is not None else None), weights=wt))

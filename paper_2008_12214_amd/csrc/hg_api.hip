@@ -293,7 +293,7 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
   bool all_bin = true;
   for (const Desc& d : ds) {
     kmax = std::max(kmax, d.iters);
-    all_bin &= (d.L == 2);
+    all_bin &= (d.L == 2 && !d.mod);
   }
   const Cfg cfg = get_cfg(ny, nx, B);
   Batch bt = make_batch(ws, L, ny, nx, cfg.C);
@@ -372,12 +372,20 @@ hg_status check_size(int ny, int nx) {
   return HG_OK;
 }
 
-hg_status check_common(const float* target, int ny, int nx, int iters, int L) {
+// slm_levels: the level count, with HG_SLM_AMPLITUDE or-ed in for an
+// amplitude-modulating SLM.
+int levels_of(int slm_levels) { return slm_levels & ~HG_SLM_AMPLITUDE; }
+int modulation_of(int slm_levels) { return (slm_levels & HG_SLM_AMPLITUDE) ? 1 : 0; }
+
+hg_status check_common(const float* target, int ny, int nx, int iters, int slm_levels) {
   hg_status s = check_size(ny, nx);
   if (s != HG_OK) return s;
   if (!target) return fail(HG_ERR_INVALID_ARG, "target is NULL");
   if (iters < 1) return fail(HG_ERR_INVALID_ARG, "iters=%d must be >= 1", iters);
+  const int L = levels_of(slm_levels);
   if (!(L == 0 || (L >= 2 && L <= 256))) return fail(HG_ERR_INVALID_ARG, "slm_levels=%d: 0 or 2..256", L);
+  if (modulation_of(slm_levels) && L < 2)
+    return fail(HG_ERR_INVALID_ARG, "an amplitude SLM needs 2..256 levels (slm_levels=%d)", L);
   return HG_OK;
 }
 
@@ -401,6 +409,8 @@ hg_status check_gs_args(bool weighted, const float* target, int ny, int nx, int 
   if (s != HG_OK) return s;
   s = check_lt(weighted, lt, lt_r0, lt_dr);
   if (s != HG_OK) return s;
+  if (lt && modulation_of(L)) return fail(HG_ERR_INVALID_ARG, "Liu-Taghizadeh runs on phase SLMs only");
+  L = levels_of(L);
   if (L >= 2 && !levels_out) return fail(HG_ERR_INVALID_ARG, "levels_out is required when slm_levels >= 2");
   if (init_levels && L < 2) return fail(HG_ERR_INVALID_ARG, "init_levels needs slm_levels >= 2");
   if (!optics_ok(lambda, pitch, z)) return fail(HG_ERR_INVALID_ARG, "Fresnel needs wavelength_m > 0 and pitch_m > 0");
@@ -432,7 +442,8 @@ hg_status gs_common(bool weighted, const float* target, int ny, int nx, int iter
   d.init_field = reinterpret_cast<const float2*>(init_field);
   d.seed = seed;
   d.item = 0;
-  d.L = L;
+  d.L = levels_of(L);
+  d.mod = modulation_of(L);
   d.iters = iters;
   d.lt = lt ? 1 : 0;
   d.lt_r0 = lt_r0;
@@ -799,11 +810,14 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
       std::string msg = g_err;
       return fail(s, "problem %d: %s", i, msg.c_str());
     }
-    if (p.slm_levels >= 2 && !p.levels_out) return fail(HG_ERR_INVALID_ARG, "problem %d: levels_out required", i);
+    if (levels_of(p.slm_levels) >= 2 && !p.levels_out)
+      return fail(HG_ERR_INVALID_ARG, "problem %d: levels_out required", i);
     if (!optics_ok(p.wavelength_m, p.pitch_m, p.z_m))
       return fail(HG_ERR_INVALID_ARG, "problem %d: Fresnel needs wavelength_m > 0 and pitch_m > 0", i);
-    if (p.init_levels && p.slm_levels < 2)
+    if (p.init_levels && levels_of(p.slm_levels) < 2)
       return fail(HG_ERR_INVALID_ARG, "problem %d: init_levels needs slm_levels >= 2", i);
+    if (p.lt && modulation_of(p.slm_levels))
+      return fail(HG_ERR_INVALID_ARG, "problem %d: Liu-Taghizadeh runs on phase SLMs only", i);
     s = check_lt(weighted != 0, p.lt, p.lt_r0, p.lt_dr);
     if (s != HG_OK) {
       std::string msg = g_err;
@@ -831,7 +845,8 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
       d.replay_out = reinterpret_cast<float2*>(p.replay_out);
       d.seed = p.seed;
       d.item = (uint32_t)i;
-      d.L = p.slm_levels;
+      d.L = levels_of(p.slm_levels);
+      d.mod = modulation_of(p.slm_levels);
       d.iters = p.iters;
       d.lt = p.lt ? 1 : 0;
       d.lt_r0 = p.lt_r0;

@@ -353,6 +353,15 @@ __device__ __forceinline__ float2 level_phasor(int k, int L) {
   return make_float2(c, s);
 }
 
+// Amplitude SLM with L uniform transmissions k / (L - 1): the nearest to
+// Re g is k = clamp(floor(Re g (L - 1) + 1/2), 0, L - 1).  s_lm1 carries the
+// scale of g (1/sqrt(nx ny) for an unscaled transform) times L - 1.
+__device__ __forceinline__ int amp_level(float gx, float s_lm1, int L) {
+  const int k = (int)floorf(gx * s_lm1 + 0.5f);
+  return min(max(k, 0), L - 1);
+}
+__device__ __forceinline__ float amp_value(int k, int L) { return (float)k / (float)(L - 1); }
+
 __device__ __forceinline__ float2 unit_phase(float2 g) {
   const float m2 = g.x * g.x + g.y * g.y;
   if (!(m2 > 0.0f) || !(m2 < 3.0e38f)) return make_float2(1.0f, 0.0f);

@@ -33,6 +33,7 @@ struct Desc {
   uint64_t seed;
   uint32_t item;              // Philox item
   int L;                      // SLM levels (0 = continuous)
+  int mod;                    // 1: amplitude SLM (transmissions k / (L - 1)); 0: phase SLM
   int iters;                  // GS iterations / OSPR subframes
   int user_weights;           // weights came from the caller
   int lt;                     // Liu-Taghizadeh: constrain only the growing centred square
@@ -331,7 +332,7 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_prepare(Batch bt, int weighte
     const int v = t + T * j;
     const size_t idx = (size_t)v * bt.nx + u;
     float tv = d.target[idx];
-    if (d.L == 2) {
+    if (d.L == 2 || d.mod) {  // binary phase or amplitude SLM: centro-symmetric replay
       const int vm = (bt.ny - v) & (bt.ny - 1);
       const float tm = d.target[(size_t)vm * bt.nx + um];
       tv = sqrtf(0.5f * (tv * tv + tm * tm));
@@ -498,7 +499,9 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
 #pragma unroll
         for (int j = 0; j < E; ++j) {
           const size_t idx = (size_t)y * NX + t + T * j;
-          v[j] = d.init_field ? d.init_field[idx] : level_phasor(d.init_levels[idx], d.L);
+          v[j] = d.init_field ? d.init_field[idx]
+                 : d.mod ? make_float2(amp_value(d.init_levels[idx], d.L), 0.f)
+                         : level_phasor(d.init_levels[idx], d.L);
         }
       } else {
         // initial phase: Philox words over row lines; element j = g + (E/4) w
@@ -515,13 +518,15 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
       const int iters = uni(d.iters);
       if (MODE == ROW_ITER && arg > iters) return;  // uniform per block
       const int L = (MODE == ROW_OSPR || LK == LK_BIN) ? 2 : uni(d.L);
+      const bool amp = (MODE == ROW_ITER && LK == LK_ANY) && uni(d.mod);  // amplitude SLM
+      const float amp_s = bt.fwd_scale * (float)(L - 1);  // unitary scale times L - 1
       const bool last = (MODE == ROW_OSPR) || (arg == iters);
       gptr<uint8_t> lev = to_global(uni_ptr(d.levels_out));
       gptr<float2> fout = to_global(uni_ptr(d.field_out));
       gptr<float2> gdump = to_global(uni_ptr(d.g_out));
       if (MODE == ROW_OSPR) lev += (size_t)(arg - 1) * bt.ny * NX;
       if constexpr (TAB) {
-        if (L > 2) {  // uniform per block
+        if (L > 2 && !amp) {  // uniform per block
           for (int i = threadIdx.x; i < L; i += RPB * T) lvl[i] = level_phasor(i, L);
           __syncthreads();
         }
@@ -551,6 +556,12 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
           float2 f;
           if constexpr (KIND == 0) {
             f = unit_phase(g);
+          } else if constexpr (KIND == 5) {  // amplitude SLM: nearest transmission to Re g
+            const int k = amp_level(g.x, amp_s, L);
+            f = make_float2(amp_value(k, L), 0.f);
+            if constexpr (WR) {
+              if (lev) lev[(size_t)y * NX + x] = (uint8_t)k;
+            }
           } else {
             const int k = KIND == 4 ? level_index_quad(g, L) : level_index(g, KIND == 2 ? 2 : L);
             if constexpr (KIND == 2) f = level_phasor(k, 2);
@@ -568,7 +579,8 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
       };
       auto by_kind = [&](auto wr) {
         if constexpr (TAB) {
-          if (L == 2) project(std::integral_constant<int, 2>{}, wr);
+          if (amp) project(std::integral_constant<int, 5>{}, wr);
+          else if (L == 2) project(std::integral_constant<int, 2>{}, wr);
           else if (L == 0) project(std::integral_constant<int, 0>{}, wr);
           else if (L == 4 || L == 8) project(std::integral_constant<int, 4>{}, wr);
           else project(std::integral_constant<int, 3>{}, wr);
@@ -677,6 +689,10 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
       w = to_global(bt.wbuf + off);
     }
     const int ltr = LT ? uni(lt_radius(d, k, NY, NX)) : 0;
+    // amplitude SLM: the zero order (row NY/2 = element E/2 of t = 0, column
+    // nx/2) keeps R and stays out of the NMSE sums
+    static_assert(T * (E / 2) == NY / 2, "the zero order is element E/2 of thread row 0");
+    const bool zo = d.mod && t == 0 && u == (NX >> 1);
 #pragma unroll
     for (int j = 0; j < E; ++j) v[j] = fld[tix(t + T * j, u, NX)];
     fft<NY, E, -1>(v, t, bt.tw_y, ex);
@@ -690,9 +706,12 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
       const float inv = a2 > 0.f ? __builtin_amdgcn_rsqf(a2) : 0.f;
       const float A = a2 * inv * bt.fwd_scale;  // |R| of the unitary transform
       const float Tv = tp[ti];
-      s_ta += Tv * A;
-      s_aa += A * A;
-      s_tt += Tv * Tv;
+      const bool zj = j == E / 2 && zo;
+      if (!zj) {
+        s_ta += Tv * A;
+        s_aa += A * A;
+        s_tt += Tv * Tv;
+      }
       if constexpr (MODE == COL_FINAL) {
         if (d.replay_out) to_global(d.replay_out)[idx] = cscale(Rr, bt.fwd_scale);
       } else {
@@ -715,6 +734,7 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
           const bool out = max(abs(t + T * j - (NY >> 1)), abs(u - (NX >> 1))) > ltr;
           v[j] = out ? cscale(Rr, bt.fwd_scale) : v[j];
         }
+        if (zj) v[j] = cscale(Rr, bt.fwd_scale);
       }
     }
     block_sum4<NT>(s_ta, s_aa, s_tt, s_w, red, tot);
@@ -882,6 +902,10 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
   if constexpr (MODE == COL_WGS) w = launder(w);
   float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f, s_w = 0.f;
   if constexpr (GSK) {
+    // amplitude SLM: the zero order (row NY/2 = element E/2 of r0 = 0, column
+    // nx/2) keeps R and stays out of the NMSE sums
+    static_assert(T * (E / 2) == NY / 2, "the zero order is element E/2 of thread row 0");
+    const bool zo = d.mod && r0 == 0 && u == (NX >> 1);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int row = r0 + T * i;
@@ -892,9 +916,12 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
       const float inv = a2 > 0.f ? __builtin_amdgcn_rsqf(a2) : 0.f;
       const float A = a2 * inv * bt.fwd_scale;  // |R| of the unitary transform
       const float Tv = tp[ti];
-      s_ta += Tv * A;
-      s_aa += A * A;
-      s_tt += Tv * Tv;
+      const bool zj = i == E / 2 && zo;
+      if (!zj) {
+        s_ta += Tv * A;
+        s_aa += A * A;
+        s_tt += Tv * Tv;
+      }
       if constexpr (MODE == COL_FINAL) {
         if (d.replay_out) to_global(d.replay_out)[idx] = cscale(Rr, bt.fwd_scale);
       } else {
@@ -917,6 +944,7 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
           const bool out = max(abs(row - (NY >> 1)), abs(u - (NX >> 1))) > ltr;
           if (out) mine[lds_pad(row)] = cscale(Rr, bt.fwd_scale);
         }
+        if (zj) mine[lds_pad(row)] = cscale(Rr, bt.fwd_scale);
       }
     }
     block_sum4<NT>(s_ta, s_aa, s_tt, s_w, red, tot);  // ends with a barrier
@@ -1133,6 +1161,7 @@ template <int E> struct ColpIn {
   float inv_m;
   float* wout;  // the problem's weight plane (wave-uniform)
   int y0, y1;   // the tile's first and last support row (y1 < y0: none)
+  int zo;       // amplitude SLM and the tile holds column nx/2: the zero order is here
   float tv[E], wv[E];
 };
 
@@ -1159,6 +1188,7 @@ __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int u = blk * C + c;
   const int NX = bt.nx;
+  in.zo = d.mod && blk == (NX >> 1) / C;
   const size_t off = (size_t)b * NY * NX;
   gptr<const float> tp = to_global(uni_ptr(bt.tprep + off));
   const uint32_t b0 = colp_b0(t, u, NX), bstep = 4u * (uint32_t)(T * NX);
@@ -1237,11 +1267,16 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
     static_assert(64 % C == 0, "whole columns of lanes per wave");
     const int tw0 = uni((int)(threadIdx.x >> 6) * (64 / C));
     const bool all_rows = DUMP || in.lt_r >= 0;
+    // amplitude SLM: the zero order (row NY/2 = t + T E/2 with t = 0, column
+    // nx/2) keeps R and stays out of the NMSE sums
+    static_assert(T * (E / 2) == NY / 2, "the zero order is element E/2 of thread row 0");
+    const bool zo = in.zo && t == 0 && u == (NX >> 1);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int row = t + T * j;
       const float2 Rr = v[j];  // unscaled replay, centred index (row, u)
-      if (!all_rows && (tw0 + T * j > in.y1 || tw0 + 64 / C - 1 + T * j < in.y0)) {
+      const bool zj = j == E / 2 && zo;
+      if (!all_rows && !(j == E / 2 && in.zo) && (tw0 + T * j > in.y1 || tw0 + 64 / C - 1 + T * j < in.y0)) {
         s_off = fmaf(Rr.x, Rr.x, fmaf(Rr.y, Rr.y, s_off));
         v[j] = make_float2(0.f, 0.f);
         continue;
@@ -1250,9 +1285,11 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
       const float inv = a2 > 0.f ? __builtin_amdgcn_rsqf(a2) : 0.f;
       const float A = a2 * inv * bt.fwd_scale;
       const float Tv = in.tv[j];
-      s_ta += Tv * A;
-      s_aa += A * A;
-      s_tt += Tv * Tv;
+      if (!zj) {
+        s_ta += Tv * A;
+        s_aa += A * A;
+        s_tt += Tv * Tv;
+      }
       if constexpr (DUMP) {  // one-iteration calls: the replay before the constraint
         const Desc& dd = bt.desc[b];
         if (dd.r_out) to_global(dd.r_out)[(size_t)row * NX + u] = cscale(Rr, bt.fwd_scale);
@@ -1273,6 +1310,7 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
         if (in.lt_r >= 0 && max(abs(t + T * j - (NY >> 1)), abs(u - (NX >> 1))) > in.lt_r)
           v[j] = cscale(Rr, bt.fwd_scale);
       }
+      if (zj) v[j] = cscale(Rr, bt.fwd_scale);
     }
     s_aa = fmaf(s_off, bt.fwd_scale * bt.fwd_scale, s_aa);
     // the tile's partial sums: one FP64 sum per wave into this tile's LDS

@@ -72,6 +72,7 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
   const int b = blockIdx.x;
   const Desc& d = bt.desc[b];
   const int L = uni(d.L), iters = uni(d.iters);
+  const int amp = uni(d.mod);  // amplitude SLM
   const int user_w = uni(d.user_weights);
   gptr<const float> tg = to_global(uni_ptr(d.target));
   gptr<uint8_t> lev = to_global(uni_ptr(d.levels_out));
@@ -93,7 +94,7 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
   if constexpr (NY != NX) {
     for (int i = threadIdx.x; i < S::TWY; i += NT) twiddle_entry<NY, 1, E>(twy_s, i);
   }
-  if (L > 2) {
+  if (L > 2 && !amp) {
     for (int i = threadIdx.x; i < L; i += NT) lvl_s[i] = level_phasor(i, L);
   }
   const lptr<const float2> twx = (lptr<const float2>)twx_s;
@@ -121,7 +122,7 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
     const int y = ct + TC * j;
     const int idx = y * NX + cu;
     float tv = tg[idx];
-    if (L == 2) {
+    if (L == 2 || amp) {  // binary phase or amplitude SLM: centro-symmetric replay
       const int ym = (NY - y) & (NY - 1);
       const float tm = tg[ym * NX + um];
       tv = sqrtf(0.5f * (tv * tv + tm * tm));
@@ -155,7 +156,7 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         const int idx = ry * NX + rt + TR * j;
-        v[j] = init_f ? init_f[idx] : level_phasor(init_l[idx], L);
+        v[j] = init_f ? init_f[idx] : amp ? make_float2(amp_value(init_l[idx], L), 0.f) : level_phasor(init_l[idx], L);
       }
     } else {
       // Philox words over row lines; element j = g + (E/4) w
@@ -188,6 +189,10 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
     fft_lds<NY, E, -1>(v, ct, twy, cex);
     const float inv_m = WEIGHTED ? (float)((omega > 0.0 ? omega : 1.0) / wsum) : 1.0f;
     float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f, s_w = 0.f;
+    // amplitude SLM: the zero order (row NY/2 = element E/2 of ct = 0, column
+    // NX/2) keeps R and stays out of the NMSE sums
+    static_assert(TC * (E / 2) == NY / 2, "the zero order is element E/2 of column thread 0");
+    const bool zo = amp && ct == 0 && cu == (NX >> 1);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int idx = (ct + TC * j) * NX + cu;
@@ -196,14 +201,17 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
       const float inv = a2 > 0.f ? __builtin_amdgcn_rsqf(a2) : 0.f;
       const float A = a2 * inv * bt.fwd_scale;  // |R| of the unitary transform
       const float Tv = tp[idx];
-      s_ta += Tv * A;
-      s_aa += A * A;
-      s_tt += Tv * Tv;
+      const bool zj = j == E / 2 && zo;
+      if (!zj) {
+        s_ta += Tv * A;
+        s_aa += A * A;
+        s_tt += Tv * Tv;
+      }
       if (fin) {
         if (rout) rout[idx] = cscale(Rr, bt.fwd_scale);
       } else {
         if (rdump) rdump[idx] = cscale(Rr, bt.fwd_scale);
-        float amp = Tv;
+        float tamp = Tv;
         if constexpr (WEIGHTED) {
           if (Tv > 0.f) {
             const float ratio = fmaxf(Tv, kWgsEps) * __builtin_amdgcn_rcpf(fmaxf(A, kWgsEps));
@@ -211,10 +219,11 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
             const float wn = __builtin_amdgcn_exp2f(kWgsGamma * __builtin_amdgcn_logf(wc));
             w[idx] = wn;
             s_w += wn;
-            amp = wn * Tv;
+            tamp = wn * Tv;
           }
         }
-        v[j] = a2 > 0.f ? cscale(Rr, amp * inv) : make_float2(amp, 0.f);
+        v[j] = a2 > 0.f ? cscale(Rr, tamp * inv) : make_float2(tamp, 0.f);
+        if (zj) v[j] = cscale(Rr, bt.fwd_scale);
       }
     }
     block_sum4<NT>(s_ta, s_aa, s_tt, s_w, red, tot);
@@ -235,6 +244,7 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
     for (int j = 0; j < E; ++j) v[j] = rex.base[lds_pad(rt + TR * j)];
     fft_lds<NX, E, +1>(v, rt, twx, rex);
     const bool last = (k == iters);
+    const float amp_s = bt.fwd_scale * (float)(L - 1);  // unitary scale times L - 1
     auto project = [&](auto kind, auto wr) {
       constexpr int KIND = decltype(kind)::value;  // 0 continuous, 2 binary, 3 other L
       constexpr bool WR = decltype(wr)::value;     // last iteration: write levels and field
@@ -246,6 +256,12 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
         float2 f;
         if constexpr (KIND == 0) {
           f = unit_phase(g);
+        } else if constexpr (KIND == 5) {  // amplitude SLM: nearest transmission to Re g
+          const int kl = amp_level(g.x, amp_s, L);
+          f = make_float2(amp_value(kl, L), 0.f);
+          if constexpr (WR) {
+            if (lev) lev[ry * NX + x] = (uint8_t)kl;
+          }
         } else {
           const int kl = level_index(g, KIND == 2 ? 2 : L);
           if constexpr (KIND == 2) f = level_phasor(kl, 2);
@@ -262,7 +278,8 @@ __global__ __launch_bounds__((NY * NX / small_elements<NY, NX>())) void k_small(
       }
     };
     auto by_kind = [&](auto wr) {
-      if (L == 2) project(std::integral_constant<int, 2>{}, wr);
+      if (amp) project(std::integral_constant<int, 5>{}, wr);
+      else if (L == 2) project(std::integral_constant<int, 2>{}, wr);
       else if (L == 0) project(std::integral_constant<int, 0>{}, wr);
       else project(std::integral_constant<int, 3>{}, wr);
     };

@@ -200,3 +200,16 @@ def test_static_scratch_variant_rejects_oversize_before_any_hip_call():
     assert call(ny=100) == hg.HG_ERR_UNSUPPORTED_SIZE
     assert call(target=None) == hg.HG_ERR_INVALID_ARG
     assert call(levels_out=None) == hg.HG_ERR_INVALID_ARG
+
+
+def test_amplitude_slm_argument_checks():
+    """slm_levels = L | HG_SLM_AMPLITUDE needs 2 <= L <= 256 and is not
+    accepted by Liu-Taghizadeh; the checks run on the host."""
+    A = hg.HG_SLM_AMPLITUDE
+    assert _gs(levels=A) == hg.HG_ERR_INVALID_ARG
+    assert _gs(levels=A | 1) == hg.HG_ERR_INVALID_ARG
+    assert _gs(levels=A | 257) == hg.HG_ERR_INVALID_ARG
+    assert _gs(levels=A | 4, levels_out=None) == hg.HG_ERR_INVALID_ARG
+    assert L.hg_lt(FAKE, 64, 64, 5, A | 2, 1, None, None, 0.0, 0.0, 0.0, 4, 1, FAKE, None, None, None, FAKE,
+                   1 << 30, None) == hg.HG_ERR_INVALID_ARG
+    assert "phase SLMs" in hg.hg_last_error()
