@@ -111,6 +111,68 @@ def cpu_baseline(budget_s=20.0):
                       f"evaluation), FP64 DFT-matrix oracle, {dt:.1f} s"}
 
 
+def oracle_scaling(sizes=(64, 512, 1024, 2048)):
+    """Seconds per weighted binary GS iteration of the FP64 oracle at several
+    grid sizes, on every BLAS thread of this host and on one: context for the
+    cpu_baseline figure (one iteration per size and thread count, after a
+    warm-up iteration at the smaller sizes)."""
+    import platform
+    import numpy as np
+    import synth
+    from oracle import hologram
+    from threadpoolctl import threadpool_info, threadpool_limits
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    out = {"cpu_model": model, "logical_cpus": os.cpu_count(), "blas_threads": threads, "per_iteration_s": {}}
+    for n in sizes:
+        T = hologram.prepare_target(synth.gaussian_target(n, seed=2), 2)
+        f = np.exp(2j * np.pi * np.random.default_rng(1).random((n, n)))
+        w = np.ones((n, n))
+        row = {}
+        for label, limit in (("all_threads", None), ("one_thread", 1)):
+            with threadpool_limits(limits=limit):
+                if n <= 1024:
+                    hologram.gs_step(T, 2, f, weighted=True, w_prev=w, next_nmse=False)
+                t0 = time.perf_counter()
+                hologram.gs_step(T, 2, f, weighted=True, w_prev=w, next_nmse=False)
+                row[label] = round(time.perf_counter() - t0, 4)
+        out["per_iteration_s"][f"{n}x{n}"] = row
+        log(f"oracle {n}^2: {row}")
+    return out
+
+
+def learned_time_to_nmse(n_eval=64):
+    """The learned start (trained weights shipped with the package) against
+    plain GS from a random phase and against GS from the quadratic start, on
+    held-out 512^2 targets with 8 levels: the time-to-NMSE half of the
+    metric.  Returns a compact summary (medians over the targets)."""
+    import torch
+    from paper_2008_12214_amd import learned
+    dev = torch.device("cuda:0")
+    params = learned.load_params(device=dev)
+    targets = learned.make_targets(512, range(900000, 900000 + n_eval), device=dev)
+    r = learned.evaluate(params, targets, levels=8, refine=10, gs_iters=200)
+    L, Q = r["learned"], r["quadratic_only"]
+    return {"workload": f"learned start + 10 GS, 512x512, 8 levels, {n_eval} held-out targets",
+            "learned_final_nmse_median": round(L["final_nmse_median"], 5),
+            "plain_gs_nmse_median_at_200": round(r["gs_nmse_median_at"]["200"], 5),
+            "plain_gs_reached_fraction": L["gs_reached_fraction"],
+            "time_gain_vs_plain_gs_median": round(L["time_gain_median"], 3),
+            "time_gain_vs_plain_gs_is_lower_bound": L["gs_reached_fraction"] < 1.0,
+            "time_gain_vs_quadratic_start_gs_median": round(L["time_gain_vs_quadratic_gs_median"], 3),
+            "quadratic_only_final_nmse_median": round(Q["final_nmse_median"], 5),
+            "quadratic_only_time_gain_vs_plain_gs_median": round(Q["time_gain_median"], 3),
+            "network_forward_us_per_image": round(r["forward_ms_batch"] / n_eval * 1e3, 2),
+            "gs_us_per_hologram_iteration": round(r["gs_ms_per_iter_batch"] / n_eval * 1e3, 3)}
+
+
 def torchfft_context(B, iters=10):
     """Context only, not the product: the weighted binary GS loop of the default
     workload written as unfused torch ops on the same GPU (torch.fft = rocFFT,
@@ -404,6 +466,7 @@ def main():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-b1", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-start time-to-NMSE leg")
     ap.add_argument("--iters", type=int, default=100,
                     help="iterations per hologram (100 is the workload; fewer only for short profiles)")
     ap.add_argument("--workload", default="wgs1024",
@@ -416,11 +479,16 @@ def main():
                          "headline batch on a binary amplitude SLM")
     ap.add_argument("--context", action="store_true",
                     help="also time the same loop as unfused torch.fft (rocFFT) ops, for context")
+    ap.add_argument("--oracle-scaling", action="store_true",
+                    help="only time the FP64 oracle per iteration at 64^2..2048^2 on all BLAS threads and on one")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.oracle_scaling:
+        print(json.dumps({"oracle_scaling": oracle_scaling()}), flush=True)
         return
     global ITERS
     ITERS = args.iters
@@ -529,6 +597,16 @@ def main():
         log(f"torch.fft loop {ctx['iter_per_s']:.0f} hologram-iterations/s")
         torch.cuda.empty_cache()
 
+    learned_summary = None
+    if not args.no_learned:
+        log("learned start: time to NMSE")
+        try:
+            learned_summary = learned_time_to_nmse()
+        except Exception as e:  # reported, not fatal: the headline line is still printed
+            learned_summary = {"error": f"{type(e).__name__}: {e}"}
+        log(f"learned start: {learned_summary}")
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -552,7 +630,7 @@ def main():
                   "whole_iteration_algorithmic_GBs": round(iter_gbs, 1),
                   "whole_iteration_frac": round(iter_gbs / HBM_PEAK_GBS, 4),
                   "per_hologram_iter_per_s": round(value / B, 1), "b1": b1, "library_context": ctx,
-                  "final_nmse_item0": nm_final},
+                  "final_nmse_item0": nm_final, "learned_init": learned_summary},
     }
     print(json.dumps(out), flush=True)
 

@@ -282,10 +282,24 @@ def main(argv=None):
     ap.add_argument("--save", default=None, help="write the trained parameters (.npy)")
     ap.add_argument("--load", default=None, help="skip training and load parameters (.npy)")
     ap.add_argument("--out", default=None, help="write the evaluation as JSON")
+    ap.add_argument("--profile", type=int, default=0,
+                    help="only run 3 forward + backward passes of the shipped network on this many targets "
+                         "(for a kernel trace) and print their times")
     a = ap.parse_args(argv)
     torch = _torch()
     dev = torch.device("cuda:0")
     n = a.size
+    if a.profile:
+        params = load_params(device=dev)
+        T = make_targets(n, range(900000, 900000 + a.profile), dev)
+        labels, _ = make_labels(T, a.levels, 20)
+        ws = B.hg_nn_workspace(a.profile, n, n, dev)
+        fwd = _time(lambda: B.hg_nn_forward(params, T, ws))
+        out = B.hg_nn_forward(params, T, ws)
+        bwd = _time(lambda: B.hg_nn_backward(params, out, labels, T, ws))
+        print(json.dumps({"batch": a.profile, "size": n, "forward_ms": fwd, "backward_ms": bwd,
+                          "forward_us_per_image": fwd / a.profile * 1e3}), flush=True)
+        return
     t0 = time.time()
     res = {}
     if a.load:
