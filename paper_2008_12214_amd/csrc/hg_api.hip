@@ -316,7 +316,9 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
   if (ny != nx) launch_twiddles(const_cast<float2*>(bt.tw_y), ny, st);
   if (fresnel) launch_chirps(const_cast<float2*>(bt.chirp), ny, nx, rates, st);
   launch_setup(bt, cfg.C, B, weighted ? 1 : 0, st);
-  const int lk = all_bin ? LK_BIN : LK_ANY;
+  bool all_quad = true;
+  for (const Desc& d : ds) all_quad &= ((d.L == 4 || d.L == 8) && !d.mod);
+  const int lk = all_bin ? LK_BIN : all_quad ? LK_QUAD : LK_ANY;
   launch_row(bt, cfg.RPB, B, fresnel, lk, ROW_INIT, 0, nullptr, nullptr, st);
   const int cmode = weighted ? COL_WGS : COL_GS;
   for (int k = 1; k <= kmax; ++k) {

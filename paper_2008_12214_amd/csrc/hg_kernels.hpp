@@ -375,7 +375,11 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_prepare(Batch bt, int weighte
 // row pass
 // ---------------------------------------------------------------------------
 enum RowMode { ROW_INIT = 0, ROW_ITER = 1, ROW_OSPR = 2, ROW_PROP_FWD = 3, ROW_PROP_BWD = 4 };
-enum LevelKind { LK_ANY = 0, LK_BIN = 1 };  // LK_BIN: every problem of the launch has L = 2
+// LK_BIN: every problem of the launch is binary phase (L = 2); LK_QUAD: every
+// problem is 4- or 8-level phase (quadrant decision, no arctangent).  A
+// launch-wide kind keeps the other projections' code, and its registers,
+// out of the kernel.
+enum LevelKind { LK_ANY = 0, LK_BIN = 1, LK_QUAD = 2 };
 
 // Modulation m[y][x] applied before the forward row FFT and conjugated after
 // the inverse one: (-1)^(x+y) for Fourier, chirp * (-1)^(x+y) for Fresnel
@@ -457,7 +461,7 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
   constexpr int NBUF = PP ? 2 : 1;
   __shared__ __align__(16) float2 lds[XCH ? RPB * NBUF * LW : 1];
   // phasors of the problem's levels (general L, projection only)
-  constexpr bool TAB = (MODE == ROW_ITER && LK == LK_ANY);
+  constexpr bool TAB = (MODE == ROW_ITER && (LK == LK_ANY || LK == LK_QUAD));
   __shared__ float2 lvl[TAB ? 256 : 1];
   const int b = blockIdx.y;
   const int r = threadIdx.x / T, t = threadIdx.x % T;
@@ -578,7 +582,9 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
         }
       };
       auto by_kind = [&](auto wr) {
-        if constexpr (TAB) {
+        if constexpr (LK == LK_QUAD) {
+          project(std::integral_constant<int, 4>{}, wr);  // every problem 4 or 8 levels
+        } else if constexpr (TAB) {
           if (amp) project(std::integral_constant<int, 5>{}, wr);
           else if (L == 2) project(std::integral_constant<int, 2>{}, wr);
           else if (L == 0) project(std::integral_constant<int, 0>{}, wr);
