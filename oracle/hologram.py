@@ -45,6 +45,17 @@ Readings where the paper is silent (each is restated in the design notes):
     freedom of the Algorithms section) and out of the NMSE.  The replay of a
     real field is centro-symmetric, so the target is symmetrised for every L
     as for binary phase.  Liu-Taghizadeh and OSPR stay phase-only.
+  * 16-bit field storage (Floating Points section: 16-, 32- and 64-bit
+    builds, throughput about inversely proportional to the bits): the
+    complex field is held between the two halves of each transform pair as
+    two IEEE binary16 values, arithmetic stays at full precision.  The
+    halves are the row transform (SLM plane -> rows transformed) and the
+    column transform; the stored quantities are the unnormalised row DFT of
+    the modulated SLM field and the unnormalised column inverse DFT of the
+    constrained replay, each times a power of two (2^-floor(log2(n)/2), n
+    the transform length) that keeps typical magnitudes near 1 and changes
+    no mantissa.  forward16 / backward16 round there (round to nearest
+    even, as a binary16 conversion does).
   * OSPR: subframe n draws a uniform random replay phase phi_n, takes the
     binary projection of IDFT(T_n e^{i phi_n}), accumulates |R_n|^2 and
     reports the NMSE of the running-average amplitude sqrt(A_n / n).
@@ -119,6 +130,48 @@ def backward(Rc, Q=None):
     return g
 
 
+def half_scale(n):
+    """Power-of-two scale of a stored 16-bit field plane for length-n transforms."""
+    return 2.0 ** -(int(np.log2(n)) // 2)
+
+
+def store16(Z, scale):
+    """Z as a 16-bit field plane holds it: each of (scale Re Z, scale Im Z)
+    rounded to IEEE binary16 (round to nearest even), then unscaled."""
+    Z = np.asarray(Z, dtype=np.complex128) * scale
+    out = np.empty(Z.shape, dtype=np.complex128)
+    out.real = Z.real.astype(np.float16).astype(np.float64)
+    out.imag = Z.imag.astype(np.float16).astype(np.float64)
+    return out / scale
+
+
+def checker(ny, nx):
+    """(-1)^(x+y): multiplying the SLM field by it centres the replay."""
+    return np.where(((np.arange(ny)[:, None] + np.arange(nx)[None, :]) & 1) == 1, -1.0, 1.0)
+
+
+def forward16(f, Q=None, store=store16):
+    """forward() with the field stored as 16-bit values between the row and
+    column halves: h = f Q (-1)^(x+y); Z = unnormalised row DFT of h, stored;
+    R = the column DFT of Z, unitary overall (centred by the checker)."""
+    f = np.asarray(f, dtype=np.complex128)
+    ny, nx = f.shape
+    h = (f * Q if Q is not None else f) * checker(ny, nx)
+    Z = store(h @ (_dft.dft_matrix(nx, -1).T * np.sqrt(nx)), half_scale(nx))
+    return _dft.dft_matrix(ny, -1) @ Z / np.sqrt(nx)
+
+
+def backward16(Rc, Q=None, store=store16):
+    """backward() with the field stored as 16-bit values between the column
+    and row halves: Y = unnormalised column inverse DFT of Rc, stored;
+    g = the row inverse DFT of Y (unitary overall) times (-1)^(x+y) conj(Q)."""
+    Rc = np.asarray(Rc, dtype=np.complex128)
+    ny, nx = Rc.shape
+    Y = store((_dft.dft_matrix(ny, +1) * np.sqrt(ny)) @ Rc, half_scale(ny))
+    g = Y @ _dft.dft_matrix(nx, +1).T / np.sqrt(ny) * checker(ny, nx)
+    return g * np.conj(Q) if Q is not None else g
+
+
 def _phase_of(R):
     A = np.abs(R)
     return np.where(A > 0, R / np.where(A > 0, A, 1.0), 1.0 + 0j), A
@@ -150,7 +203,7 @@ def lt_window(ny, nx, r):
 
 
 def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
-       weighted=False, weights=None, optics=None, batch_item=0, lt=None, amplitude=False):
+       weighted=False, weights=None, optics=None, batch_item=0, lt=None, amplitude=False, field16=False):
     """Gerchberg-Saxton / weighted GS / Liu-Taghizadeh.  Returns a dict of final state.
 
     optics = (wavelength_m, pitch_m, z_m) selects a Fresnel hologram.
@@ -158,6 +211,8 @@ def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
     constrains the replay amplitude only inside lt_window(r0 + (i-1) dr)
     and leaves it free (R' = R) outside.
     amplitude selects an L-level amplitude SLM (GS or weighted GS).
+    field16 holds the field as 16-bit values between transform halves
+    (forward16 / backward16).
     Keys: field (f_K), levels (k_K or None), g (the last field before
     projection), replay (R_K), nmse (K+1), fienup (K+1), weights (w_K),
     m (mean of w_K on Omega), target (prepared T).
@@ -184,14 +239,14 @@ def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
     if lt is not None and weighted:
         raise ValueError("Liu-Taghizadeh is a GS variant: weighted=False")
     for it in range(iters):
-        st = _iterate(T, L, f, Q, weighted, w, m, None if lt is None else lt[0] + it * lt[1], amplitude)
+        st = _iterate(T, L, f, Q, weighted, w, m, None if lt is None else lt[0] + it * lt[1], amplitude, field16)
         nm.append(_m.nmse(T, st["A"], dc))
         fe.append(fienup_error(T, st["A"], dc))
         g, f, levels = st["g"], st["field"], st["levels"]
         if weighted:
             w = st["weights"]
             m = float(np.mean(w[omega])) if np.any(omega) else 1.0
-    R = forward(f, Q)
+    R = forward16(f, Q) if field16 else forward(f, Q)
     A = np.abs(R)
     nm.append(_m.nmse(T, A, dc))
     fe.append(fienup_error(T, A, dc))
@@ -227,7 +282,8 @@ def ospr_subframe(T, A_prev, n, adaptive, seed=0, batch_item=0):
     return k, g, A, _m.nmse(T, np.sqrt(A / n))
 
 
-def gs_step(T, L, f_prev, weighted=False, w_prev=None, optics=None, lt_r=None, next_nmse=True, amplitude=False):
+def gs_step(T, L, f_prev, weighted=False, w_prev=None, optics=None, lt_r=None, next_nmse=True, amplitude=False,
+            field16=False):
     """One GS / weighted GS / Liu-Taghizadeh iteration from a given state.
 
     T is the PREPARED target (prepare_target), f_prev the SLM field f_{k-1}
@@ -250,13 +306,14 @@ def gs_step(T, L, f_prev, weighted=False, w_prev=None, optics=None, lt_r=None, n
         w_prev = np.asarray(w_prev, dtype=np.float64)
         omega = T > 0
         m = float(np.mean(w_prev[omega])) if np.any(omega) else 1.0
-    st = _iterate(T, L, np.asarray(f_prev, dtype=np.complex128), Q, weighted, w_prev, m, lt_r, amplitude)
+    st = _iterate(T, L, np.asarray(f_prev, dtype=np.complex128), Q, weighted, w_prev, m, lt_r, amplitude, field16)
+    fwd = forward16 if field16 else forward
     return dict(replay=st["R"], g=st["g"], field=st["field"], levels=st["levels"],
                 weights=st["weights"] if weighted else None, nmse=_m.nmse(T, st["A"], dc),
-                nmse_next=_m.nmse(T, np.abs(forward(st["field"], Q)), dc) if next_nmse else None)
+                nmse_next=_m.nmse(T, np.abs(fwd(st["field"], Q)), dc) if next_nmse else None)
 
 
-def _iterate(T, L, f, Q, weighted, w, m, lt_r, amplitude=False):
+def _iterate(T, L, f, Q, weighted, w, m, lt_r, amplitude=False, field16=False):
     """The body of one iteration (Iterative Fourier Transform Algorithms
     section): R = forward(f); replay constraint (GS: R' = T R/|R|, R = 0
     gives T; weighted GS: the weight update, then R' = w T R/|R|;
@@ -265,7 +322,7 @@ def _iterate(T, L, f, Q, weighted, w, m, lt_r, amplitude=False):
     g = backward(R'); f_next = P_L(g) (phase) or the nearest transmission
     (amplitude).  m is the lagged mean m_{k-1} of the weights over Omega."""
     ny, nx = T.shape
-    R = forward(f, Q)
+    R = forward16(f, Q) if field16 else forward(f, Q)
     ph, A = _phase_of(R)
     if lt_r is not None:
         Rp = np.where(lt_window(ny, nx, lt_r), T * ph, R)
@@ -278,7 +335,7 @@ def _iterate(T, L, f, Q, weighted, w, m, lt_r, amplitude=False):
     if amplitude:
         dc = zero_order(ny, nx)
         Rp[dc] = R[dc]
-    g = backward(Rp, Q)
+    g = backward16(Rp, Q) if field16 else backward(Rp, Q)
     f_next, levels = _slm.project_amplitude(g, L) if amplitude else _slm.project(g, L)
     return dict(R=R, A=A, g=g, field=f_next, levels=levels, weights=w)
 
