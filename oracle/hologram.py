@@ -139,10 +139,10 @@ def store16(Z, scale):
     """Z as a 16-bit field plane holds it: each of (scale Re Z, scale Im Z)
     rounded to IEEE binary16 (round to nearest even), then unscaled."""
     Z = np.asarray(Z, dtype=np.complex128) * scale
-    out = np.empty(Z.shape, dtype=np.complex128)
-    out.real = Z.real.astype(np.float16).astype(np.float64)
-    out.imag = Z.imag.astype(np.float16).astype(np.float64)
-    return out / scale
+    out = np.empty(Z.shape, dtype=np.complex128)  # parts set one by one: inf stays inf
+    out.real = Z.real.astype(np.float16).astype(np.float64) / scale
+    out.imag = Z.imag.astype(np.float16).astype(np.float64) / scale
+    return out
 
 
 def checker(ny, nx):
