@@ -318,6 +318,33 @@ def other_workload(args):
         config = {"workload": "lt_binary_1024x1024_100it", "batch": B, "grid": [n, n], "iters": iters,
                   "slm_levels": levels, "lt_r0": 256, "lt_dr": 4, "target": "gaussian sum, 32 blobs, central window"}
         kernel = "column pass of Liu-Taghizadeh (one tile per workgroup, k_colq<1024,4,COL_GS>)"
+    elif wl == "wgs1024f16":
+        n, B, iters = 1024, 32, 100
+        levels = 2 | hg.HG_FIELD_FP16  # the headline batch with the field held as binary16 pairs
+        tnp = [synth.gaussian_target(n, seed=2, batch_item=b) for b in range(B)]
+        tg = [torch.from_numpy(a).to(dev) for a in tnp]
+        lv = [torch.empty((n, n), dtype=torch.uint8, device=dev) for _ in range(B)]
+        nm = [torch.empty(iters + 1, dtype=torch.float64, device=dev) for _ in range(B)]
+        arr = (hg_problem * B)()
+        for b in range(B):
+            arr[b] = hg_problem(n, n, levels, iters, 1, 0.0, 0.0, 0.0, tg[b].data_ptr(), lv[b].data_ptr(),
+                                nm[b].data_ptr())
+        nb = lib.hg_gs_batched_workspace_size(arr, B)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+
+        def step():
+            check(lib.hg_gs_batched(arr, B, 1, ctypes.c_void_p(ws.data_ptr()), nb, cur_stream()))
+        px = n * n * B
+        units, unit = iters * B, "iter/s"
+        # 16-bit field: weighted column pass field r+w 8 + 12 omega B/px, final
+        # pass field 4 + target 4 (wave kernel, target everywhere), rows 8
+        om = sum(support_of(a, True) for a in tnp) / B
+        bytes_col = px * (iters * (8 + 12 * om) + 8)
+        bytes_row = px * (4 + iters * 8 + 1)
+        config = {"workload": "wgs_binary_1024x1024_100it_field16", "batch": B, "grid": [n, n], "iters": iters,
+                  "slm_levels": 2, "field_storage": "binary16 pairs",
+                  "target": "gaussian sum, 32 blobs, central window"}
+        kernel = "column pass of weighted GS, 16-bit field (k_colq<1024,4,COL_WGS,16,false,true>)"
     elif wl == "amp1024":
         n, B, iters = 1024, 32, 100
         levels = 2 | hg.HG_SLM_AMPLITUDE  # binary amplitude SLM, transmissions {0, 1}
@@ -470,13 +497,15 @@ def main():
     ap.add_argument("--iters", type=int, default=100,
                     help="iterations per hologram (100 is the workload; fewer only for short profiles)")
     ap.add_argument("--workload", default="wgs1024",
-                    choices=["wgs1024", "gs64", "ospr512", "ospr1024x32", "uneven", "lt1024", "amp1024"],
+                    choices=["wgs1024", "gs64", "ospr512", "ospr1024x32", "uneven", "lt1024", "amp1024",
+                             "wgs1024f16"],
                     help="wgs1024 (default): the headline batch; gs64: one 64^2 8-level GS, latency; "
                          "ospr512: adaptive binary OSPR, 512^2, 24 subframes; uneven: 256 Fresnel problems "
                          "of four sizes, 8 levels, 50 iterations; lt1024: 32 binary Liu-Taghizadeh problems "
                          "of 1024^2, 100 iterations, region radius 256 + 4 per iteration; ospr1024x32: 32 "
                          "adaptive binary OSPR problems of 1024^2, 24 subframes, in one call; amp1024: the "
-                         "headline batch on a binary amplitude SLM")
+                         "headline batch on a binary amplitude SLM; wgs1024f16: the headline batch with 16-bit "
+                         "field storage")
     ap.add_argument("--context", action="store_true",
                     help="also time the same loop as unfused torch.fft (rocFFT) ops, for context")
     ap.add_argument("--oracle-scaling", action="store_true",

@@ -99,6 +99,21 @@ size_t hg_workspace_size(int op, int ny, int nx, int iters);
  * or OSPR).  Levels out are the indices k.                                 */
 #define HG_SLM_AMPLITUDE 0x10000
 
+/* 16-bit field storage ("Floating Points" section: 16-, 32- and 64-bit
+ * builds).  slm_levels | HG_FIELD_FP16 keeps the complex field between the
+ * row and column passes as two IEEE binary16 values (4 bytes per element
+ * instead of 8) in the workspace; every transform, constraint and projection
+ * still computes in FP32.  The stored values are the unnormalised row
+ * transform of the modulated SLM field and the unnormalised column inverse
+ * transform of the constrained replay, each times 2^-floor(log2(n)/2) (n
+ * the transform length: magnitudes near 1, no mantissa changed), rounded to
+ * nearest even; a value beyond the binary16 range becomes infinite and the
+ * NMSE NaN (HG_ERR_NUMERIC).  Accepted by hg_gs, hg_wgs, hg_lt, hg_gs_step
+ * and hg_gs_batched for ny in {256, 512, 1024} (any supported nx); those
+ * calls use the default launch configuration.  hg_workspace_size's answer
+ * covers both storages.                                                     */
+#define HG_FIELD_FP16 0x20000
+
 /* Gerchberg-Saxton ("Iterative Fourier Transform Algorithms" section).
  *   target        [ny][nx] float, centred replay-plane amplitude, >= 0, not all 0
  *   iters         >= 1 iterations of: forward transform, replay constraint

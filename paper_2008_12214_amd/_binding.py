@@ -280,6 +280,8 @@ def hg_wgs_static(target, iters, slm_levels, seed=0, init_levels=None, init_fiel
 HG_STATIC_SCRATCH_BYTES = 32 << 20
 # slm_levels flag: an amplitude SLM with the L transmissions k / (L - 1)
 HG_SLM_AMPLITUDE = 0x10000
+# slm_levels flag: the field between passes held as two binary16 values (ny in 256..1024)
+HG_FIELD_FP16 = 0x20000
 
 
 def hg_gs_step(target, slm_levels, levels_in=None, field_in=None, weights=None, lt_radius=-1, wavelength_m=0.0,

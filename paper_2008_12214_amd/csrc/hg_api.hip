@@ -121,7 +121,7 @@ Cfg default_cfg(int ny, int nx, int B) {
     default: c.C = 2; break;
   }
   const int T = nx / kE;
-  c.RPB = T >= 256 ? 1 : T == 128 ? 4 : 256 / T;  // 2048-wide rows: staged 4-row groups
+  c.RPB = default_rpb(nx);  // 2048-wide rows: staged 4-row groups
   (void)B;
   return c;
 }
@@ -286,8 +286,10 @@ Batch make_batch(void* ws, const Layout& L, int ny, int nx, int C) {
 
 // Whole GS / WGS pipeline for one size class.
 // status: the call's status word; cleared here when `first` (the call's first size class).
+// f16: the class's field plane holds 16-bit elements (the default launch
+// configuration, whose kernels exist for them, and their power-of-two scales).
 hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::vector<double>& rates, bool weighted,
-                       void* ws, const Layout& L, hipStream_t st, int* status, bool first) {
+                       void* ws, const Layout& L, hipStream_t st, int* status, bool first, bool f16 = false) {
   const int B = (int)ds.size();
   int kmax = 0;
   bool all_bin = true;
@@ -295,8 +297,18 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
     kmax = std::max(kmax, d.iters);
     all_bin &= (d.L == 2 && !d.mod);
   }
-  const Cfg cfg = get_cfg(ny, nx, B);
+  // 16-bit planes: the tile kernel's shape (256 threads: C = 4096 / ny) and
+  // the default row grouping, the instantiations that exist for them
+  const Cfg cfg = f16 ? Cfg{4096 / ny, default_rpb(nx)} : get_cfg(ny, nx, B);
   Batch bt = make_batch(ws, L, ny, nx, cfg.C);
+  if (f16) {
+    bt.f16 = 1;
+    const int ex = ilog2(nx) / 2, ey = ilog2(ny) / 2;  // 2^-floor(log2(n) / 2)
+    bt.s16_row = std::ldexp(1.0f, -ex);
+    bt.inv16_row = std::ldexp(1.0f, ex);
+    bt.s16_col = std::ldexp(1.0f, -ey);
+    bt.inv16_col = std::ldexp(1.0f, ey);
+  }
   bool any_lt = false;  // Liu-Taghizadeh: not in the single-launch small-problem kernel
   for (const Desc& d : ds) any_lt |= (d.lt != 0);
   for (const Desc& d : ds) bt.dump |= (d.r_out != nullptr) ? 1 : 0;
@@ -376,8 +388,9 @@ hg_status check_size(int ny, int nx) {
 
 // slm_levels: the level count, with HG_SLM_AMPLITUDE or-ed in for an
 // amplitude-modulating SLM.
-int levels_of(int slm_levels) { return slm_levels & ~HG_SLM_AMPLITUDE; }
+int levels_of(int slm_levels) { return slm_levels & ~(HG_SLM_AMPLITUDE | HG_FIELD_FP16); }
 int modulation_of(int slm_levels) { return (slm_levels & HG_SLM_AMPLITUDE) ? 1 : 0; }
+int field16_of(int slm_levels) { return (slm_levels & HG_FIELD_FP16) ? 1 : 0; }
 
 hg_status check_common(const float* target, int ny, int nx, int iters, int slm_levels) {
   hg_status s = check_size(ny, nx);
@@ -388,6 +401,8 @@ hg_status check_common(const float* target, int ny, int nx, int iters, int slm_l
   if (!(L == 0 || (L >= 2 && L <= 256))) return fail(HG_ERR_INVALID_ARG, "slm_levels=%d: 0 or 2..256", L);
   if (modulation_of(slm_levels) && L < 2)
     return fail(HG_ERR_INVALID_ARG, "an amplitude SLM needs 2..256 levels (slm_levels=%d)", L);
+  if (field16_of(slm_levels) && !f16_ok(ny))
+    return fail(HG_ERR_UNSUPPORTED_SIZE, "16-bit field storage needs ny in {256, 512, 1024} (ny=%d)", ny);
   return HG_OK;
 }
 
@@ -455,19 +470,26 @@ hg_status gs_common(bool weighted, const float* target, int ny, int nx, int iter
   std::vector<Desc> ds{d};
   std::vector<double> rates{chirp_rate(lambda, pitch, z)};
   return run_gs_class(ny, nx, ds, rates, weighted, ws, Lo, static_cast<hipStream_t>(stream), at<int>(ws, Lo.status),
-                      true);
+                      true, field16_of(L) != 0);
 }
 
-// Size classes of a batched call in order of first appearance.
-struct ClassPlan {
-  std::vector<std::pair<int, int>> order;
-  std::map<std::pair<int, int>, std::vector<int>> members;
+// Size classes of a batched call in order of first appearance: problems of
+// one grid size and one field storage (complex64 or 16-bit) share launches.
+struct ClassKey {
+  int ny, nx, f16;
+  bool operator<(const ClassKey& o) const { return std::tie(ny, nx, f16) < std::tie(o.ny, o.nx, o.f16); }
 };
+struct ClassPlan {
+  std::vector<ClassKey> order;
+  std::map<ClassKey, std::vector<int>> members;
+};
+int storage16_of(const hg_problem& p) { return (p.slm_levels & HG_FIELD_FP16) ? 1 : 0; }
+int storage16_of(const hg_ospr_problem&) { return 0; }
 template <class P>
 ClassPlan plan_classes(const P* probs, int count) {
   ClassPlan cp;
   for (int i = 0; i < count; ++i) {
-    auto key = std::make_pair(probs[i].ny, probs[i].nx);
+    const ClassKey key{probs[i].ny, probs[i].nx, storage16_of(probs[i])};
     if (!cp.members.count(key)) cp.order.push_back(key);
     cp.members[key].push_back(i);
   }
@@ -690,7 +712,7 @@ size_t hg_ospr_batched_workspace_size(const hg_ospr_problem* probs, int count, i
   const ClassPlan cp = plan_classes(probs, count);
   size_t total = 0;
   for (auto& key : cp.order)
-    total += make_layout(HG_OP_OSPR, key.first, key.second, (int)cp.members.at(key).size(), subframes).total;
+    total += make_layout(HG_OP_OSPR, key.ny, key.nx, (int)cp.members.at(key).size(), subframes).total;
   return total;
 }
 
@@ -727,8 +749,8 @@ hg_status hg_ospr_batched(const hg_ospr_problem* probs, int count, int subframes
       d.iters = subframes;
       ds.push_back(d);
     }
-    const Layout Lo = make_layout(HG_OP_OSPR, key.first, key.second, (int)idx.size(), subframes);
-    s = run_ospr_class(key.first, key.second, ds, subframes, adaptive, static_cast<char*>(workspace) + off, Lo, st,
+    const Layout Lo = make_layout(HG_OP_OSPR, key.ny, key.nx, (int)idx.size(), subframes);
+    s = run_ospr_class(key.ny, key.nx, ds, subframes, adaptive, static_cast<char*>(workspace) + off, Lo, st,
                        at<int>(workspace, 0), off == 0);
     if (s != HG_OK) return s;
     off += Lo.total;
@@ -796,7 +818,7 @@ size_t hg_gs_batched_workspace_size(const hg_problem* probs, int count) {
     int kmax = 0;
     for (int i : cp.members.at(key)) kmax = std::max(kmax, probs[i].iters);
     // the weighted layout is the larger one; one query serves both modes
-    total += make_layout(HG_OP_WGS, key.first, key.second, (int)cp.members.at(key).size(), kmax).total;
+    total += make_layout(HG_OP_WGS, key.ny, key.nx, (int)cp.members.at(key).size(), kmax).total;
   }
   return total;
 }
@@ -859,9 +881,9 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
       rates.push_back(chirp_rate(p.wavelength_m, p.pitch_m, p.z_m));
       kmax = std::max(kmax, p.iters);
     }
-    const Layout Lo = make_layout(HG_OP_WGS, key.first, key.second, (int)idx.size(), kmax);
-    s = run_gs_class(key.first, key.second, ds, rates, weighted != 0, static_cast<char*>(workspace) + off, Lo, st,
-                     at<int>(workspace, 0), off == 0);
+    const Layout Lo = make_layout(HG_OP_WGS, key.ny, key.nx, (int)idx.size(), kmax);
+    s = run_gs_class(key.ny, key.nx, ds, rates, weighted != 0, static_cast<char*>(workspace) + off, Lo, st,
+                     at<int>(workspace, 0), off == 0, key.f16 != 0);
     if (s != HG_OK) return s;
     off += Lo.total;
   }

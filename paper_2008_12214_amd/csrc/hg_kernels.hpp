@@ -61,7 +61,23 @@ struct Batch {
   int any_lt;           // some problem of the batch has a Liu-Taghizadeh region
   int* status;          // the call's numeric status word: nonzero once a finisher saw non-finite sums
   int dump;             // some problem asks for r_out: the first column pass runs its dumping instantiation
+  int f16;              // the field plane holds two binary16 values per element (4 bytes), not complex64
+  float s16_row, inv16_row;  // 16-bit planes: the row pass stores x s16_row, the column pass loads x inv16_row
+  float s16_col, inv16_col;  // the column pass stores x s16_col, the row pass loads x inv16_col
 };
+
+// 16-bit field storage: one element as two IEEE binary16 values (real in the
+// low half), each rounded to nearest even from the value times a power-of-
+// two scale (which changes no mantissa); loads undo the scale exactly.
+__device__ __forceinline__ uint32_t pack_h2(float2 v, float s) {
+  const _Float16 a = (_Float16)(v.x * s), b = (_Float16)(v.y * s);
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+__device__ __forceinline__ float2 unpack_h2(uint32_t w, float inv_s) {
+  const _Float16 a = __builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+  const _Float16 b = __builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+  return make_float2((float)a * inv_s, (float)b * inv_s);
+}
 
 __device__ __forceinline__ double* part_ptr(const Batch& bt, int b, int slot, int blk) {
   return bt.part + (((size_t)b * bt.slots + slot) * bt.nblk + blk) * 4;
@@ -429,6 +445,42 @@ __device__ __forceinline__ void lds_to_quad(const float2* lds, gptr<float2> q) {
   }
 }
 
+// 16-bit planes: a 4 x 4 tile is 64 contiguous bytes, so chunk c (16 bytes)
+// of a 4-row group holds the elements x = 4 (c >> 2) .. 4 (c >> 2) + 3 of
+// row c & 3.  Staged rows stay float2 in LDS.
+template <int NX, int NT, int LW>
+__device__ __forceinline__ void quad16_to_lds(gptr<const uint32_t> q, float2* lds, float inv_s) {
+  constexpr int NCH = NX;  // 4 rows x NX elements x 4 bytes / 16
+  static_assert(LW % 2 == 0, "16-byte aligned rows");
+#pragma unroll
+  for (int m = 0; m < NCH / NT; ++m) {
+    const int c = threadIdx.x + NT * m;
+    const uint4 w = reinterpret_cast<gptr<const uint4>>(q)[c];
+    const int rr = c & 3, x = 4 * (c >> 2);
+    const float2 e0 = unpack_h2(w.x, inv_s), e1 = unpack_h2(w.y, inv_s);
+    const float2 e2 = unpack_h2(w.z, inv_s), e3 = unpack_h2(w.w, inv_s);
+    *reinterpret_cast<float4*>(lds + rr * LW + x) = make_float4(e0.x, e0.y, e1.x, e1.y);
+    *reinterpret_cast<float4*>(lds + rr * LW + x + 2) = make_float4(e2.x, e2.y, e3.x, e3.y);
+  }
+}
+template <int NX, int NT, int LW>
+__device__ __forceinline__ void lds_to_quad16(const float2* lds, gptr<uint32_t> q, float s) {
+  constexpr int NCH = NX;
+#pragma unroll
+  for (int m = 0; m < NCH / NT; ++m) {
+    const int c = threadIdx.x + NT * m;
+    const int rr = c & 3, x = 4 * (c >> 2);
+    const float4 a = *reinterpret_cast<const float4*>(lds + rr * LW + x);
+    const float4 b = *reinterpret_cast<const float4*>(lds + rr * LW + x + 2);
+    uint4 w;
+    w.x = pack_h2(make_float2(a.x, a.y), s);
+    w.y = pack_h2(make_float2(a.z, a.w), s);
+    w.z = pack_h2(make_float2(b.x, b.y), s);
+    w.w = pack_h2(make_float2(b.z, b.w), s);
+    reinterpret_cast<gptr<uint4>>(q)[c] = w;
+  }
+}
+
 // MODE  ROW_INIT: build f0 (Philox, levels or field), forward FFT.
 //       ROW_ITER: inverse FFT, project, forward FFT (iteration k = arg).
 //       ROW_OSPR: as ROW_ITER with L = 2, writing subframe arg's levels.
@@ -440,9 +492,12 @@ __device__ __forceinline__ void lds_to_quad(const float2* lds, gptr<float2> q) {
 // with one workgroup fewer per CU.)
 template <int NX, int RPB> constexpr int row_min_waves() { return ((NX == 2048 || NX == 1024) && RPB == 4) ? 4 : 1; }
 
-template <int NX, int RPB, bool FRESNEL, int MODE, int LK>
+// F16: the field plane holds 16-bit elements (Batch::f16); ROW_INIT and
+// ROW_ITER only.
+template <int NX, int RPB, bool FRESNEL, int MODE, int LK, bool F16 = false>
 __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k_row(Batch bt, int arg,
                                                                                      const float2* pin, float2* pout) {
+  static_assert(!F16 || MODE == ROW_INIT || MODE == ROW_ITER, "16-bit planes in GS / weighted GS only");
   constexpr int E = kE;
   using P = Plan<NX, E>;
   constexpr int T = P::T;
@@ -470,6 +525,10 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
   // this row's elements in the tiled field: x at row[(x >> 2) * 16 + (x & 3)]
   gptr<float2> row = to_global(bt.field + off + (size_t)(y >> 2) * (NX >> 2) * 16 + (y & 3) * 4);
   gptr<float2> quad = to_global(bt.field + off + (size_t)(y >> 2) * (NX >> 2) * 16);  // the group's tiles
+  // the same element offsets in a 16-bit plane (4 bytes per element)
+  gptr<uint32_t> row16 = to_global(reinterpret_cast<uint32_t*>(bt.field) + off + (size_t)(y >> 2) * (NX >> 2) * 16 +
+                                   (y & 3) * 4);
+  gptr<uint32_t> quad16 = to_global(reinterpret_cast<uint32_t*>(bt.field) + off + (size_t)(y >> 2) * (NX >> 2) * 16);
   gptr<const float2> cx = to_global(static_cast<const float2*>(bt.chirp)) + (size_t)b * (NX + bt.ny);
   const float2 cyv = FRESNEL ? static_cast<float2>(cx[NX + y]) : make_float2(1.f, 0.f);
   RowEx<WAVE, PP> ex;
@@ -536,10 +595,14 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
         }
       }
       if constexpr (STAGE) {
-        quad_to_lds<NX, RPB * T, LW>(quad, lds);
+        if constexpr (F16) quad16_to_lds<NX, RPB * T, LW>(quad16, lds, bt.inv16_col);
+        else quad_to_lds<NX, RPB * T, LW>(quad, lds);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < E; ++j) v[j] = ex.b[0][t + T * j];  // unpadded staging order
+      } else if constexpr (F16) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = unpack_h2(row16[((t + T * j) >> 2) * 16 + (t & 3)], bt.inv16_col);
       } else {
 #pragma unroll
         for (int j = 0; j < E; ++j) v[j] = row[((t + T * j) >> 2) * 16 + (t & 3)];
@@ -606,7 +669,11 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
 #pragma unroll
       for (int j = 0; j < E; ++j) ex.b[0][t + T * j] = v[j];  // unpadded staging order
       __syncthreads();
-      lds_to_quad<NX, RPB * T, LW>(lds, quad);
+      if constexpr (F16) lds_to_quad16<NX, RPB * T, LW>(lds, quad16, bt.s16_row);
+      else lds_to_quad<NX, RPB * T, LW>(lds, quad);
+    } else if constexpr (F16) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) row16[((t + T * j) >> 2) * 16 + (t & 3)] = pack_h2(v[j], bt.s16_row);
     } else {
 #pragma unroll
       for (int j = 0; j < E; ++j) row[((t + T * j) >> 2) * 16 + (t & 3)] = v[j];
@@ -845,9 +912,12 @@ struct WaveColEx {
   __device__ void st(int e, float2 v) { s[e] = v; }
 };
 
-template <int NY, int C, int MODE, bool LT = false, bool DUMP = false>  // LT, DUMP as for k_col
+// LT, DUMP as for k_col; F16: the field plane holds 16-bit elements (the final
+// measurement pass of such calls)
+template <int NY, int C, int MODE, bool LT = false, bool DUMP = false, bool F16 = false>
 __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int adaptive, const float2* pin,
                                                         float2* pout) {
+  static_assert(!F16 || MODE == COL_FINAL, "16-bit planes: the tile kernel runs the iterations");
   constexpr int E = kE, T = NY / E, NT = C * T;
   static_assert(T <= 64 && 64 % T == 0, "a column must fit in one wave");
   constexpr int RS = colw_stride<NY, C>();
@@ -887,7 +957,14 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
   // A + B: forward column transform of the field
   if constexpr (MODE != COL_OSPR_FIRST) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = fld[tix(r0 + T * i, u, NX)];
+    for (int i = 0; i < E; ++i) {
+      if constexpr (F16) {
+        v[i] = unpack_h2(to_global(reinterpret_cast<const uint32_t*>(bt.field) + off)[tix(r0 + T * i, u, NX)],
+                         bt.inv16_row);
+      } else {
+        v[i] = fld[tix(r0 + T * i, u, NX)];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < E; ++i) mine[lds_pad(r0 + T * i)] = v[i];
     __syncthreads();
@@ -1141,22 +1218,29 @@ template <int C> __device__ __forceinline__ int colp_sidx(int row, int c) {
 // C / 4 tiles of 128 contiguous bytes (2 C chunks of 16 bytes).  Each wave
 // instruction fills 64 consecutive chunks (1 KB of LDS from a wave-uniform
 // base).
-template <int NY, int C, int E>
+// F16: a 16-bit plane, whose 4 x 4 tile is 64 bytes (C chunks per row quad),
+// lands in the stage as 4-byte elements in the same order.
+template <int NY, int C, int E, bool F16 = false>
 __device__ __forceinline__ void colp_prefetch(const Batch& bt, int vt, int tpp, float2* F) {
   using S = ColpShape<NY, C, E>;
-  constexpr int NW = S::NT / 64, CPQ = 2 * C;  // chunks per row quad
+  constexpr int EB = F16 ? 4 : 8;              // bytes per element
+  constexpr int NW = S::NT / 64, CPQ = C * EB / 4;  // 16-byte chunks per row quad (4 rows x C columns)
+  constexpr int EPC = 16 / EB;                 // elements per chunk
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int b = vt / tpp, blk = vt - b * tpp;
   const int NX = bt.nx;
-  const float2* src = bt.field + (size_t)b * NY * NX + (size_t)blk * C * 4;  // tile (0, blk C / 4)
-  const size_t qstride = (size_t)(NX >> 2) * 16;                               // elements per tile row
+  const char* src = reinterpret_cast<const char*>(bt.field) +
+                    ((size_t)b * NY * NX + (size_t)blk * C * 4) * EB;  // tile (0, blk C / 4)
+  const size_t qstride = (size_t)(NX >> 2) * 16 * EB;                   // bytes per tile row
+  char* dst = reinterpret_cast<char*>(F);
 #pragma unroll
-  for (int q = 0; q < NY * 2 * C / 4 / S::NT; ++q) {
+  for (int q = 0; q < NY * CPQ / 4 / S::NT; ++q) {
     const int base = (q * NW + wave) * 64;
     const int ch = base + lane;
     const int quad = ch / CPQ, part = ch - quad * CPQ;
-    __builtin_amdgcn_global_load_lds(HG_AS1(src + quad * qstride + 2 * part), HG_AS3(F + 2 * base), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(HG_AS1(src + quad * qstride + 16 * part), HG_AS3(dst + 16 * base), 16, 0, 0);
   }
+  (void)EPC;
 }
 
 // Register-held per-tile inputs: activity, 1/m, the weight plane, target
@@ -1238,7 +1322,7 @@ __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int
 // wait for everything (each wave for its own loads) before the barrier.
 // LATE: this tile's target and weights are loaded here, after the forward
 // transform, instead of ahead (in.active set by the caller).
-template <int NY, int C, int MODE, int E, int PAR, class TWP, bool LATE = false, bool DUMP = false>
+template <int NY, int C, int MODE, int E, int PAR, class TWP, bool LATE = false, bool DUMP = false, bool F16 = false>
 __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vtn, int total, int tpp,
                                           float2* __restrict__ Fc, float2* __restrict__ Fn, TWP tw,
                                           double (&red)[kMaxWaves][4], double (&tot)[4], ColpIn<E>& in) {
@@ -1247,7 +1331,7 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
   constexpr bool WGS = MODE == COL_WGS;
   static_assert(2 * (NT / 64) <= kMaxWaves, "two tiles' per-wave partial slots");
   static_assert(Plan<NY, E>::ns > 1, "the inverse transform's exchange orders the slot writes before the reads");
-  if (vtn < total) colp_prefetch<NY, C, E>(bt, vtn, tpp, Fn);
+  if (vtn < total) colp_prefetch<NY, C, E, F16>(bt, vtn, tpp, Fn);
   if (in.active) {
     const int b = vt / tpp, blk = vt - b * tpp;
     const int c = threadIdx.x % C, t = threadIdx.x / C;
@@ -1255,8 +1339,14 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
     const int NX = bt.nx;
     const size_t off = (size_t)b * NY * NX;
     float2 v[E];
+    if constexpr (F16) {
+      const uint32_t* F4 = reinterpret_cast<const uint32_t*>(Fc);
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = Fc[colp_sidx<C>(t + T * j, c)];
+      for (int j = 0; j < E; ++j) v[j] = unpack_h2(F4[colp_sidx<C>(t + T * j, c)], bt.inv16_row);
+    } else {
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = Fc[colp_sidx<C>(t + T * j, c)];
+    }
     ColExL<C> ex{Fc + c};
     fft_stage<NY, E, -1, 0>(v, t, tw, ex);
     if constexpr (LATE) colp_load_in<NY, C, MODE, E>(bt, k, vt, tpp, in);
@@ -1339,9 +1429,15 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
       if (threadIdx.x < 3) part_ptr(bt, b, k - 1, blk)[threadIdx.x] = acc;
       else if (WGS) part_ptr(bt, b, k, blk)[3] = acc;
     }
-    gptr<float2> fld = to_global(uni_ptr(bt.field + off));
+    if constexpr (F16) {
+      gptr<uint32_t> fld = to_global(uni_ptr(reinterpret_cast<uint32_t*>(bt.field) + off));
 #pragma unroll
-    for (int j = 0; j < E; ++j) *at_bytes(fld, 2u * (b0 + bstep * j)) = v[j];
+      for (int j = 0; j < E; ++j) *at_bytes(fld, b0 + bstep * j) = pack_h2(v[j], bt.s16_col);
+    } else {
+      gptr<float2> fld = to_global(uni_ptr(bt.field + off));
+#pragma unroll
+      for (int j = 0; j < E; ++j) *at_bytes(fld, 2u * (b0 + bstep * j)) = v[j];
+    }
   }
   if (vtn < total) colp_load_in<NY, C, MODE, E>(bt, k, vtn, tpp, in);
   __builtin_amdgcn_s_waitcnt(0);
@@ -1388,7 +1484,7 @@ void k_colp(Batch bt, int k, int nprob) {
 // (plain GS) workgroups share a CU and hide each other's loads.  Capping the
 // weighted kernel at 128 registers to fit four spills, and measured 9%
 // slower.
-template <int NY, int C, int MODE, int E = kColpE, bool DUMP = false>
+template <int NY, int C, int MODE, int E = kColpE, bool DUMP = false, bool F16 = false>
 __global__ __launch_bounds__(C * (NY / E))
 void k_colq(Batch bt, int k, int nprob) {
   using S = ColpShape<NY, C, E>;
@@ -1399,12 +1495,12 @@ void k_colq(Batch bt, int k, int nprob) {
   const int tpp = bt.nx / C, total = tpp * nprob;
   const int vt = xcd_tile(blockIdx.x, gridDim.x);
   if (vt >= total) return;  // uniform per block
-  colp_prefetch<NY, C, E>(bt, vt, tpp, FA);
+  colp_prefetch<NY, C, E, F16>(bt, vt, tpp, FA);
   ColpIn<E> in;
   colp_load_in<NY, C, MODE, E>(bt, k, vt, tpp, in);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  colp_tile<NY, C, MODE, E, 0, decltype(launder(to_global(bt.tw_y))), false, DUMP>(
+  colp_tile<NY, C, MODE, E, 0, decltype(launder(to_global(bt.tw_y))), false, DUMP, F16>(
       bt, k, vt, total, total, tpp, FA, FA, launder(to_global(bt.tw_y)), red, tot, in);
 }
 

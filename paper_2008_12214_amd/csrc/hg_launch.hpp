@@ -31,6 +31,17 @@ __host__ __device__ constexpr bool rpb_ok(int N, int RPB) {
   return (RPB * T == 128 || RPB * T == 256) || (T >= 256 && RPB == 1) || (T == 128 && RPB == 4);
 }
 
+// Default rows per row-pass workgroup for a row length N: one 4-row group of
+// 1024- or 2048-wide rows, 256 threads for shorter rows, one row beyond.
+__host__ __device__ constexpr int default_rpb(int N) {
+  return N / kE >= 256 ? 1 : (N / kE == 128 ? 4 : 256 / (N / kE));
+}
+
+// 16-bit field planes (Batch::f16) run their column passes in the tile
+// kernel, whose 256-thread tiles exist for these column lengths (with the
+// default tile width), and their row passes with default_rpb rows.
+__host__ __device__ constexpr bool f16_ok(int ny) { return ny == 256 || ny == 512 || ny == 1024; }
+
 // Kernel of the GS / weighted GS column passes (hg_set_column_kernel):
 //   CK_TILE        one column tile per workgroup (k_colq) where its
 //                  256-thread tile is compiled, else as CK_PERSISTENT;

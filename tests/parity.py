@@ -21,6 +21,18 @@ FIELD_TOL = 1e-4
 NMSE_TOL = 1e-4
 BAND = 1e-5
 DIST = 1e-5
+# 16-bit field storage: both sides round the stored field to binary16 at the
+# same points, so they differ only where an FP32 and an FP64 value straddle a
+# binary16 rounding boundary: one binary16 step (2^-11 relative) on a small
+# fraction of the stored elements.  That leaves R within about 1e-5 relative
+# L2, but the replay constraint divides by |R| (and weighted GS multiplies by
+# the weights), so g differs by up to about 1.3e-4 (measured on the GPU and
+# reproduced on the CPU by perturbing the oracle's values by FP32-sized
+# errors before each store).  Fields are therefore held to one binary16 step,
+# 2^-11 relative L2, and the distance band and its bound widen 50-fold
+# (5e-4 rms: about four times the per-pixel error of g).
+FIELD16_TOL = 2.0 ** -11
+FIELD16_BAND = 50.0
 
 
 def say(*a):
@@ -36,7 +48,7 @@ def rel_max(a, b):
     return float(np.max(np.abs(a - b) / np.abs(b)))
 
 
-def exempt_bounds(npx, L):
+def exempt_bounds(npx, L, scale=1.0):
     """Most exempt level mismatches one comparison of npx pixels at L levels
     may have: (in either band, in the distance band alone).
 
@@ -48,25 +60,27 @@ def exempt_bounds(npx, L):
     pixels at L = 2, 2 at L = 8, 60 at L = 256).  The angular band adds
     pixels of small |g| that the distance band mostly holds already.  The
     bounds leave a four-fold headroom, plus a count of 2 for small planes."""
-    dist = 2 + int(np.ceil(1e-6 * max(L, 2) * npx))
+    dist = 2 + int(np.ceil(scale * 1e-6 * max(L, 2) * npx))
     return dist + int(np.ceil(1e-5 * npx)), dist
 
 
-def level_check(gpu_lev, ref_lev, g_ref, L, where="", amplitude=False):
+def level_check(gpu_lev, ref_lev, g_ref, L, where="", amplitude=False, band_scale=1.0):
     """(non-exempt mismatches, exempt mismatches) of GPU levels against the
     oracle's; prints each non-exempt mismatch and asserts the exempt counts
     are within exempt_bounds.  amplitude: levels of an amplitude SLM, whose
-    decision boundaries are values of Re g (only the distance band applies)."""
+    decision boundaries are values of Re g (only the distance band applies).
+    band_scale widens the distance band and its bound together (16-bit field
+    storage: 10, see FIELD16_BAND)."""
     mism = np.asarray(gpu_lev, np.int64) != np.asarray(ref_lev, np.int64)
     rms = np.sqrt(np.mean(np.abs(g_ref) ** 2))
     if amplitude:
         margin = slm.amplitude_margin(g_ref, L)  # a distance in field units
-        zero = mism & (margin < DIST * rms)
+        zero = mism & (margin < band_scale * DIST * rms)
         band = np.zeros_like(mism)
     else:
         margin = slm.boundary_margin(g_ref, L)
         # Euclidean distance to the nearest boundary ray (margin <= pi/L <= pi/2)
-        zero = mism & (np.abs(g_ref) * np.sin(margin) < DIST * rms)
+        zero = mism & (np.abs(g_ref) * np.sin(margin) < band_scale * DIST * rms)
         band = mism & (margin < BAND) & ~zero
     bad = mism & ~(band | zero)
     if bad.any():
@@ -77,7 +91,7 @@ def level_check(gpu_lev, ref_lev, g_ref, L, where="", amplitude=False):
     nb, nz = int(band.sum()), int(zero.sum())
     if nb or nz:
         say(f"  {where} exempt level mismatches: {nb} in the angular band, {nz} in the distance band")
-    max_all, max_zero = exempt_bounds(mism.size, L)
+    max_all, max_zero = exempt_bounds(mism.size, L, band_scale)
     assert nb + nz <= max_all, f"{where}: {nb + nz} exempt mismatches exceed the bound {max_all}"
     assert nz <= max_zero, f"{where}: {nz} distance-band mismatches exceed the bound {max_zero}"
     return int(bad.sum()), nb + nz
