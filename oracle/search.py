@@ -10,6 +10,12 @@ Here it serves as a brute-force reference for the iterative algorithms:
   * ``direct_search``: raster sweeps over all pixels, trying every other
     level, accepting strict decreases, until a sweep changes nothing.  The
     result is a local minimum under every single-pixel change.
+  * ``simulated_annealing``: the same trial, one proposed level per pixel
+    per sweep, accepted when the error falls or, with probability
+    exp(-dE / tau), when it rises (the temperature-based acceptance of the
+    Holographic Search Algorithms section; Metropolis rule), with a
+    geometric temperature schedule tau_s = t0 alpha^(s - 1).  Proposals and
+    acceptance draws come from Philox4x64-10 (see sa_words).
 
 The replay change from one pixel change is formed incrementally,
 dR = dh * w / sqrt(Nx Ny) with w the centred DFT kernel of that pixel;
@@ -20,7 +26,10 @@ import itertools
 import numpy as np
 
 from . import dft as _dft
+from . import philox as _ph
 from . import slm as _slm
+
+TAG_SA = 0x5A  # Philox tag of the simulated-annealing draws
 
 
 def _kernel(ny, nx, y, x):
@@ -91,3 +100,65 @@ def direct_search(T, L, init_levels, max_sweeps=1000):
         if not changed:
             return lev, err, sweep
     return lev, err, max_sweeps
+
+
+def sa_words(seed, sweep, ny, nx, batch_item=0):
+    """The two random words of every simulated-annealing trial of a sweep:
+    trial (sweep s, pixel p = y nx + x) takes words 0 and 1 of the
+    Philox4x64-10 block at counter (p, s, 0, 0) under key
+    (seed, (item << 32) | TAG_SA).  Returns two (ny, nx) uint64 arrays."""
+    p = np.arange(ny * nx, dtype=np.uint64)
+    s = np.full_like(p, np.uint64(sweep))
+    z = np.zeros_like(p)
+    key = (np.uint64(seed), np.uint64(((batch_item & 0xFFFFFFFF) << 32) | TAG_SA))
+    w = _ph.philox4x64_10((p, s, z, z), key)
+    return w[0].reshape(ny, nx), w[1].reshape(ny, nx)
+
+
+def sa_proposal(k, L, word):
+    """Proposed level of a trial: another level than k, uniformly
+    (k + 1 + floor(u (L - 1))) mod L with u = u24(word); binary: the flip."""
+    return int((k + 1 + int(np.floor(float(_ph.u24(word)) * (L - 1)))) % L)
+
+
+def simulated_annealing(T, L, init_levels, sweeps, t0, alpha, seed=0, batch_item=0, history=False):
+    """Simulated annealing from init_levels over `sweeps` raster sweeps.
+
+    Trial at pixel (y, x): propose sa_proposal(k, L, word 0); dE = change of
+    the replay error sum (|R| - T)^2; accept when dE < 0, or when tau > 0
+    and u24(word 1) < exp(-dE / tau), tau = t0 alpha^(s - 1) in the units of
+    the error.  Returns (levels, errors: the error before sweep 1 and after
+    each sweep, accepted trial count[, the levels after each sweep when
+    history]).  Parity unpinned as a quality
+    statement (the schedule is a reading); the acceptance rule is pinned by
+    its stationary distribution.
+    """
+    T = np.asarray(T, dtype=np.float64)
+    ny, nx = T.shape
+    lev = np.asarray(init_levels, np.int64).copy()
+    R = _dft.centre(_dft.dft2(_slm.level_phasor(lev, L)))
+    err = float(np.sum((np.abs(R) - T) ** 2))
+    errors, accepted, hist = [err], 0, []
+    kernels = {}
+    for sweep in range(1, sweeps + 1):
+        tau = t0 * alpha ** (sweep - 1)
+        w0, w1 = sa_words(seed, sweep, ny, nx, batch_item)
+        for y in range(ny):
+            for x in range(nx):
+                if (y, x) not in kernels:
+                    kernels[(y, x)] = _kernel(ny, nx, y, x)
+                k = int(lev[y, x])
+                kn = sa_proposal(k, L, w0[y, x])
+                Rn = R + (_slm.level_phasor(np.array(kn), L) - _slm.level_phasor(np.array(k), L)) * kernels[(y, x)]
+                en = float(np.sum((np.abs(Rn) - T) ** 2))
+                de = en - err
+                ok = de < 0.0 or (tau > 0.0 and float(_ph.u24(w1[y, x])) < np.exp(-de / tau))
+                if ok:
+                    lev[y, x], R, err = kn, Rn, en
+                    accepted += 1
+        errors.append(err)
+        if history:
+            hist.append(lev.copy())
+    if history:
+        return lev, np.array(errors), accepted, hist
+    return lev, np.array(errors), accepted
