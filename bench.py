@@ -208,6 +208,56 @@ def torchfft_context(B, iters=10):
     return B * iters / (time.perf_counter() - t0)
 
 
+def search_workload(args):
+    """Holographic search: 256 binary holograms of 64 x 64 pixels, direct
+    search from random levels until a sweep keeps no change (at most 40
+    sweeps), one call.  value = pixel trials per second (one trial = one
+    proposed level change, whose error change sums over all 4096 replay
+    pixels)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2008_12214_amd as hg
+    dev = torch.device("cuda:0")
+    B, n, L, max_sw = 256, 64, 2, 40
+    T = torch.from_numpy(np.stack([synth.gaussian_target(n, seed=61, batch_item=b) for b in range(B)])).to(dev)
+    init = torch.from_numpy(np.random.default_rng(7).integers(0, L, (B, n, n)).astype(np.uint8)).to(dev)
+    ws = torch.empty(hg.hg_search_workspace_size(n, n, B), dtype=torch.uint8, device=dev)
+    out = hg.hg_search(T, L, hg.HG_SEARCH_DS, max_sw, init, workspace=ws)  # warm-up
+    torch.cuda.synchronize(dev)
+    times = []
+    for _ in range(max(1, args.steps)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        out = hg.hg_search(T, L, hg.HG_SEARCH_DS, max_sw, init, workspace=ws)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b) * 1e-3)
+    med = sorted(times)[len(times) // 2]
+    sweeps = out["sweeps"].cpu().numpy()
+    trials = int(np.sum(sweeps)) * n * n * (L - 1)
+    flops_per_trial = 22 * n * n  # per replay pixel: kernel and change products, modulus, error terms
+    achieved = trials * flops_per_trial / med / 1e12
+    err = out["error"].cpu().numpy()
+    log(f"search: {trials} trials in {med * 1e3:.1f} ms, {trials / med:.3e} trials/s")
+    res = {"metric": "pixel trials/s (holographic direct search)", "value": round(trials / med, 1),
+           "unit": "trials/s", "n_gpus": 1, "steps": len(times), "warmup": 1,
+           "ms_per_step": round(med * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "direct_search_binary_64x64_x256", "batch": B, "grid": [n, n], "slm_levels": L,
+                      "max_sweeps": max_sw, "start": "uniform random levels"},
+           "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": 157.3, "unit": "TFLOP/s",
+                        "frac": round(achieved / 157.3, 4), "traffic": None,
+                        "kernel": "k_search<64,64> (one workgroup per hologram, sequential trials)",
+                        "flop_per_trial": flops_per_trial},
+           "cpu_baseline": None,
+           "extra": {"sweeps_median": float(np.median(sweeps)), "us_per_trial_per_hologram": round(
+               med / (np.max(sweeps) * n * n * (L - 1)) * 1e6, 3),
+               "error_median_start": float(np.median(err[:, 0])),
+               "error_median_final": float(np.median(err[np.arange(B), sweeps]))}}
+    print(json.dumps(res), flush=True)
+
+
 def other_workload(args):
     """The non-headline workloads, one JSON line each.  The timed region is K
     replays of a HIP graph holding one whole library call (set-up, every
@@ -498,14 +548,14 @@ def main():
                     help="iterations per hologram (100 is the workload; fewer only for short profiles)")
     ap.add_argument("--workload", default="wgs1024",
                     choices=["wgs1024", "gs64", "ospr512", "ospr1024x32", "uneven", "lt1024", "amp1024",
-                             "wgs1024f16"],
+                             "wgs1024f16", "search64"],
                     help="wgs1024 (default): the headline batch; gs64: one 64^2 8-level GS, latency; "
                          "ospr512: adaptive binary OSPR, 512^2, 24 subframes; uneven: 256 Fresnel problems "
                          "of four sizes, 8 levels, 50 iterations; lt1024: 32 binary Liu-Taghizadeh problems "
                          "of 1024^2, 100 iterations, region radius 256 + 4 per iteration; ospr1024x32: 32 "
                          "adaptive binary OSPR problems of 1024^2, 24 subframes, in one call; amp1024: the "
                          "headline batch on a binary amplitude SLM; wgs1024f16: the headline batch with 16-bit "
-                         "field storage")
+                         "field storage; search64: direct search on 256 binary 64^2 holograms")
     ap.add_argument("--context", action="store_true",
                     help="also time the same loop as unfused torch.fft (rocFFT) ops, for context")
     ap.add_argument("--oracle-scaling", action="store_true",
@@ -524,6 +574,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "search64":
+        search_workload(args)
+        return
     if args.workload != "wgs1024":
         other_workload(args)
         return

@@ -342,6 +342,38 @@ hg_status hg_timing_read(hg_kernel_times* out);
  * workspace.  NULL or misaligned workspace: HG_ERR_INVALID_ARG.            */
 hg_status hg_numeric_status(const void* workspace, void* stream);
 
+/* Holographic search ("Holographic Search Algorithms" section): direct
+ * search (DS) and simulated annealing (SA) on phase SLMs, one hologram per
+ * workgroup, `batch` holograms of one size per call.
+ *   targets      [batch][ny][nx] float raw replay amplitudes, prepared as
+ *                for hg_gs (scaled to sum T^2 = nx ny; binary symmetrised)
+ *   ny, nx       8, 16, 32 or 64 (the replay field lives in registers)
+ *   slm_levels   2..256 phase levels 2 pi k / L
+ *   algorithm    HG_SEARCH_DS: raster sweeps trying every other level at
+ *                each pixel, keeping a change when the error
+ *                E = sum (|R| - T)^2 (unit-rms scale) falls by more than
+ *                1e-12, until a sweep keeps none (or max_sweeps);
+ *                HG_SEARCH_SA: one proposal per pixel per sweep, level
+ *                (k + 1 + floor(u0 (L - 1))) mod L, kept when E falls or
+ *                when u1 < exp(-dE / tau), tau = t0 alpha^(s - 1) in the
+ *                units of E, for max_sweeps sweeps; u0, u1 = the top 24
+ *                bits of words 0 and 1 of the Philox4x64-10 block at
+ *                counter (y nx + x, s, 0, 0), key (seed, (b << 32) | 0x5A)
+ *                for hologram b
+ *   init_levels  [batch][ny][nx] uint8 start levels (< slm_levels), required
+ *   levels_out   [batch][ny][nx] uint8 final levels
+ *   error_out    [batch][max_sweeps + 1] doubles: E before the first sweep
+ *                and after each (DS: repeated after the last sweep run)
+ *   sweeps_out   nullable [batch] ints: sweeps run (DS: including the sweep
+ *                that kept no change)
+ *   workspace    hg_search_workspace_size(ny, nx, batch) bytes (256-aligned)
+ * Errors as hg_gs (sizes outside the list: HG_ERR_UNSUPPORTED_SIZE).       */
+enum hg_search_algorithm { HG_SEARCH_DS = 0, HG_SEARCH_SA = 1 };
+size_t hg_search_workspace_size(int ny, int nx, int batch);
+hg_status hg_search(const float* targets, int batch, int ny, int nx, int slm_levels, int algorithm, int max_sweeps,
+                    double t0, double alpha, uint64_t seed, const uint8_t* init_levels, uint8_t* levels_out,
+                    double* error_out, int* sweeps_out, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Weighted GS with no workspace argument, for callers that cannot allocate
  * device memory (code under HIP graph capture, serving loops, harnesses
  * that forbid hipMalloc).  Arguments, results and errors as hg_wgs; the

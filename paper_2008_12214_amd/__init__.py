@@ -11,7 +11,7 @@ from ._binding import (  # noqa: F401
     HG_OK, HG_ERR_INVALID_ARG, HG_ERR_UNSUPPORTED_SIZE, HG_ERR_WORKSPACE, HG_ERR_HIP, HG_ERR_NUMERIC,
     HG_OP_GS, HG_OP_WGS, HG_OP_OSPR, HG_OP_PROPAGATE,
     HologenError, lib, lib_path,
-    hg_workspace_size, hg_gs, hg_wgs, hg_wgs_static, HG_STATIC_SCRATCH_BYTES, HG_SLM_AMPLITUDE, HG_FIELD_FP16, hg_gs_step, hg_numeric_status, hg_lt, hg_ospr, hg_ospr_batched, hg_fresnel_propagate,
+    hg_workspace_size, hg_gs, hg_wgs, hg_wgs_static, HG_STATIC_SCRATCH_BYTES, HG_SLM_AMPLITUDE, HG_FIELD_FP16, hg_search, hg_search_workspace_size, HG_SEARCH_DS, HG_SEARCH_SA, hg_gs_step, hg_numeric_status, hg_lt, hg_ospr, hg_ospr_batched, hg_fresnel_propagate,
     hg_gs_batched, hg_gs_batched_workspace_size, hg_random_phase, hg_status_string, hg_last_error,
     hg_timing_enable, hg_timing_read, hg_autotune, hg_set_launch_config, hg_get_launch_config,
     hg_set_small_fused, hg_set_column_kernel, COLUMN_TILE, COLUMN_PERSISTENT, COLUMN_CLASSIC,

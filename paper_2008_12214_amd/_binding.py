@@ -74,6 +74,10 @@ def lib():
                              _vp]
         L.hg_wgs_static.restype = _i
         L.hg_wgs_static.argtypes = [_vp, _i, _i, _i, _i, _u64, _vp, _vp, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.hg_search_workspace_size.restype = _sz
+        L.hg_search_workspace_size.argtypes = [_i, _i, _i]
+        L.hg_search.restype = _i
+        L.hg_search.argtypes = [_vp, _i, _i, _i, _i, _i, _i, _d, _d, _u64, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
         L.hg_gs_step.restype = _i
         L.hg_gs_step.argtypes = [_vp, _i, _i, _i, _i, _vp, _vp, _d, _d, _d, _i, _vp, _vp, _vp, _vp, _vp, _vp,
                                  _vp, _sz, _vp]
@@ -282,6 +286,33 @@ HG_STATIC_SCRATCH_BYTES = 32 << 20
 HG_SLM_AMPLITUDE = 0x10000
 # slm_levels flag: the field between passes held as two binary16 values (ny in 256..1024)
 HG_FIELD_FP16 = 0x20000
+
+
+HG_SEARCH_DS, HG_SEARCH_SA = 0, 1
+
+
+def hg_search_workspace_size(ny, nx, batch):
+    return int(lib().hg_search_workspace_size(ny, nx, batch))
+
+
+def hg_search(targets, slm_levels, algorithm, max_sweeps, init_levels, t0=0.0, alpha=1.0, seed=0, stream=None,
+              workspace=None):
+    """Direct search or simulated annealing over a batch of holograms of one
+    size: targets [B, ny, nx] float32, init_levels [B, ny, nx] uint8 (CUDA).
+    Returns dict(levels [B, ny, nx], error [B, max_sweeps + 1], sweeps [B])."""
+    torch = _torch()
+    B, ny, nx = targets.shape
+    _dev_tensor(targets, torch.float32, (B, ny, nx), "targets")
+    _dev_tensor(init_levels, torch.uint8, (B, ny, nx), "init_levels")
+    dev = targets.device
+    ws = _workspace(int(lib().hg_search_workspace_size(ny, nx, B)), dev, workspace)
+    levels = torch.empty((B, ny, nx), dtype=torch.uint8, device=dev)
+    err = torch.empty((B, max_sweeps + 1), dtype=torch.float64, device=dev)
+    sweeps = torch.empty(B, dtype=torch.int32, device=dev)
+    _check(lib().hg_search(_ptr(targets), B, ny, nx, int(slm_levels), int(algorithm), int(max_sweeps), float(t0),
+                           float(alpha), seed & (2**64 - 1), _ptr(init_levels), _ptr(levels), _ptr(err),
+                           _ptr(sweeps), _ptr(ws), ws.numel(), _stream(dev, stream)))
+    return dict(levels=levels, error=err, sweeps=sweeps)
 
 
 def hg_gs_step(target, slm_levels, levels_in=None, field_in=None, weights=None, lt_radius=-1, wavelength_m=0.0,

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhologen.so")
 SIZES = (64, 128, 256, 512, 1024, 2048, 4096)
 SOURCES = [os.path.join(HERE, "csrc", "hg_api.hip"), os.path.join(HERE, "csrc", "hg_nn.hip"),
-           os.path.join(HERE, "csrc", "hg_small.hip")] + \
+           os.path.join(HERE, "csrc", "hg_small.hip"), os.path.join(HERE, "csrc", "hg_search.hip")] + \
           [os.path.join(HERE, "csrc", f"hg_n{n}.hip") for n in SIZES]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -213,3 +213,21 @@ def test_amplitude_slm_argument_checks():
     assert L.hg_lt(FAKE, 64, 64, 5, A | 2, 1, None, None, 0.0, 0.0, 0.0, 4, 1, FAKE, None, None, None, FAKE,
                    1 << 30, None) == hg.HG_ERR_INVALID_ARG
     assert "phase SLMs" in hg.hg_last_error()
+
+
+def test_search_argument_checks():
+    """hg_search validates sizes, levels, algorithm and sweeps on the host."""
+    def call(ny=16, nx=16, levels=2, algo=0, sweeps=5, t0=0.0, alpha=1.0, init=FAKE, ws=FAKE, wsb=1 << 30):
+        return L.hg_search(FAKE, 2, ny, nx, levels, algo, sweeps, t0, alpha, 1, init, FAKE, FAKE, None, ws, wsb, None)
+    assert hg.hg_search_workspace_size(16, 16, 2) == 2 * 16 * 16 * 8
+    assert hg.hg_search_workspace_size(128, 16, 2) == 0
+    assert call(ny=128) == hg.HG_ERR_UNSUPPORTED_SIZE
+    assert call(nx=12) == hg.HG_ERR_UNSUPPORTED_SIZE
+    assert call(levels=1) == hg.HG_ERR_INVALID_ARG
+    assert call(algo=7) == hg.HG_ERR_INVALID_ARG
+    assert call(sweeps=0) == hg.HG_ERR_INVALID_ARG
+    assert call(init=None) == hg.HG_ERR_INVALID_ARG
+    assert call(algo=1, t0=-1.0) == hg.HG_ERR_INVALID_ARG
+    assert call(algo=1, alpha=0.0) == hg.HG_ERR_INVALID_ARG
+    assert call(ws=None) == hg.HG_ERR_WORKSPACE
+    assert call(wsb=100) == hg.HG_ERR_WORKSPACE
