@@ -336,12 +336,17 @@ __device__ __forceinline__ int level_index(float2 g, int L) {
 // from comparing |y| with |x| (L = 4: boundary at pi/4) or with tan(pi/8) |x|
 // and |x| with tan(pi/8) |y| (L = 8: boundaries at pi/8 and 3 pi/8).  The
 // product's FP32 rounding moves a boundary by about 1e-7 rad.  g = 0 gives 0.
+// Selects only (no branch on L): a projection loop over a thread's elements
+// stays one basic block, so the compiler can overlap the elements' loads.
 __device__ __forceinline__ int level_index_quad(float2 g, int L) {
   const float ax = fabsf(g.x), ay = fabsf(g.y);
   constexpr float kTan8 = 0.414213562373095049f;  // tan(pi/8)
-  int q;  // level within the quadrant, 0 nearest the x axis
-  if (L == 8) q = ay <= kTan8 * ax ? 0 : (ax <= kTan8 * ay ? 2 : 1);
-  else q = ay <= ax ? 0 : 1;
+  const bool l8 = L == 8;
+  const float tq = l8 ? kTan8 : 1.0f;  // the first boundary: pi/8 or pi/4
+  // level within the quadrant, 0 nearest the x axis: past the first
+  // boundary, and (L = 8) past the second at 3 pi/8
+  const bool a = ay > tq * ax, b = l8 && ax <= kTan8 * ay;
+  const int q = a ? (b ? 2 : 1) : 0;
   const int up = g.x < 0.0f ? (L >> 1) - q : q;  // as if y >= 0
   return g.y < 0.0f ? (L - up) & (L - 1) : up;
 }
