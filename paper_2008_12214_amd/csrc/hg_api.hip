@@ -331,10 +331,11 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
   bool all_quad = true;
   for (const Desc& d : ds) all_quad &= ((d.L == 4 || d.L == 8) && !d.mod);
   const int lk = all_bin ? LK_BIN : all_quad ? LK_QUAD : LK_ANY;
+  // weighted GS: each row pass also sets 1 / m for the column pass after it
+  bt.row_invm = weighted ? 1 : 0;
   launch_row(bt, cfg.RPB, B, fresnel, lk, ROW_INIT, 0, nullptr, nullptr, st);
   const int cmode = weighted ? COL_WGS : COL_GS;
   for (int k = 1; k <= kmax; ++k) {
-    launch_col_prep(bt, cfg.C, B, cmode, k, st);
     launch_col(bt, cfg.C, B, cmode, k, 0, nullptr, nullptr, st);
     launch_row(bt, cfg.RPB, B, fresnel, lk, ROW_ITER, k, nullptr, nullptr, st);
   }

@@ -62,6 +62,8 @@ struct Batch {
   int* status;          // the call's numeric status word: nonzero once a finisher saw non-finite sums
   int dump;             // some problem asks for r_out: the first column pass runs its dumping instantiation
   int f16;              // the field plane holds two binary16 values per element (4 bytes), not complex64
+  int row_invm;         // weighted GS: the row pass after column pass k (or the initial one, k = 0) sets
+                        // invm of every problem for column pass k + 1 from the weight sums of slot k
   float s16_row, inv16_row;  // 16-bit planes: the row pass stores x s16_row, the column pass loads x inv16_row
   float s16_col, inv16_col;  // the column pass stores x s16_col, the row pass loads x inv16_col
 };
@@ -234,6 +236,21 @@ __device__ __forceinline__ double slot_total(const Batch& bt, int b, int slot, i
   }
   __syncthreads();
   return *bcast;
+}
+
+// Weighted GS: 1 / m of problem b, m the mean weight on the support, from the
+// weight sums in slot k (the support size in the set-up slot), computed by
+// one wave in slot_total's fixed order.
+__device__ __forceinline__ void wgs_invm_wave(const Batch& bt, int b, int k) {
+  const int lane = threadIdx.x & 63;
+  double om = 0.0, ws = 0.0;
+  for (int i = lane; i < bt.nblk; i += 64) {
+    om += part_ptr(bt, b, bt.slots - 1, i)[1];
+    ws += part_ptr(bt, b, k, i)[3];
+  }
+  om = wave_sum(om);
+  ws = wave_sum(ws);
+  if (lane == 0) bt.invm[b] = (float)((om > 0.0 ? om : 1.0) / ws);
 }
 
 // ---------------------------------------------------------------------------
@@ -519,6 +536,15 @@ __global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k
   constexpr bool TAB = (MODE == ROW_ITER && (LK == LK_ANY || LK == LK_QUAD));
   __shared__ float2 lvl[TAB ? 256 : 1];
   const int b = blockIdx.y;
+  // weighted GS: the next column pass's 1 / m of every problem, by the first
+  // wave of the first workgroups dispatched (they have the whole launch to
+  // finish it; the weight sums were complete before this launch began)
+  if constexpr (MODE == ROW_INIT || MODE == ROW_ITER) {
+    if (bt.row_invm && b == 0 && threadIdx.x < 64) {
+      for (int p = blockIdx.x; p < (int)gridDim.y; p += (int)gridDim.x)
+        wgs_invm_wave(bt, p, MODE == ROW_INIT ? 0 : arg);
+    }
+  }
   const int r = threadIdx.x / T, t = threadIdx.x % T;
   const int y = blockIdx.x * RPB + r;
   const size_t off = (size_t)b * bt.ny * NX;
@@ -1644,17 +1670,7 @@ static __global__ void k_weights_out(Batch bt) {
 
 // 1 / m_{k-1} of every problem for the pipelined weighted-GS column pass k:
 // the same fixed-order sums as slot_total.
-static __global__ __launch_bounds__(64) void k_wgs_invm(Batch bt, int k) {
-  const int b = blockIdx.x;
-  double om = 0.0, ws = 0.0;
-  for (int i = threadIdx.x; i < bt.nblk; i += 64) {
-    om += part_ptr(bt, b, bt.slots - 1, i)[1];
-    ws += part_ptr(bt, b, k - 1, i)[3];
-  }
-  om = wave_sum(om);
-  ws = wave_sum(ws);
-  if (threadIdx.x == 0) bt.invm[b] = (float)((om > 0.0 ? om : 1.0) / ws);
-}
+static __global__ __launch_bounds__(64) void k_wgs_invm(Batch bt, int k) { wgs_invm_wave(bt, blockIdx.x, k - 1); }
 
 // NMSE = 1 - sta^2 / (stt saa) from the FP64 sums; a replay or target of
 // zero energy gives 1.  Non-finite sums give NaN and raise the call's
