@@ -136,18 +136,36 @@ __global__ __launch_bounds__(256) void k_conv3x3(const u16* __restrict__ X, cons
 // of a 16-byte A-fragment read fall in distinct bank groups.
 __host__ __device__ inline int tile_pixel_stride(int Cin) { return ((Cin / 8) & 1) ? Cin : Cin + 8; }
 
-template <int NB, int GW>
+// Division by a runtime divisor d (the same for the whole launch) with one
+// multiply-high: q = floor(i m / 2^32), m = ceil(2^32 / d), exact for
+// i < 2^32 / d (d < 2^16 here, indices below 2^16); d = 1 is handled apart.
+struct FastDiv {
+  uint32_t d, m;
+  __device__ __forceinline__ explicit FastDiv(uint32_t dd) : d(dd), m(dd > 1 ? 0xFFFFFFFFu / dd + 1u : 0u) {}
+  __device__ __forceinline__ uint32_t div(uint32_t i) const { return d > 1 ? __umulhi(i, m) : i; }
+};
+
+// Global 16-byte load at a wave-uniform base plus a 32-bit byte offset (one
+// scalar base register pair, no 64-bit address arithmetic per lane).
+__device__ __forceinline__ bf16x8 load8_at(const u16* base, uint32_t byte_off) {
+  typedef const __attribute__((address_space(1))) uint4* gp;
+  return __builtin_bit_cast(bf16x8, *(gp)((const __attribute__((address_space(1))) char*)base + byte_off));
+}
+
+// A32: Cin % 32 == 0, so each 32-wide k step lies in one tap and its tap and
+// first channel are the same for the whole wave (kept in scalar registers);
+// otherwise (Cin = 16 or 48) each lane tracks its own (tap, channel).
+template <int NB, int GW, bool A32>
 __global__ __launch_bounds__(256) void k_conv3x3_tile(const u16* __restrict__ X, const u16* __restrict__ Wg,
                                                       const float* __restrict__ bias, const u16* __restrict__ mask,
                                                       u16* __restrict__ Y, int H, int W, int Cin, int Cout, int Kpad,
                                                       int relu, int TW, int R) {
   extern __shared__ __align__(16) u16 smem[];
-  const int tiles_x = W / TW + (W % TW ? 1 : 0), tiles_y = H / R + (H % R ? 1 : 0);
-  int t = blockIdx.x;
-  const int tx = t % tiles_x;
-  t /= tiles_x;
-  const int ty = t % tiles_y;
-  const int n = t / tiles_y;
+  // grid: x = tile of the image (tiles_x per tile row), y = output-channel
+  // block, z = image
+  const int tiles_x = W / TW + (W % TW ? 1 : 0);
+  const int ty = (int)blockIdx.x / tiles_x, tx = (int)blockIdx.x - ty * tiles_x;
+  const int n = blockIdx.z;
   const int x0 = tx * TW, y0 = ty * R;
   const int TWp = TW + 2;
   const int PS = tile_pixel_stride(Cin);           // LDS elements per pixel
@@ -155,72 +173,114 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(const u16* __restrict__ X,
   u16* outs = smem + (size_t)(R + 2) * TWp * PS;   // [R TW][16 NB]
   const int cpp = Cin / 8;                         // 16-byte chunks per pixel
   const u16* xn = X + (size_t)n * H * W * Cin;
-  for (int i = threadIdx.x; i < (R + 2) * TWp * cpp; i += 256) {
-    const int c = i % cpp, pix = i / cpp;
-    const int ly = pix / TWp, lx = pix - ly * TWp;
-    const int gy = y0 + ly - 1, gx = x0 + lx - 1;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-      v = *reinterpret_cast<const uint4*>(xn + ((size_t)gy * W + gx) * Cin + 8 * c);
-    *reinterpret_cast<uint4*>(in + (size_t)pix * PS + 8 * c) = v;
-  }
-  __syncthreads();
+  const int co0 = blockIdx.y * 16 * NB;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = lane & 15, kb = lane >> 4;
+  float bv[NB];  // bias, fetched before the k loop
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) bv[nb] = bias ? bias[co0 + nb * 16 + m] : 0.f;
+  {
+    const FastDiv by_cpp((uint32_t)cpp), by_twp((uint32_t)TWp);
+    const int nchunk = (R + 2) * TWp * cpp;
+    for (int i = threadIdx.x; i < nchunk; i += 256) {
+      const int pix = (int)by_cpp.div((uint32_t)i), c = i - pix * cpp;
+      const int ly = (int)by_twp.div((uint32_t)pix), lx = pix - ly * TWp;
+      const int gy = y0 + ly - 1, gx = x0 + lx - 1;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+        v = *reinterpret_cast<const uint4*>(xn + ((size_t)gy * W + gx) * Cin + 8 * c);
+      *reinterpret_cast<uint4*>(in + (size_t)pix * PS + 8 * c) = v;
+    }
+  }
+  __syncthreads();
   const int gpr = TW / 16;
-  const int co0 = blockIdx.y * 16 * NB;
   const int K = 9 * Cin;
   f32x4 acc[GW][NB];
 #pragma unroll
   for (int j = 0; j < GW; ++j)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[j][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  int abase[GW];  // LDS element offset of lane m's pixel (tap (0, 0)) in group j
+  // LDS byte offset of lane m's pixel (tap (0, 0)) in group j, plus the
+  // lane's channel offset 8 kb when the k steps are tap-aligned
+  uint32_t abase[GW];
 #pragma unroll
   for (int j = 0; j < GW; ++j) {
     const int g = wave * GW + j;
     const int r = g / gpr, xg = (g - r * gpr) * 16;
-    abase[j] = (r * TWp + xg + m) * PS;
+    abase[j] = (uint32_t)(((r * TWp + xg + m) * PS + (A32 ? 8 * kb : 0)) * 2);
   }
-  // weight fragments are fetched one k step ahead of their use
-  const u16* wrow[NB];
+  auto lds8 = [&](uint32_t byte_off) { return *reinterpret_cast<const bf16x8*>(reinterpret_cast<const char*>(in) + byte_off); };
+  // weight rows: byte offset of lane (m, kb)'s fragment of block nb at k = 0
+  uint32_t woff[NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) wrow[nb] = Wg + (size_t)(co0 + nb * 16 + m) * Kpad + 8 * kb;
-  bf16x8 b[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) b[nb] = load8(wrow[nb]);
-  for (int kc = 0; kc < Kpad; kc += 32) {
-    const int k = kc + 8 * kb;
-    const bool kv = k < K;
-    int off = 0;
-    if (kv) {
-      const int tap = k / Cin, ci = k - tap * Cin;
-      off = ((tap / 3) * TWp + tap % 3) * PS + ci;
+  for (int nb = 0; nb < NB; ++nb) woff[nb] = (uint32_t)(((co0 + nb * 16 + m) * Kpad + 8 * kb) * 2);
+  // k = kc + 8 kb as (tap, channel) of the next step to load: A32 tracks the
+  // wave's (tap offset, first channel) of the step; otherwise each lane
+  // tracks its own, with up to two wraps per step of 32 (Cin >= 16)
+  int ci = A32 ? 0 : 8 * kb, kx = 0, toff = 0;
+  auto wrap = [&]() {
+    if (ci >= Cin) {
+      ci -= Cin;
+      const bool row_end = kx == 2;
+      kx = row_end ? 0 : kx + 1;
+      toff += row_end ? (TWp - 2) * PS : PS;
     }
-    bf16x8 bn[NB];
-    const int kn = kc + 32 < Kpad ? kc + 32 : kc;
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) bn[nb] = load8(wrow[nb] + kn);
-#pragma unroll
-    for (int j = 0; j < GW; ++j) {
-      const bf16x8 a = kv ? load8(in + abase[j] + off) : zero8();
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[j][nb], 0, 0, 0);
-    }
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) b[nb] = bn[nb];
+  };
+  if constexpr (!A32) {
+    wrap();
+    wrap();
   }
+  // fragments of k step kl into (b, a), then advance the cursor.  Steps past
+  // the last load the last step's weights again (a valid address) and zero A
+  // fragments, so every step issues the same loads and the outstanding-load
+  // count is the same on every path.
+  auto load_step = [&](int kl, bf16x8 (&b)[NB], bf16x8 (&a)[GW]) {
+    const u16* wk = Wg + (kl < Kpad ? kl : Kpad - 32);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) b[nb] = load8_at(wk, woff[nb]);
+    const bool kv = A32 ? kl < Kpad : kl + 8 * kb < K;
+    const uint32_t off = (uint32_t)((toff + ci) * 2);
+#pragma unroll
+    for (int j = 0; j < GW; ++j) a[j] = kv ? lds8(abase[j] + off) : zero8();
+    ci += 32;
+    wrap();
+    if constexpr (!A32) wrap();
+  };
+  auto mma = [&](const bf16x8 (&b)[NB], const bf16x8 (&a)[GW]) {
+#pragma unroll
+    for (int j = 0; j < GW; ++j)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j], b[nb], acc[j][nb], 0, 0, 0);
+  };
+  // software pipeline over three register sets, unrolled three times so no
+  // fragment is copied: step s uses set s mod 3 while the load for step s + 2
+  // goes into the set step s - 1 used
+  bf16x8 bs0[NB], bs1[NB], bs2[NB], as0[GW], as1[GW], as2[GW];
+  const int nsteps = Kpad / 32, ntrip = nsteps / 3;
+  load_step(0, bs0, as0);
+  load_step(32, bs1, as1);
+  int kc = 0;
+  for (int tr = 0; tr < ntrip; ++tr, kc += 96) {
+    load_step(kc + 64, bs2, as2);
+    mma(bs0, as0);
+    load_step(kc + 96, bs0, as0);
+    mma(bs1, as1);
+    load_step(kc + 128, bs1, as1);
+    mma(bs2, as2);
+  }
+  // the last one or two steps (in sets 0 and 1)
+  if (nsteps - 3 * ntrip >= 1) mma(bs0, as0);
+  if (nsteps - 3 * ntrip >= 2) mma(bs1, as1);
   constexpr int CW = 16 * NB;  // staged channels per pixel
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    const float bv = bias ? bias[co0 + nb * 16 + m] : 0.f;
 #pragma unroll
     for (int j = 0; j < GW; ++j) {
       const int g = wave * GW + j;
       const int r = g / gpr, xg = (g - r * gpr) * 16;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        float v = acc[j][nb][i] + bv;
+        float v = acc[j][nb][i] + bv[nb];
         if (relu) v = fmaxf(v, 0.f);
         outs[(r * TW + xg + 4 * kb + i) * CW + nb * 16 + m] = f2bf(v);
       }
@@ -228,9 +288,10 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(const u16* __restrict__ X,
   }
   __syncthreads();
   constexpr int CPO = CW / 8;  // 16-byte chunks per staged pixel
+  const FastDiv by_tw((uint32_t)TW);
   for (int i = threadIdx.x; i < R * TW * CPO; i += 256) {
-    const int c = i % CPO, pl = i / CPO;
-    const int ly = pl / TW, lx = pl - ly * TW;
+    const int pl = i / CPO, c = i - pl * CPO;
+    const int ly = (int)by_tw.div((uint32_t)pl), lx = pl - ly * TW;
     const int gy = y0 + ly, gx = x0 + lx;
     if (gy < H && gx < W) {
       uint4 v = *reinterpret_cast<const uint4*>(outs + pl * CW + 8 * c);
@@ -997,18 +1058,26 @@ bool tile_shape(int W, int Cin, int NB, int* R, int* TW, int* GW) {
   return false;
 }
 
+template <int NB, bool A32>
+void conv_tile_launch_a(int GW, dim3 grid, size_t lds, hipStream_t st, const u16* X, const u16* Wg, const float* bias,
+                        const u16* mask, u16* Y, int H, int W, int Cin, int Cout, int Kp, int relu, int TW, int R) {
+  if (GW == 4)
+    hipLaunchKernelGGL((k_conv3x3_tile<NB, 4, A32>), grid, dim3(256), lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout,
+                       Kp, relu, TW, R);
+  else if (GW == 2)
+    hipLaunchKernelGGL((k_conv3x3_tile<NB, 2, A32>), grid, dim3(256), lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout,
+                       Kp, relu, TW, R);
+  else
+    hipLaunchKernelGGL((k_conv3x3_tile<NB, 1, A32>), grid, dim3(256), lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout,
+                       Kp, relu, TW, R);
+}
 template <int NB>
 void conv_tile_launch(int GW, dim3 grid, size_t lds, hipStream_t st, const u16* X, const u16* Wg, const float* bias,
                       const u16* mask, u16* Y, int H, int W, int Cin, int Cout, int Kp, int relu, int TW, int R) {
-  if (GW == 4)
-    hipLaunchKernelGGL((k_conv3x3_tile<NB, 4>), grid, dim3(256), lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout, Kp,
-                       relu, TW, R);
-  else if (GW == 2)
-    hipLaunchKernelGGL((k_conv3x3_tile<NB, 2>), grid, dim3(256), lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout, Kp,
-                       relu, TW, R);
+  if (Cin % 32 == 0)
+    conv_tile_launch_a<NB, true>(GW, grid, lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout, Kp, relu, TW, R);
   else
-    hipLaunchKernelGGL((k_conv3x3_tile<NB, 1>), grid, dim3(256), lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout, Kp,
-                       relu, TW, R);
+    conv_tile_launch_a<NB, false>(GW, grid, lds, st, X, Wg, bias, mask, Y, H, W, Cin, Cout, Kp, relu, TW, R);
 }
 
 void conv_launch(const u16* X, const u16* Wg, const float* bias, const u16* mask, u16* Y, long P, int H, int W,
@@ -1016,10 +1085,10 @@ void conv_launch(const u16* X, const u16* Wg, const float* bias, const u16* mask
   const int nb16 = Cout / 16;
   const int NB = nb16 % 4 == 0 ? 4 : nb16 % 3 == 0 ? 3 : nb16 % 2 == 0 ? 2 : 1;
   int R, TW, GW;
-  if (tile_shape(W, Cin, NB, &R, &TW, &GW)) {
+  if (P / ((long)H * W) <= 65535 && tile_shape(W, Cin, NB, &R, &TW, &GW)) {  // images on grid.z
     const long N = P / ((long)H * W);
-    const long tiles = N * (H / R + (H % R ? 1 : 0)) * (W / TW + (W % TW ? 1 : 0));
-    const dim3 grid((unsigned)tiles, nb16 / NB);
+    const long tiles = (long)(H / R + (H % R ? 1 : 0)) * (W / TW + (W % TW ? 1 : 0));
+    const dim3 grid((unsigned)tiles, nb16 / NB, (unsigned)N);
     const size_t lds = ((size_t)(R + 2) * (TW + 2) * tile_pixel_stride(Cin) + (size_t)R * TW * 16 * NB) * 2;
     const int Kp = kpad_of(9 * Cin);
     switch (NB) {
