@@ -15,6 +15,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 
 #include <algorithm>
 
@@ -292,6 +293,183 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(const u16* __restrict__ X,
   for (int i = threadIdx.x; i < R * TW * CPO; i += 256) {
     const int pl = i / CPO, c = i - pl * CPO;
     const int ly = (int)by_tw.div((uint32_t)pl), lx = pl - ly * TW;
+    const int gy = y0 + ly, gx = x0 + lx;
+    if (gy < H && gx < W) {
+      uint4 v = *reinterpret_cast<const uint4*>(outs + pl * CW + 8 * c);
+      const size_t o = (((size_t)n * H + gy) * W + gx) * Cout + co0 + 8 * c;
+      if (mask) {
+        const uint4 mk = *reinterpret_cast<const uint4*>(mask + o);
+        uint32_t* vv = reinterpret_cast<uint32_t*>(&v);
+        const uint32_t* mm = reinterpret_cast<const uint32_t*>(&mk);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t lo = bf2f((u16)(mm[q] & 0xFFFFu)) > 0.f ? 0x0000FFFFu : 0u;
+          const uint32_t hi = bf2f((u16)(mm[q] >> 16)) > 0.f ? 0xFFFF0000u : 0u;
+          vv[q] &= lo | hi;
+        }
+      }
+      *reinterpret_cast<uint4*>(Y + o) = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The convolution for Cin % 16 == 0 with input channels streamed in chunks
+// of 32 (the last one 16 when Cin % 32 == 16): a workgroup covers a 4 x 64 pixel tile of one image for 16 NB
+// output channels, wave w row w of the tile (four 16-pixel groups).  For
+// each chunk, the 6 x 66 halo tile and the chunk's weights (9 taps x 16 NB
+// channels x 32) go straight from global memory into LDS
+// (global_load_lds_dwordx4, no registers held), 80 bytes per pixel or
+// weight row (an odd multiple of 16 bytes: conflict-free fragment reads;
+// the fifth 16 bytes are filler); then the nine taps run from LDS, A and B
+// fragments read one tap ahead.  256 pixels share every weight row the
+// workgroup stages, and the k loop issues no global loads, so two
+// workgroups per CU overlap one's staging with the other's MFMAs.
+// ---------------------------------------------------------------------------
+#if defined(__HIP_DEVICE_COMPILE__)
+#define NN_AS1(p) ((const __attribute__((address_space(1))) void*)(p))
+#define NN_AS3(p) ((__attribute__((address_space(3))) void*)(p))
+#else
+#define NN_AS1(p) ((const void*)(p))
+#define NN_AS3(p) ((void*)(p))
+#endif
+constexpr int kCcR = 4, kCcTW = 64, kCcC = 32;
+constexpr int kCcTWp = kCcTW + 2;
+constexpr int kCcSlot = 5;                                   // 16-byte slots per pixel or weight row
+constexpr int kCcPix = (kCcR + 2) * kCcTWp;                  // halo pixels
+constexpr int kCcInSlots = (kCcPix * kCcSlot + 255) / 256 * 256;  // whole wave instructions (4 waves)
+template <int NB> constexpr int cc_w_slots() { return (9 * 16 * NB * kCcSlot + 255) / 256 * 256; }
+template <int NB> constexpr int cc_lds_bytes() { return (kCcInSlots + cc_w_slots<NB>()) * 16; }
+
+template <int NB>
+__global__ __launch_bounds__(256, 2) void k_conv3x3_cc(const u16* __restrict__ X, const u16* __restrict__ Wg,
+                                                       const float* __restrict__ bias, const u16* __restrict__ mask,
+                                                       u16* __restrict__ Y, int H, int W, int Cin, int Cout, int Kpad,
+                                                       int relu) {
+  constexpr int WSL = cc_w_slots<NB>();
+  static_assert(2 * cc_lds_bytes<NB>() <= 160 * 1024, "two workgroups per CU");
+  static_assert(16 * NB * kCcR * kCcTW * 2 <= cc_lds_bytes<NB>(), "output staging fits");
+  __shared__ __align__(16) char lds[cc_lds_bytes<NB>()];
+  char* lin = lds;                      // [pixel][5 slots]
+  char* lw = lds + kCcInSlots * 16;     // [tap][16 NB rows][5 slots]
+  const int tiles_x = W / kCcTW + (W % kCcTW ? 1 : 0);
+  const int ty = (int)blockIdx.x / tiles_x, tx = (int)blockIdx.x - ty * tiles_x;
+  const int n = blockIdx.z;
+  const int x0 = tx * kCcTW, y0 = ty * kCcR;
+  const int co0 = blockIdx.y * 16 * NB;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, kb = lane >> 4;
+  const u16* xn = X + (size_t)n * H * W * Cin;
+  float bv[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) bv[nb] = bias ? bias[co0 + nb * 16 + m] : 0.f;
+  // this lane's staging slots: wave instruction u fills slots
+  // 64 (4 u + wave) .. + 63 (a wave-uniform LDS base), slot = lane + that base
+  constexpr int NIN = kCcInSlots / 256, NWS = WSL / 256;
+  // A chunk holds channels c0 .. c0 + 31, or c0 .. c0 + 15 when only 16 are
+  // left (Cin % 32 == 16): then slots 2 and 3 of every pixel are filler and
+  // the same slots of every weight row are zeroed, so they add nothing.
+  int isrc[NIN];   // element offset of the slot's pixel in the image, or -1: outside (zero)
+  int iq[NIN];     // the slot's 16-byte part (4: filler)
+#pragma unroll
+  for (int u = 0; u < NIN; ++u) {
+    const int sl = 64 * (4 * u + wave) + lane;
+    const int pix = sl / kCcSlot, q = sl - pix * kCcSlot;
+    const int ly = pix / kCcTWp, lx = pix - ly * kCcTWp;
+    const int gy = y0 + ly - 1, gx = x0 + lx - 1;
+    const bool in_img = pix < kCcPix && gy >= 0 && gy < H && gx >= 0 && gx < W;
+    isrc[u] = in_img ? (gy * W + gx) * Cin : -1;
+    iq[u] = q;
+  }
+  int wsrc[NWS];   // element offset of the slot's weight row at k = tap Cin (spare slots: row 0)
+  int wq[NWS];     // the slot's 16-byte part (4: filler; spare slots 4)
+#pragma unroll
+  for (int u = 0; u < NWS; ++u) {
+    const int sl = 64 * (4 * u + wave) + lane;
+    const int row = sl / kCcSlot, q = sl - row * kCcSlot;
+    const int t = row / (16 * NB), co = row - t * 16 * NB;
+    const bool real = row < 9 * 16 * NB;
+    wsrc[u] = real ? (co0 + co) * Kpad + t * Cin : co0 * Kpad;
+    wq[u] = real ? q : 4;
+  }
+  f32x4 acc[4][NB];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[j][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // fragment byte offsets: A of group j at tap (0, 0), B of block nb at tap 0
+  const uint32_t aoff = (uint32_t)(((wave * kCcTWp + m) * kCcSlot + kb) * 16);
+  const uint32_t boff = (uint32_t)((m * kCcSlot + kb) * 16);
+  auto frag = [](const char* p) { return *reinterpret_cast<const bf16x8*>(p); };
+  auto ld = [&](int t, bf16x8 (&a)[4], bf16x8 (&b)[NB]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[j] = frag(lin + aoff + (((t / 3) * kCcTWp + (t % 3) + 16 * j) * kCcSlot) * 16);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) b[nb] = frag(lw + boff + ((t * 16 * NB + nb * 16) * kCcSlot) * 16);
+  };
+  auto mma = [&](const bf16x8 (&a)[4], const bf16x8 (&b)[NB]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j], b[nb], acc[j][nb], 0, 0, 0);
+  };
+  const int nchunk = (Cin + kCcC - 1) / kCcC;
+  bf16x8 a0[4], b0[NB], a1[4], b1[NB];
+  for (int c = 0; c < nchunk; ++c) {
+    const int c0 = kCcC * c;
+    const int qv = min(4, (Cin - c0) / 8);  // real 16-byte parts per pixel: 4, or 2 in a half chunk
+    // stage chunk c (out-of-image pixels load the image's first element, then
+    // are zeroed by the lane that staged them once its loads have landed;
+    // filler slots load part 0 of their pixel or row)
+#pragma unroll
+    for (int u = 0; u < NIN; ++u)
+      __builtin_amdgcn_global_load_lds(NN_AS1(xn + (isrc[u] >= 0 ? isrc[u] + c0 + 8 * (iq[u] < qv ? iq[u] : 0) : 0)),
+                                       NN_AS3(lin + 1024 * (4 * u + wave)), 16, 0, 0);
+#pragma unroll
+    for (int u = 0; u < NWS; ++u)
+      __builtin_amdgcn_global_load_lds(NN_AS1(Wg + wsrc[u] + c0 + 8 * (wq[u] < qv ? wq[u] : 0)),
+                                       NN_AS3(lw + 1024 * (4 * u + wave)), 16, 0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+    for (int u = 0; u < NIN; ++u)
+      if (isrc[u] < 0) *reinterpret_cast<uint4*>(lin + 1024 * (4 * u + wave) + 16 * lane) = make_uint4(0, 0, 0, 0);
+    if (qv < 4) {  // half chunk: zero the weight rows' parts 2 and 3
+#pragma unroll
+      for (int u = 0; u < NWS; ++u)
+        if (wq[u] >= qv && wq[u] < 4)
+          *reinterpret_cast<uint4*>(lw + 1024 * (4 * u + wave) + 16 * lane) = make_uint4(0, 0, 0, 0);
+    }
+    __syncthreads();
+    ld(0, a0, b0);
+    ld(1, a1, b1); mma(a0, b0);
+    ld(2, a0, b0); mma(a1, b1);
+    ld(3, a1, b1); mma(a0, b0);
+    ld(4, a0, b0); mma(a1, b1);
+    ld(5, a1, b1); mma(a0, b0);
+    ld(6, a0, b0); mma(a1, b1);
+    ld(7, a1, b1); mma(a0, b0);
+    ld(8, a0, b0); mma(a1, b1);
+    mma(a0, b0);
+    __syncthreads();  // the next chunk's staging overwrites these buffers
+  }
+  // epilogue: bias, ReLU, bf16, staged in LDS for 16-byte stores
+  constexpr int CW = 16 * NB;
+  u16* outs = reinterpret_cast<u16*>(lds);
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float v = acc[j][nb][i] + bv[nb];
+        if (relu) v = fmaxf(v, 0.f);
+        outs[(wave * kCcTW + 16 * j + 4 * kb + i) * CW + nb * 16 + m] = f2bf(v);
+      }
+  __syncthreads();
+  constexpr int CPO = CW / 8;
+  for (int i = threadIdx.x; i < kCcR * kCcTW * CPO; i += 256) {
+    const int pl = i / CPO, c = i - pl * CPO;
+    const int ly = pl / kCcTW, lx = pl - ly * kCcTW;
     const int gy = y0 + ly, gx = x0 + lx;
     if (gy < H && gx < W) {
       uint4 v = *reinterpret_cast<const uint4*>(outs + pl * CW + 8 * c);
@@ -1042,6 +1220,17 @@ void head_bwd_launch(const float* dout, const float* w, const u16* x, u16* dx, l
 // ---- layer launchers (arguments validated by the callers) ----
 constexpr size_t kTileLdsMax = 64 * 1024;
 
+// Smallest input channel count the channel-chunked kernel serves (below it
+// the LDS-tiled kernel does): 32 by default; HG_CONV_CC_MIN overrides it
+// for comparisons (a large value switches the chunked kernel off).
+int cc_min_cin() {
+  static const int v = [] {
+    const char* e = getenv("HG_CONV_CC_MIN");
+    return e ? atoi(e) : 32;
+  }();
+  return v;
+}
+
 // Tile shape of k_conv3x3_tile for this layer, largest first; false if none fits.
 bool tile_shape(int W, int Cin, int NB, int* R, int* TW, int* GW) {
   if (Cin % 8 || W % 16) return false;
@@ -1085,6 +1274,24 @@ void conv_launch(const u16* X, const u16* Wg, const float* bias, const u16* mask
   const int nb16 = Cout / 16;
   const int NB = nb16 % 4 == 0 ? 4 : nb16 % 3 == 0 ? 3 : nb16 % 2 == 0 ? 2 : 1;
   int R, TW, GW;
+  if (P / ((long)H * W) <= 65535 && Cin % 16 == 0 && Cin >= cc_min_cin() && W >= kCcTW &&
+      (long)H * W * Cin < (1L << 31)) {
+    // channel-chunked kernel, 4 x 64 pixel tiles (images on grid.z)
+    const long N = P / ((long)H * W);
+    const long tiles = (long)(H / kCcR + (H % kCcR ? 1 : 0)) * (W / kCcTW + (W % kCcTW ? 1 : 0));
+    const dim3 grid((unsigned)tiles, nb16 / NB, (unsigned)N);
+    const int Kp = kpad_of(9 * Cin);
+#define HG_CC(NBV) \
+  hipLaunchKernelGGL((k_conv3x3_cc<NBV>), grid, dim3(256), 0, st, X, Wg, bias, mask, Y, H, W, Cin, Cout, Kp, relu);
+    switch (NB) {
+      case 4: HG_CC(4) break;
+      case 3: HG_CC(3) break;
+      case 2: HG_CC(2) break;
+      default: HG_CC(1) break;
+    }
+#undef HG_CC
+    return;
+  }
   if (P / ((long)H * W) <= 65535 && tile_shape(W, Cin, NB, &R, &TW, &GW)) {  // images on grid.z
     const long N = P / ((long)H * W);
     const long tiles = (long)(H / R + (H % R ? 1 : 0)) * (W / TW + (W % TW ? 1 : 0));

@@ -77,6 +77,13 @@ CONV_CASES = [  # n, h, w, cin, cout, bias/relu, mask
     (1, 4, 32, 192, 64, True, True),    # 2 x 32 tiles
     (1, 3, 16, 128, 128, False, False),  # 4 x 16 tiles
     (1, 7, 80, 64, 64, True, False),
+    # channel-chunked kernel (Cin % 32 == 0, width >= 64): 4 x 64 tiles, every
+    # output-channel block count, several chunks, ragged tiles, masks
+    (1, 6, 64, 192, 64, True, True),
+    (2, 9, 130, 32, 48, False, False),
+    (1, 4, 64, 64, 16, True, False),
+    (1, 5, 96, 128, 32, True, True),
+    (1, 5, 72, 48, 16, True, True),     # a half chunk (16 channels) after a whole one
 ]
 
 
@@ -100,7 +107,8 @@ def test_conv3x3_forward(n, h, w, cin, cout, affine, masked):
 
 
 @pytest.mark.parametrize("n,h,w,cin,cout", [(2, 10, 12, 16, 32), (1, 6, 7, 48, 16), (2, 4, 8, 128, 64),
-                                            (2, 6, 64, 48, 16), (1, 5, 32, 192, 64)])
+                                            (2, 6, 64, 48, 16), (1, 5, 32, 192, 64), (1, 5, 64, 16, 64),
+                                            (1, 4, 128, 32, 96)])
 def test_conv3x3_data_gradient(n, h, w, cin, cout):
     say("conv3x3 data gradient", n, h, w, cin, cout)
     rng = np.random.default_rng(7 + cin)
