@@ -321,7 +321,7 @@ def other_workload(args):
         bytes_row = px * 17 * sub
         config = {"workload": "adaptive_ospr_binary_512x512_24sf", "grid": [n, n], "subframes": sub,
                   "slm_levels": 2, "target": "gaussian sum, 32 blobs, central window"}
-        kernel = "column pass of adaptive OSPR (one tile per workgroup, k_colq_ospr<512,8,COL_OSPR>)"
+        kernel = "column pass of adaptive OSPR (4-column tiles, 8 elements per thread, k_colq_ospr<512,4,COL_OSPR,8>)"
     elif wl == "ospr1024x32":
         n, B, sub = 1024, 32, 24
         tg = [torch.from_numpy(synth.gaussian_target(n, seed=3, batch_item=b)).to(dev) for b in range(B)]

@@ -136,6 +136,10 @@ Cfg get_cfg(int ny, int nx, int B) {
   auto it = g_tuned.find(std::make_tuple(ny, nx, batch_class(B)));
   return it != g_tuned.end() ? it->second : default_cfg(ny, nx, B);
 }
+bool has_tuned_cfg(int ny, int nx, int B) {
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  return g_tuned.count(std::make_tuple(ny, nx, batch_class(B))) != 0;
+}
 
 // ---------------------------------------------------------------------------
 // workspace layout of one size class (B problems of ny x nx)
@@ -143,7 +147,7 @@ Cfg get_cfg(int ny, int nx, int B) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t status, desc, field, tprep, wbuf, accum, twx, twy, chirp, part, invm, total;
+  size_t status, desc, field, tprep, wbuf, accum, twx, twy, twy8, chirp, part, invm, total;
   int max_nblk, slots;
 };
 
@@ -162,6 +166,7 @@ Layout make_layout(int op, int ny, int nx, int B, int kmax) {
   L.accum = take(op == HG_OP_OSPR ? px * sizeof(float) : 0);
   L.twx = take(nx * sizeof(float2));
   L.twy = take(ny * sizeof(float2));
+  L.twy8 = take(op == HG_OP_OSPR ? ny * sizeof(float2) : 0);  // column twiddles of the 8-element plan
   L.chirp = take((size_t)B * (nx + ny) * sizeof(float2));
   L.part = take((size_t)B * L.slots * L.max_nblk * 4 * sizeof(double));
   L.invm = take((size_t)B * sizeof(float));
@@ -223,6 +228,9 @@ void upload_descs(Desc* dst, const std::vector<Desc>& ds, hipStream_t st, int* c
 
 void launch_twiddles(float2* tw, int n, hipStream_t st) {
   with_size(n, [&](auto nc) { launch_twiddles_t<decltype(nc)::value>(tw, st); });
+}
+void launch_twiddles8(float2* tw, int n, hipStream_t st) {
+  with_size(n, [&](auto nc) { launch_twiddles8_t<decltype(nc)::value>(tw, st); });
 }
 
 void launch_chirps(float2* chirp, int ny, int nx, const std::vector<double>& rates, hipStream_t st) {
@@ -300,6 +308,8 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
   // 16-bit planes: the tile kernel's shape (256 threads: C = 4096 / ny) and
   // the default row grouping, the instantiations that exist for them
   const Cfg cfg = f16 ? Cfg{4096 / ny, default_rpb(nx)} : get_cfg(ny, nx, B);
+  if (!col_ok(ny, cfg.C) || !rpb_ok(nx, cfg.RPB))  // a pass with no compiled kernel would launch nothing
+    return fail(HG_ERR_INVALID_ARG, "no kernel for %d-column tiles / %d rows per group at %dx%d", cfg.C, cfg.RPB, ny, nx);
   Batch bt = make_batch(ws, L, ny, nx, cfg.C);
   if (f16) {
     bt.f16 = 1;
@@ -358,12 +368,27 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
 hg_status run_ospr_class(int ny, int nx, const std::vector<Desc>& ds, int subframes, int adaptive, void* ws,
                          const Layout& L, hipStream_t st, int* status, bool first) {
   const int B = (int)ds.size();
-  const Cfg cfg = get_cfg(ny, nx, B);
+  Cfg cfg = get_cfg(ny, nx, B);
+  // fewer than 8 problems of 512 rows: 4-column tiles (the default unless a
+  // configuration was tuned or set), which run with 8 elements per thread in
+  // the column passes: twice the workgroups of the default tiles and half
+  // the per-thread work
+  if (ny == 512 && batch_class(B) == 0 && !has_tuned_cfg(ny, nx, B)) {
+    cfg.C = 4;
+    if (nx == 512) cfg.RPB = 4;  // 512-wide rows: 8 elements per thread there too, one wave per row
+  }
+  const bool e8 = ny == 512 && batch_class(B) == 0 && cfg.C == 4 && column_kernel() == CK_TILE;
+  if (!col_ok(ny, cfg.C) || !rpb_ok(nx, cfg.RPB))  // a pass with no compiled kernel would launch nothing
+    return fail(HG_ERR_INVALID_ARG, "no kernel for %d-column tiles / %d rows per group at %dx%d", cfg.C, cfg.RPB, ny, nx);
   Batch bt = make_batch(ws, L, ny, nx, cfg.C);
   bt.status = status;
   upload_descs(const_cast<Desc*>(bt.desc), ds, st, first ? status : nullptr);
   launch_twiddles(const_cast<float2*>(bt.tw_x), nx, st);
   if (ny != nx) launch_twiddles(const_cast<float2*>(bt.tw_y), ny, st);
+  if (e8) {
+    bt.tw_y8 = at<float2>(ws, L.twy8);
+    launch_twiddles8(const_cast<float2*>(bt.tw_y8), ny, st);
+  }
   launch_setup(bt, cfg.C, B, 0, st);
   launch_col(bt, cfg.C, B, COL_OSPR_FIRST, 1, adaptive, nullptr, nullptr, st);
   for (int n = 1; n <= subframes; ++n) {

@@ -66,6 +66,7 @@ struct Batch {
                         // invm of every problem for column pass k + 1 from the weight sums of slot k
   float s16_row, inv16_row;  // 16-bit planes: the row pass stores x s16_row, the column pass loads x inv16_row
   float s16_col, inv16_col;  // the column pass stores x s16_col, the row pass loads x inv16_col
+  const float2* tw_y8;  // OSPR columns of 512 with 8 elements per thread: staged twiddles of that plan (else null)
 };
 
 // 16-bit field storage: one element as two IEEE binary16 values (real in the
@@ -275,12 +276,12 @@ __device__ __forceinline__ void twiddle_entry(float2* tw, int m) {
   }
 }
 
-template <int N>
+template <int N, int E = kE>
 __global__ void k_twiddles(float2* tw) {
-  constexpr int total = TwLayout<N, kE>::total();
+  constexpr int total = TwLayout<N, E>::total();
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= total) return;
-  twiddle_entry<N, 1>(tw, m);
+  twiddle_entry<N, 1, E>(tw, m);
 }
 
 // cx[x] = exp(i pi p^2 (x - nx/2)^2 / (lambda z)) (-1)^x, then cy likewise.
@@ -511,11 +512,13 @@ template <int NX, int RPB> constexpr int row_min_waves() { return ((NX == 2048 |
 
 // F16: the field plane holds 16-bit elements (Batch::f16); ROW_INIT and
 // ROW_ITER only.
-template <int NX, int RPB, bool FRESNEL, int MODE, int LK, bool F16 = false>
-__global__ __launch_bounds__(RPB * (NX / kE), (row_min_waves<NX, RPB>())) void k_row(Batch bt, int arg,
+// EE: elements per thread (16; 8 for the small-batch OSPR rows of 512, whose
+// twiddles are then that plan's table).
+template <int NX, int RPB, bool FRESNEL, int MODE, int LK, bool F16 = false, int EE = kE>
+__global__ __launch_bounds__(RPB * (NX / EE), (row_min_waves<NX, RPB>())) void k_row(Batch bt, int arg,
                                                                                      const float2* pin, float2* pout) {
   static_assert(!F16 || MODE == ROW_INIT || MODE == ROW_ITER, "16-bit planes in GS / weighted GS only");
-  constexpr int E = kE;
+  constexpr int E = EE;
   using P = Plan<NX, E>;
   constexpr int T = P::T;
   constexpr bool XCH = P::ns > 1;

@@ -66,6 +66,7 @@ template <int N> void launch_col_prep_t(int C, const Batch& bt, int B, int mode,
 template <int N> void launch_row_t(int RPB, bool fresnel, int lk, const Batch& bt, int B, int mode, int arg,
                                    const float2* pin, float2* pout, hipStream_t st);
 template <int N> void launch_twiddles_t(float2* tw, hipStream_t st);
+template <int N> void launch_twiddles8_t(float2* tw, hipStream_t st);  // the 8-element plan (512 only)
 template <int N> constexpr int twiddle_count() { return TwLayout<N, kE>::total(); }
 
 }  // namespace hg
