@@ -1585,7 +1585,20 @@ void k_colq_ospr(Batch bt, int n, int adaptive, int nprob) {
       for (int j = 0; j < E; ++j) tv[j] = 0.f;
     }
   };
-  if constexpr (FIRST) load_target();
+  // 8 elements per thread (small batches): target and A_{n-2} are loaded
+  // with the field, their latency hidden by its; with 16, after the forward
+  // transform, so fewer registers are live across it.  A_{n-2} is zero for
+  // n = 2, where the plane holds no accumulation yet (loaded anyway and
+  // discarded by a select: no branch per element).
+  constexpr bool EARLY = E <= 8;
+  if constexpr (FIRST || EARLY) load_target();
+  if constexpr (!FIRST && EARLY) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const float x = *at_bytes(acc, b0 + bstep * j);
+      av[j] = n == 2 ? 0.f : x;
+    }
+  }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   const auto tw = launder(to_global(bt.tw_y));
@@ -1595,14 +1608,13 @@ void k_colq_ospr(Batch bt, int n, int adaptive, int nprob) {
 #pragma unroll
     for (int j = 0; j < E; ++j) v[j] = FA[colp_sidx<C>(t + T * j, c)];
     fft_stage<NY, E, -1, 0>(v, t, tw, ex);
-    // target and A_{n-2} after the transform: fewer registers live across it
-    load_target();
-    // A_{n-2}: zero for n = 2, where the plane holds no accumulation yet
-    // (loaded anyway and discarded by a select: no branch per element)
+    if constexpr (!EARLY) {
+      load_target();
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const float x = *at_bytes(acc, b0 + bstep * j);
-      av[j] = n == 2 ? 0.f : x;
+      for (int j = 0; j < E; ++j) {
+        const float x = *at_bytes(acc, b0 + bstep * j);
+        av[j] = n == 2 ? 0.f : x;
+      }
     }
     const float inv_prev = 1.0f / (float)(n - 1);
     float s_ta = 0.f, s_aa = 0.f, s_tt = 0.f;
