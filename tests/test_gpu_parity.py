@@ -363,11 +363,22 @@ def test_multi_iteration_call_equals_chained_steps():
 # ---------------------------------------------------------------------------
 # OSPR, lock-step on the accumulated intensity
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("n,subframes,adaptive", [(128, 8, False), (512, 24, True)])
-def test_ospr_lockstep(n, subframes, adaptive):
-    say("ospr", n, subframes, adaptive)
-    T_raw = synth.gaussian_target(n, seed=3)
-    out = hg.hg_ospr(dev(T_raw), subframes, adaptive, seed=3, want_accum=True)
+@pytest.mark.parametrize("ny,nx,subframes,adaptive,cfg", [
+    (128, 128, 8, False, None),
+    (512, 512, 24, True, None),     # small batch at 512: 8 elements per thread in both passes
+    (512, 1024, 4, True, None),     # 8-element columns, 16-element rows
+    (512, 512, 4, True, (8, 8)),    # the 16-element tiles, set explicitly
+])
+def test_ospr_lockstep(ny, nx, subframes, adaptive, cfg):
+    say("ospr", ny, nx, subframes, adaptive, cfg)
+    T_raw = synth.gaussian_target(nx, seed=3, ny=ny)
+    if cfg is not None:
+        hg.hg_set_launch_config(ny, nx, 1, *cfg)
+    try:
+        out = hg.hg_ospr(dev(T_raw), subframes, adaptive, seed=3, want_accum=True)
+    finally:
+        if cfg is not None:
+            hg.hg_set_launch_config(ny, nx, 1, 0, 0)
     lev = host(out["levels"]).astype(np.int64)
     nm = host(out["nmse"])
     T = hologram.prepare_target(T_raw, 2)
