@@ -199,10 +199,32 @@ __host__ __device__ constexpr bool col_pingpong(int NY, int C) { return false &&
 // ---------------------------------------------------------------------------
 // deterministic block reductions into FP64
 // ---------------------------------------------------------------------------
+// One DPP move of a double (two 32-bit halves); lanes the control does not
+// write, or whose source is out of range, read +0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the wave's 64 lanes in a fixed order, returned to every lane:
+// within quads (quad_perm 1,0,3,2 and 2,3,0,1), within rows of 16 (half-row
+// and row mirrors), then rows 0+1 and 2+3 (row_bcast:15 into rows 1 and 3)
+// and the two halves (row_bcast:31 into rows 2 and 3); lane 63 then holds
+// the total.  Cross-lane moves by DPP, no LDS traffic.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_f64<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E>(v);        // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141>(v);       // row_half_mirror
+  v += dpp_f64<0x140>(v);       // row_mirror
+  v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15, rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31, rows 2 and 3
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
 // Sums of four per-thread float values over the block, in a fixed order;
