@@ -561,24 +561,179 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const u16* __restrict__ X
   }
 }
 
-// dw[co][k] (OHWI) = sum over the pixel blocks of part, in block order.
+// ---------------------------------------------------------------------------
+// Weight gradient for Cin % 16 == 0 and Cout % 16 == 0 with the pixels on
+// the MFMA's reduction axis and the operands transposed through LDS:
+// part[pb][co][tap Cin + ci] = sum over pixel block pb of dY[p][co]
+// X[p + tap offset][ci] (zero outside the image), i.e. D = dY^T X with
+// M = 16 output channels, N = 16 input channels, K = 32 pixels.  A
+// workgroup owns 16 NB output channels and one chunk of 32 input channels
+// (16 in a last half chunk), and walks the 2 x 64 pixel tiles of its block:
+// - the tile's dY goes to LDS as [co][pixel] (A fragments: 8 consecutive
+//   pixels of one channel), its input halo as three copies [kx][ci][row][p]
+//   shifted by the tap column kx, so that every B fragment (8 consecutive
+//   pixels of one channel) is a 16-byte aligned read;
+// - wave w takes the taps w, w + 4, w + 8 (< 9) for every output-channel
+//   block: per 32-pixel step, NB A fragments and one B fragment per tap and
+//   channel block, NB MFMAs per B;
+// - wave 0 also sums dY over the pixels for the bias gradient.
+// Channel strides are odd multiples of 16 bytes (conflict-free fragment
+// reads).  The partials are reduced over pixel blocks, in order, by
+// k_wgrad_reduce.
+// ---------------------------------------------------------------------------
+constexpr int kWgXP = 64;                 // pixels of a shifted halo row copy
+constexpr int kWgCIS = 4 * kWgXP + 8;     // elements per input channel of a copy (4 halo rows)
+constexpr int kWgDS = 2 * 64 + 8;         // elements per output channel of the dY tile
+
+template <int NB>
+__global__ __launch_bounds__(256, 2) void k_wgrad_cc(const u16* __restrict__ X, const u16* __restrict__ dY,
+                                                     float* __restrict__ part, float* __restrict__ bpart, int H,
+                                                     int W, int Cin, int Cout, int Kpad, int tpb, int ntiles) {
+  __shared__ __align__(16) u16 xs[3 * 32 * kWgCIS];
+  __shared__ __align__(16) u16 dys[16 * NB * kWgDS];
+  const int tiles_x = (W + 63) / 64, tiles_img = tiles_x * ((H + 1) / 2);
+  const int co0 = blockIdx.y * 16 * NB, c0 = blockIdx.z * 32;
+  const int ncib = min(2, (Cin - c0) / 16);  // 16-channel blocks in this chunk
+  const int qn = 2 * ncib;                   // 16-byte parts of a pixel's chunk
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, kb = lane >> 4;
+  f32x4 acc[3][2][NB];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[i][cb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) bsum[nb] = 0.f;
+  const int t_end = min((int)blockIdx.x * tpb + tpb, ntiles);
+  for (int tl = blockIdx.x * tpb; tl < t_end; ++tl) {
+    const int n = tl / tiles_img, rem = tl - n * tiles_img;
+    const int ty = rem / tiles_x, tx = rem - ty * tiles_x;
+    const int y0 = 2 * ty, x0 = 64 * tx;
+    __syncthreads();  // the previous tile's fragment reads are done
+    // input halo: rows y0 - 1 .. y0 + 2, columns x0 - 1 .. x0 + 64
+    for (int i = threadIdx.x; i < 4 * 66 * qn; i += 256) {
+      const int q = i % qn, hp = i / qn;
+      const int hy = hp / 66, hx = hp - hy * 66;
+      const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+        v = *reinterpret_cast<const uint4*>(X + (((size_t)n * H + gy) * W + gx) * Cin + c0 + 8 * q);
+      const u16* e = reinterpret_cast<const u16*>(&v);
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx) {
+        const int p = hx - kx;
+        if (p >= 0 && p < kWgXP) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) xs[(kx * 32 + 8 * q + k) * kWgCIS + hy * kWgXP + p] = e[k];
+        }
+      }
+    }
+    // dY of the tile's 2 x 64 pixels, transposed to [co][pixel]
+    for (int i = threadIdx.x; i < 128 * 2 * NB; i += 256) {
+      const int q = i % (2 * NB), pp = i / (2 * NB);
+      const int r = pp >> 6, c = pp & 63;
+      const int gy = y0 + r, gx = x0 + c;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (gy < H && gx < W)
+        v = *reinterpret_cast<const uint4*>(dY + (((size_t)n * H + gy) * W + gx) * Cout + co0 + 8 * q);
+      const u16* e = reinterpret_cast<const u16*>(&v);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) dys[(8 * q + k) * kWgDS + pp] = e[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {  // 32-pixel steps: row ks / 2, columns 32 (ks % 2) ..
+      const int r = ks >> 1, cc = (ks & 1) * 32;
+      bf16x8 a[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        a[nb] = *reinterpret_cast<const bf16x8*>(dys + (nb * 16 + m) * kWgDS + r * 64 + cc + 8 * kb);
+      if (wave == 0) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const u16* e = reinterpret_cast<const u16*>(&a[nb]);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) bsum[nb] += bf2f(e[k]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int t = wave + 4 * i;
+        if (t < 9) {  // wave-uniform
+          const int ky = t / 3, kx = t - 3 * ky;
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) {
+            if (cb < ncib) {  // uniform
+              const bf16x8 b = *reinterpret_cast<const bf16x8*>(
+                  xs + (kx * 32 + cb * 16 + m) * kWgCIS + (r + ky) * kWgXP + cc + 8 * kb);
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb)
+                acc[i][cb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[nb], b, acc[i][cb][nb], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+  }
+  // partials: lane (m, kb) holds input channel m and output channels 4 kb .. + 3
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int t = wave + 4 * i;
+    if (t >= 9) continue;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      if (cb >= ncib) continue;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int co = co0 + nb * 16 + 4 * kb + e;
+          part[((size_t)blockIdx.x * Cout + co) * Kpad + t * Cin + c0 + cb * 16 + m] = acc[i][cb][nb][e];
+        }
+    }
+  }
+  if (bpart && blockIdx.z == 0 && wave == 0) {  // lanes m, m + 16, m + 32, m + 48 hold channel m's pixels
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      float v = bsum[nb];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (lane < 16) bpart[(size_t)blockIdx.x * Cout + co0 + nb * 16 + m] = v;
+    }
+  }
+}
+
+// dw[co][k] (OHWI) = sum over the pixel blocks of part, in a fixed order.
+// Sum of n values at p[0], p[stride], ... in a fixed order: eight
+// interleaved running sums (b mod 8), so eight loads are in flight, added
+// pairwise at the end.
+__device__ __forceinline__ float sum_strided(const float* __restrict__ p, int n, size_t stride) {
+  float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int b = 0;
+  for (; b + 8 <= n; b += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += p[(size_t)(b + u) * stride];
+  }
+  for (int u = 0; b < n; ++b, ++u) a[u] += p[(size_t)b * stride];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 __global__ void k_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dw, int npb, int Cout, int Kpad,
                                int K) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Cout * K) return;
   const int co = i / K, k = i - co * K;
-  float s = 0.f;
-  for (int b = 0; b < npb; ++b) s += part[((size_t)b * Cout + co) * Kpad + k];
-  dw[i] = s;
+  dw[i] = sum_strided(part + (size_t)co * Kpad + k, npb, (size_t)Cout * Kpad);
 }
 
-// out[j] = sum_b part[b][j], b in order
+// out[j] = sum_b part[b][j] in sum_strided's fixed order
 __global__ void k_sum_parts(const float* __restrict__ part, float* __restrict__ out, int nparts, int ncol) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= ncol) return;
-  float s = 0.f;
-  for (int b = 0; b < nparts; ++b) s += part[(size_t)b * ncol + j];
-  out[j] = s;
+  out[j] = sum_strided(part + j, nparts, (size_t)ncol);
 }
 
 // ---------------------------------------------------------------------------
@@ -1223,6 +1378,16 @@ constexpr size_t kTileLdsMax = 64 * 1024;
 // Smallest input channel count the channel-chunked kernel serves (below it
 // the LDS-tiled kernel does): 32 by default; HG_CONV_CC_MIN overrides it
 // for comparisons (a large value switches the chunked kernel off).
+// Smallest input channel count the MFMA weight-gradient kernel serves (1:
+// every Cin % 16 == 0 layer); HG_WGRAD_CC_MIN overrides it for comparisons.
+int wgrad_cc_min_cin() {
+  static const int v = [] {
+    const char* e = getenv("HG_WGRAD_CC_MIN");
+    return e ? atoi(e) : 1;
+  }();
+  return v;
+}
+
 int cc_min_cin() {
   static const int v = [] {
     const char* e = getenv("HG_CONV_CC_MIN");
@@ -1342,21 +1507,64 @@ WgradPlan wgrad_plan(long P, int Cin, int Cout) {
   pb = std::max(256L, (pb + 31) / 32 * 32);
   return {pb, (int)((P + pb - 1) / pb)};
 }
+// The MFMA weight-gradient kernel (k_wgrad_cc): whether it serves a layer,
+// its output-channel blocks, and a workgroup count of about 512 (two per CU
+// resident) as blocks of consecutive 2 x 64 pixel tiles; more blocks make
+// the partials' reduction cost more than they save.
+constexpr long kWgTarget = 512;
+bool wgrad_cc_ok(long P, int Cin, int Cout) {
+  return Cin % 16 == 0 && Cout % 16 == 0 && Cin >= wgrad_cc_min_cin() && P * (long)std::max(Cin, Cout) < (1L << 31);
+}
+int wgrad_cc_nb(int Cout) {
+  const int nb16 = Cout / 16;
+  return nb16 % 4 == 0 ? 4 : nb16 % 2 == 0 ? 2 : 1;
+}
+long wgrad_cc_max_blocks(int Cin, int Cout) {
+  const long gyz = (long)(Cout / 16 / wgrad_cc_nb(Cout)) * ((Cin + 31) / 32);
+  return std::max(1L, kWgTarget / gyz);
+}
 size_t wgrad_ws_bytes(long P, int Cin, int Cout) {
   const WgradPlan w = wgrad_plan(P, Cin, Cout);
-  return al256((size_t)w.npb * Cout * kpad_of(9 * Cin) * sizeof(float)) + al256((size_t)w.npb * Cout * sizeof(float));
+  long npb = w.npb;
+  if (wgrad_cc_ok(P, Cin, Cout)) npb = std::max(npb, wgrad_cc_max_blocks(Cin, Cout));
+  return al256((size_t)npb * Cout * kpad_of(9 * Cin) * sizeof(float)) + al256((size_t)npb * Cout * sizeof(float));
 }
 void wgrad_launch(const u16* X, const u16* dY, float* dw, float* db, long P, int H, int W, int Cin, int Cout,
                   char* ws, hipStream_t st) {
   const WgradPlan wp = wgrad_plan(P, Cin, Cout);
   const int Kp = kpad_of(9 * Cin);
+  const bool cc = wgrad_cc_ok(P, Cin, Cout);
+  // partial slots of the workspace (as sized by wgrad_ws_bytes)
+  const long slots = cc ? std::max((long)wp.npb, wgrad_cc_max_blocks(Cin, Cout)) : wp.npb;
   float* part = reinterpret_cast<float*>(ws);
-  float* bpart = db ? reinterpret_cast<float*>(ws + al256((size_t)wp.npb * Cout * Kp * sizeof(float))) : nullptr;
-  hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(wp.npb, Cout / 16, (Kp + 63) / 64), dim3(256), 0, st, X, dY, part, bpart,
-                     P, H, W, Cin, Cout, Kp, wp.pb_len);
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk((long)Cout * 9 * Cin, 256)), dim3(256), 0, st, part, dw, wp.npb, Cout,
+  float* bpart = db ? reinterpret_cast<float*>(ws + al256((size_t)slots * Cout * Kp * sizeof(float))) : nullptr;
+  int npb = wp.npb;
+  const long N = P / ((long)H * W);
+  if (cc) {
+    // MFMA over pixel tiles (k_wgrad_cc): blocks of consecutive 2 x 64
+    // pixel tiles, at most wgrad_cc_max_blocks of them
+    const int nb16 = Cout / 16, NB = wgrad_cc_nb(Cout);
+    const long ntiles = N * ((H + 1) / 2) * ((W + 63) / 64);
+    const long want = std::min(ntiles, wgrad_cc_max_blocks(Cin, Cout));
+    const long tpb = (ntiles + want - 1) / want;
+    npb = (int)((ntiles + tpb - 1) / tpb);
+    const dim3 grid((unsigned)npb, nb16 / NB, (Cin + 31) / 32);
+#define HG_WG(NBV)                                                                                                  \
+  hipLaunchKernelGGL((k_wgrad_cc<NBV>), grid, dim3(256), 0, st, X, dY, part, bpart, H, W, Cin, Cout, Kp, (int)tpb, \
+                     (int)ntiles);
+    switch (NB) {
+      case 4: HG_WG(4) break;
+      case 2: HG_WG(2) break;
+      default: HG_WG(1) break;
+    }
+#undef HG_WG
+  } else {
+    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(wp.npb, Cout / 16, (Kp + 63) / 64), dim3(256), 0, st, X, dY, part,
+                       bpart, P, H, W, Cin, Cout, Kp, wp.pb_len);
+  }
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk((long)Cout * 9 * Cin, 256)), dim3(256), 0, st, part, dw, npb, Cout,
                      Kp, 9 * Cin);
-  if (db) hipLaunchKernelGGL(k_sum_parts, dim3(nblk(Cout, 256)), dim3(256), 0, st, bpart, db, wp.npb, Cout);
+  if (db) hipLaunchKernelGGL(k_sum_parts, dim3(nblk(Cout, 256)), dim3(256), 0, st, bpart, db, npb, Cout);
 }
 
 constexpr int kLossParts = 64;

@@ -122,7 +122,9 @@ def test_conv3x3_data_gradient(n, h, w, cin, cout):
 
 
 @pytest.mark.parametrize("n,h,w,cin,cout", [(2, 16, 24, 16, 16), (1, 7, 9, 1, 16), (2, 12, 20, 48, 48),
-                                            (1, 8, 8, 128, 128), (4, 64, 64, 16, 32)])
+                                            (1, 8, 8, 128, 128), (4, 64, 64, 16, 32),
+                                            # odd heights, partial 64-wide tiles, several images
+                                            (3, 7, 70, 32, 64), (2, 9, 130, 64, 16)])
 def test_conv3x3_weight_gradient(n, h, w, cin, cout):
     say("conv3x3 weight gradient", n, h, w, cin, cout)
     rng = np.random.default_rng(11 + cout)
