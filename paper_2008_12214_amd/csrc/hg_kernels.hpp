@@ -1728,12 +1728,25 @@ static __global__ void k_finish(Batch bt, int count, int ospr) {
   if (b >= count) return;
   const Desc& d = bt.desc[b];
   if (!d.nmse_out || k >= d.iters + (ospr ? 0 : 1)) return;
-  double sta = 0.0, saa = 0.0, stt = 0.0;
-  for (int i = 0; i < bt.nblk; ++i) {
-    const double* pp = part_ptr(bt, b, k, i);
-    sta += pp[0]; saa += pp[1]; stt += pp[2];
+  // four interleaved running sums (tile mod 4), added pairwise at the end:
+  // a fixed order with four records' loads in flight
+  double a[4][3] = {};
+  int i = 0;
+  for (; i + 4 <= bt.nblk; i += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double* pp = part_ptr(bt, b, k, i + u);
+      a[u][0] += pp[0]; a[u][1] += pp[1]; a[u][2] += pp[2];
+    }
   }
-  d.nmse_out[k] = nmse_from_sums(sta, saa, stt, bt.status);
+  for (int u = 0; i < bt.nblk; ++i, ++u) {
+    const double* pp = part_ptr(bt, b, k, i);
+    a[u][0] += pp[0]; a[u][1] += pp[1]; a[u][2] += pp[2];
+  }
+  double sum[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) sum[c] = (a[0][c] + a[1][c]) + (a[2][c] + a[3][c]);
+  d.nmse_out[k] = nmse_from_sums(sum[0], sum[1], sum[2], bt.status);
 }
 
 }  // namespace hg
