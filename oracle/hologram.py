@@ -21,6 +21,16 @@ Readings where the paper is silent (each is restated in the design notes):
   * LT: at iteration i the amplitude is constrained inside the centred
     square of radius r0 + (i-1) dr pixels and left free (R' = R) outside;
     nmse is still taken over the whole plane.
+  * Region of interest (Background section: many applications care about
+    part of the replay field only, and restricting the error metric to it
+    adds freedom; Algorithms section: amplitude freedom where the replay is
+    not controlled).  A GS problem may carry a mask M of controlled pixels.
+    The target outside M is ignored: T <- prepare(T_raw * M).  The
+    controlled region is M, or M united with its mirror image for binary
+    phase and amplitude SLMs, whose replay is centro-symmetric (that is also
+    where the symmetrised target can be nonzero).  Inside the region
+    R' = T R/|R|; outside R' = R; the NMSE counts the region only.  Weighted
+    GS and LT do not take a region.
   * Weighted GS (the paper names weighting only): a leaky log-domain
     integrator of the amplitude error,
       w_k = clamp(w_{k-1} * ratio / m_{k-1}, 1e-6, 1e6) ** GAMMA,
@@ -177,12 +187,15 @@ def _phase_of(R):
     return np.where(A > 0, R / np.where(A > 0, A, 1.0), 1.0 + 0j), A
 
 
-def fienup_error(T, A, exclude=None):
+def fienup_error(T, A, exclude=None, region=None):
     """Unscaled replay error sum (|R| - T)^2, the quantity GS never increases
-    (exclude: a pixel left free, e.g. an amplitude SLM's zero order)."""
+    (exclude: a pixel left free, e.g. an amplitude SLM's zero order; region:
+    the controlled pixels, the others being free)."""
     d = (np.asarray(A, dtype=np.float64) - np.asarray(T, dtype=np.float64)) ** 2
     if exclude is not None:
         d[exclude] = 0.0
+    if region is not None:
+        d[~region] = 0.0
     return float(np.sum(d))
 
 
@@ -202,8 +215,16 @@ def lt_window(ny, nx, r):
     return (v <= r) & (u <= r)
 
 
+def roi_region(roi, L, amplitude=False):
+    """Controlled replay pixels of a region-of-interest mask: M, or M with its
+    mirror image for binary phase and amplitude SLMs."""
+    M = np.asarray(roi) != 0
+    return M | mirror(M) if (L == 2 or amplitude) else M
+
+
 def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
-       weighted=False, weights=None, optics=None, batch_item=0, lt=None, amplitude=False, field16=False):
+       weighted=False, weights=None, optics=None, batch_item=0, lt=None, amplitude=False, field16=False,
+       roi=None):
     """Gerchberg-Saxton / weighted GS / Liu-Taghizadeh.  Returns a dict of final state.
 
     optics = (wavelength_m, pitch_m, z_m) selects a Fresnel hologram.
@@ -213,12 +234,23 @@ def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
     amplitude selects an L-level amplitude SLM (GS or weighted GS).
     field16 holds the field as 16-bit values between transform halves
     (forward16 / backward16).
+    roi: optional [ny][nx] mask of controlled replay pixels (plain GS only;
+    see the region-of-interest reading above).
     Keys: field (f_K), levels (k_K or None), g (the last field before
     projection), replay (R_K), nmse (K+1), fienup (K+1), weights (w_K),
     m (mean of w_K on Omega), target (prepared T).
     """
     if amplitude and (L < 2 or lt is not None):
         raise ValueError("an amplitude SLM has L >= 2 levels and runs GS or weighted GS")
+    region = None
+    if roi is not None:
+        if lt is not None or weighted:
+            raise ValueError("a region of interest runs with plain GS")
+        M = np.asarray(roi) != 0
+        if M.shape != np.shape(T_raw):
+            raise ValueError("roi and target differ in shape")
+        T_raw = np.where(M, np.asarray(T_raw, dtype=np.float64), 0.0)
+        region = roi_region(M, L, amplitude)
     T = prepare_target(T_raw, L, amplitude)
     ny, nx = T.shape
     dc = zero_order(ny, nx) if amplitude else None
@@ -239,19 +271,20 @@ def gs(T_raw, iters, L, seed=0, init_levels=None, init_field=None,
     if lt is not None and weighted:
         raise ValueError("Liu-Taghizadeh is a GS variant: weighted=False")
     for it in range(iters):
-        st = _iterate(T, L, f, Q, weighted, w, m, None if lt is None else lt[0] + it * lt[1], amplitude, field16)
-        nm.append(_m.nmse(T, st["A"], dc))
-        fe.append(fienup_error(T, st["A"], dc))
+        st = _iterate(T, L, f, Q, weighted, w, m, None if lt is None else lt[0] + it * lt[1], amplitude, field16,
+                      region)
+        nm.append(_m.nmse(T, st["A"], dc, region))
+        fe.append(fienup_error(T, st["A"], dc, region))
         g, f, levels = st["g"], st["field"], st["levels"]
         if weighted:
             w = st["weights"]
             m = float(np.mean(w[omega])) if np.any(omega) else 1.0
     R = forward16(f, Q) if field16 else forward(f, Q)
     A = np.abs(R)
-    nm.append(_m.nmse(T, A, dc))
-    fe.append(fienup_error(T, A, dc))
+    nm.append(_m.nmse(T, A, dc, region))
+    fe.append(fienup_error(T, A, dc, region))
     return dict(field=f, levels=levels, g=g, replay=R, nmse=np.array(nm),
-                fienup=np.array(fe), weights=w, m=m, target=T)
+                fienup=np.array(fe), weights=w, m=m, target=T, region=region)
 
 
 def ospr_target(T, A_prev, n, adaptive):
@@ -313,12 +346,13 @@ def gs_step(T, L, f_prev, weighted=False, w_prev=None, optics=None, lt_r=None, n
                 nmse_next=_m.nmse(T, np.abs(fwd(st["field"], Q)), dc) if next_nmse else None)
 
 
-def _iterate(T, L, f, Q, weighted, w, m, lt_r, amplitude=False, field16=False):
+def _iterate(T, L, f, Q, weighted, w, m, lt_r, amplitude=False, field16=False, region=None):
     """The body of one iteration (Iterative Fourier Transform Algorithms
     section): R = forward(f); replay constraint (GS: R' = T R/|R|, R = 0
     gives T; weighted GS: the weight update, then R' = w T R/|R|;
     Liu-Taghizadeh: R' = T R/|R| inside the square of radius lt_r, R' = R
-    outside; an amplitude SLM keeps R' = R at the zero order);
+    outside; a region of interest likewise keeps R' = R outside its region;
+    an amplitude SLM keeps R' = R at the zero order);
     g = backward(R'); f_next = P_L(g) (phase) or the nearest transmission
     (amplitude).  m is the lagged mean m_{k-1} of the weights over Omega."""
     ny, nx = T.shape
@@ -332,6 +366,8 @@ def _iterate(T, L, f, Q, weighted, w, m, lt_r, amplitude=False, field16=False):
         Rp = w * T * ph
     else:
         Rp = T * ph
+    if region is not None:
+        Rp = np.where(region, Rp, R)
     if amplitude:
         dc = zero_order(ny, nx)
         Rp[dc] = R[dc]

@@ -15,6 +15,9 @@ normalised by the target energy,
 
 over the whole replay plane, with s = sum T A / sum A^2.  For an
 amplitude-modulating SLM the zero-order pixel is left out (see hologram).
+Background section: many applications care about part of the replay field
+only, and the error metric may then count that region alone; with a region
+R the sums run over R (T and A taken as zero elsewhere).
 """
 import numpy as np
 
@@ -27,14 +30,18 @@ def mse(T, R):
     return float(np.sum((np.abs(T) - np.abs(R)) ** 2) / (nx * ny))
 
 
-def nmse(T, A, exclude=None):
+def nmse(T, A, exclude=None, region=None):
     """Scale-optimal normalised MSE of replay amplitude A against target T;
-    exclude: optional (row, column) of one pixel left out of the sums."""
+    exclude: optional (row, column) of one pixel left out of the sums;
+    region: optional boolean mask, the only pixels counted."""
     T = np.array(T, dtype=np.float64)
     A = np.array(A, dtype=np.float64)
     if exclude is not None:
         T[exclude] = 0.0
         A[exclude] = 0.0
+    if region is not None:
+        T[~region] = 0.0
+        A[~region] = 0.0
     sta = float(np.sum(T * A))
     saa = float(np.sum(A * A))
     stt = float(np.sum(T * T))

@@ -16,12 +16,16 @@ available; the paper uses no public dataset):
   fresnel_z        per-problem propagation distance, uniform in [0.1, 0.5] m
   batch_mix        the uneven 256-problem Fresnel batch (64x256^2,
                    96x512^2, 64x1024^2, 32x2048^2)
+  roi_mask         a region-of-interest mask: the union of a few discs and
+                   rectangles placed off centre (kind "shapes"), or
+                   independent pixels with probability 1/2 (kind "pixels")
 """
 import numpy as np
 
 TAG_TARGET = 2
 TAG_GAUSS = 3
 TAG_ZDRAW = 4
+TAG_ROI = 5
 
 WAVELENGTH_M = 532e-9
 PITCH_M = 8e-6
@@ -74,3 +78,27 @@ def batch_mix(scale=1):
     for n, c in mix:
         out += [n] * max(1, c // scale)
     return out
+
+
+def roi_mask(ny, nx, seed, kind="shapes"):
+    """Region-of-interest mask, uint8 [ny][nx] (1 = controlled replay pixel).
+
+    shapes: 2 discs (radius ny/16 - ny/6) and 2 rectangles (sides nx/8 -
+    nx/3), centres uniform over the plane, so the mask is neither centred
+    nor centro-symmetric; pixels: each pixel in with probability 1/2."""
+    rng = _rng(seed, TAG_ROI)
+    if kind == "pixels":
+        return (rng.random((ny, nx)) < 0.5).astype(np.uint8)
+    yy = np.arange(ny)[:, None]
+    xx = np.arange(nx)[None, :]
+    m = np.zeros((ny, nx), bool)
+    for _ in range(2):
+        cy, cx = rng.random() * ny, rng.random() * nx
+        r = (1.0 / 16 + (1.0 / 6 - 1.0 / 16) * rng.random()) * ny
+        m |= (yy - cy) ** 2 + (xx - cx) ** 2 <= r * r
+    for _ in range(2):
+        h = int((1.0 / 8 + (1.0 / 3 - 1.0 / 8) * rng.random()) * ny)
+        w = int((1.0 / 8 + (1.0 / 3 - 1.0 / 8) * rng.random()) * nx)
+        y0, x0 = int(rng.random() * (ny - h)), int(rng.random() * (nx - w))
+        m[y0:y0 + h, x0:x0 + w] = True
+    return m.astype(np.uint8)
