@@ -247,7 +247,23 @@ typedef struct hg_problem {
   float* weights;               /* weighted calls: nullable [ny][nx] centred weights, read as w_0 and
                                    overwritten with w_K (as hg_wgs); NULL starts from 1. Ignored
                                    (may be set) when the call is not weighted */
+  const uint8_t* roi;           /* nullable region of interest, see below (plain GS only) */
 } hg_problem;
+
+/* Region of interest (Background section: many applications care about part
+ * of the replay field only, and restricting the error metric to that part
+ * gives the algorithm more freedom; Algorithms section: amplitude freedom
+ * where the replay is not controlled).  roi is a centred [ny][nx] uint8 mask,
+ * nonzero = controlled replay pixel.  The target outside the mask is
+ * ignored (it is zeroed before the preparation, so the energy scaling counts
+ * the mask only).  The controlled region is the mask, united with its mirror
+ * image T(-u) for binary phase and amplitude SLMs, whose replay is
+ * centro-symmetric.  Inside the region the constraint is GS's,
+ * R' = T R/|R|; outside R' = R; every NMSE (nmse_out) counts the region
+ * only.  A problem with a region runs plain GS on a phase or amplitude SLM:
+ * with weighted != 0 or lt != 0 the call fails with HG_ERR_INVALID_ARG.  A
+ * target with no energy inside the mask gives NaN NMSEs (HG_ERR_NUMERIC).
+ * Problems with a region run the multi-launch pipeline at every size.        */
 
 /* Many OSPR / adaptive OSPR problems in one call ("Time-Averaged
  * Algorithms" section; the paper's batch processing of independent

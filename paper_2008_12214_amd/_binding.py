@@ -38,7 +38,7 @@ class hg_problem(ctypes.Structure):
                 ("wavelength_m", _d), ("pitch_m", _d), ("z_m", _d),
                 ("target", _vp), ("levels_out", _vp), ("nmse_out", _vp),
                 ("init_levels", _vp), ("replay_out", _vp),
-                ("lt", _i), ("lt_r0", _i), ("lt_dr", _i), ("reserved_", _i), ("weights", _vp)]
+                ("lt", _i), ("lt_r0", _i), ("lt_dr", _i), ("reserved_", _i), ("weights", _vp), ("roi", _vp)]
 
 
 class hg_ospr_problem(ctypes.Structure):
@@ -434,6 +434,8 @@ def _problem_array(problems):
             arr[i].lt, arr[i].lt_r0, arr[i].lt_dr = 1, int(lt[0]), int(lt[1])
         if p.get("weights") is not None:
             arr[i].weights = p["weights"].data_ptr()
+        if p.get("roi") is not None:
+            arr[i].roi = p["roi"].data_ptr()
     return arr
 
 
@@ -443,7 +445,7 @@ def hg_gs_batched_workspace_size(problems):
 
 
 def hg_gs_batched(targets, iters, slm_levels, seeds=None, optics=None, weighted=False, init_levels=None,
-                  want_replay=False, stream=None, workspace=None, lt=None, weights=None):
+                  want_replay=False, stream=None, workspace=None, lt=None, weights=None, roi=None):
     """Many GS problems (possibly of different sizes) in one call.
 
     targets: list of float32 CUDA tensors; slm_levels: one value for every
@@ -452,8 +454,10 @@ def hg_gs_batched(targets, iters, slm_levels, seeds=None, optics=None, weighted=
     (wavelength_m, pitch_m, z_m) per problem; init_levels: optional list of
     uint8 start levels (entries may be None); weights: optional list of
     float32 weight tensors (weighted calls read w_0 and write w_K in place;
-    entries may be None).  Returns (levels, nmse) lists, plus the list of
-    final centred replays when want_replay.
+    entries may be None); roi: optional list of uint8 region-of-interest
+    masks (centred, nonzero = controlled; entries may be None).  Returns
+    (levels, nmse) lists, plus the list of final centred replays when
+    want_replay.
     """
     torch = _torch()
     dev = targets[0].device
@@ -471,11 +475,14 @@ def hg_gs_batched(targets, iters, slm_levels, seeds=None, optics=None, weighted=
         wt = weights[i] if weights is not None else None
         if wt is not None:
             _dev_tensor(wt, torch.float32, (ny, nx), f"weights[{i}]")
+        rm = roi[i] if roi is not None else None
+        if rm is not None:
+            _dev_tensor(rm, torch.uint8, (ny, nx), f"roi[{i}]")
         lam, pit, z = optics[i] if optics is not None else (0.0, 0.0, 0.0)
         probs.append(dict(ny=ny, nx=nx, slm_levels=per[i], iters=iters,
                           seed=(seeds[i] if seeds is not None else 0), wavelength_m=lam, pitch_m=pit, z_m=z,
                           target=t, levels_out=lv, nmse_out=nm, init_levels=il, replay_out=rp,
-                          lt=(lt[i] if lt is not None else None), weights=wt))
+                          lt=(lt[i] if lt is not None else None), weights=wt, roi=rm))
         levels.append(lv)
         nmses.append(nm)
         replays.append(rp)

@@ -319,10 +319,16 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
     bt.s16_col = std::ldexp(1.0f, -ey);
     bt.inv16_col = std::ldexp(1.0f, ey);
   }
-  bool any_lt = false;  // Liu-Taghizadeh: not in the single-launch small-problem kernel
-  for (const Desc& d : ds) any_lt |= (d.lt != 0);
+  // Liu-Taghizadeh or a region of interest: not in the single-launch
+  // small-problem kernel; in the classic kernels' window instantiation
+  bool any_lt = false, any_roi = false;
+  for (const Desc& d : ds) {
+    any_lt |= (d.lt != 0) || (d.roi != nullptr);
+    any_roi |= d.roi != nullptr;
+  }
   for (const Desc& d : ds) bt.dump |= (d.r_out != nullptr) ? 1 : 0;
   bt.any_lt = any_lt ? 1 : 0;  // the classic GS column kernels' window instantiation
+  bt.any_roi = any_roi ? 1 : 0;  // the GS tile kernels' region instantiation
   bt.status = status;
   upload_descs(const_cast<Desc*>(bt.desc), ds, st, first ? status : nullptr);
   bool fresnel = false;
@@ -359,7 +365,7 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
   std::sort(ks.begin(), ks.end());
   ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
   for (int k : ks) launch_col(bt, cfg.C, B, COL_FINAL, k + 1, 0, nullptr, nullptr, st);
-  hipLaunchKernelGGL(k_finish, dim3(B, (kmax + 1 + 255) / 256), dim3(256), 0, st, bt, B, 0);
+  hipLaunchKernelGGL(k_finish, dim3(B, finish_grid_y(kmax + 1)), dim3(64 * kFinishPerBlock), 0, st, bt, B, 0);
   return check_launch();
 }
 
@@ -395,7 +401,7 @@ hg_status run_ospr_class(int ny, int nx, const std::vector<Desc>& ds, int subfra
     launch_row(bt, cfg.RPB, B, false, LK_BIN, ROW_OSPR, n, nullptr, nullptr, st);
     launch_col(bt, cfg.C, B, n == subframes ? COL_OSPR_FINAL : COL_OSPR, n + 1, adaptive, nullptr, nullptr, st);
   }
-  hipLaunchKernelGGL(k_finish, dim3(B, (subframes + 255) / 256), dim3(256), 0, st, bt, B, 1);
+  hipLaunchKernelGGL(k_finish, dim3(B, finish_grid_y(subframes)), dim3(64 * kFinishPerBlock), 0, st, bt, B, 1);
   return check_launch();
 }
 
@@ -873,6 +879,8 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
       std::string msg = g_err;
       return fail(s, "problem %d: %s", i, msg.c_str());
     }
+    if (p.roi && (weighted || p.lt))
+      return fail(HG_ERR_INVALID_ARG, "problem %d: a region of interest runs with plain GS (not weighted, not LT)", i);
   }
   const size_t need = hg_gs_batched_workspace_size(probs, count);
   hg_status s = check_ws(workspace, workspace_bytes, need);
@@ -903,6 +911,7 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
       d.lt_dr = p.lt_dr;
       d.weights = weighted ? p.weights : nullptr;
       d.user_weights = (weighted && p.weights) ? 1 : 0;
+      d.roi = p.roi;
       ds.push_back(d);
       rates.push_back(chirp_rate(p.wavelength_m, p.pitch_m, p.z_m));
       kmax = std::max(kmax, p.iters);

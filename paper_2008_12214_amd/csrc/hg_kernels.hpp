@@ -18,6 +18,9 @@ namespace hg {
 
 constexpr int kMaxWaves = 16;
 constexpr int kE = 16;  // elements per thread in every transform
+// Prepared-target value of a replay pixel outside a problem's region of
+// interest (prepared targets are otherwise >= 0 or NaN).
+constexpr float kRoiFree = -1.0f;
 
 // Per-problem descriptor (device memory).  Replay-plane arrays are centred.
 struct Desc {
@@ -29,7 +32,11 @@ struct Desc {
   float* weights;             // WGS weights: user buffer or workspace
   const uint8_t* init_levels; // nullable
   const float2* init_field;   // nullable
-  float* accum_out;           // OSPR accumulator out (nullable)
+  union {
+    float* accum_out;         // OSPR: accumulator out (nullable)
+    const uint8_t* roi;       // GS: region of interest [ny][nx] (nonzero = controlled replay pixel; nullable),
+                              // read only in batches with any_roi set (a 128-byte descriptor)
+  };
   uint64_t seed;
   uint32_t item;              // Philox item
   int L;                      // SLM levels (0 = continuous)
@@ -41,6 +48,7 @@ struct Desc {
   float2* r_out;              // one-iteration calls: replay of the start field, before the constraint (nullable)
   float2* g_out;              // one-iteration calls: SLM-plane field before the projection (nullable)
 };
+static_assert(sizeof(Desc) == 128, "descriptors at a power-of-two stride: two scalar-cache lines each");
 
 // Launch-uniform view of one size class of problems (passed by value).
 struct Batch {
@@ -58,7 +66,7 @@ struct Batch {
   int nblk;             // column tiles per problem (= nx / C)
   int slots;            // partial slots per problem
   float fwd_scale;      // 1/sqrt(nx ny)
-  int any_lt;           // some problem of the batch has a Liu-Taghizadeh region
+  int any_lt;           // some problem of the batch has a Liu-Taghizadeh region or a region of interest
   int* status;          // the call's numeric status word: nonzero once a finisher saw non-finite sums
   int dump;             // some problem asks for r_out: the first column pass runs its dumping instantiation
   int f16;              // the field plane holds two binary16 values per element (4 bytes), not complex64
@@ -67,6 +75,8 @@ struct Batch {
   float s16_row, inv16_row;  // 16-bit planes: the row pass stores x s16_row, the column pass loads x inv16_row
   float s16_col, inv16_col;  // the column pass stores x s16_col, the row pass loads x inv16_col
   const float2* tw_y8;  // OSPR columns of 512 with 8 elements per thread: staged twiddles of that plan (else null)
+  int any_roi;          // a GS batch in which some problem has a region of interest (Desc::roi is read;
+                        // the GS tile kernels run COL_GSR)
 };
 
 // 16-bit field storage: one element as two IEEE binary16 values (real in the
@@ -354,10 +364,13 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_energy(Batch bt) {
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int u = blk * C + c;
   const float* tg = bt.desc[b].target;
+  const uint8_t* roi = bt.any_roi ? bt.desc[b].roi : nullptr;
   float e = 0.0f;
 #pragma unroll
   for (int j = 0; j < kE; ++j) {
-    const float v = tg[(size_t)(t + T * j) * bt.nx + u];
+    const size_t idx = (size_t)(t + T * j) * bt.nx + u;
+    float v = tg[idx];
+    if (roi) v = roi[idx] ? v : 0.f;  // the target outside the region is ignored
     e += v * v;
   }
   block_sum4<NT>(e, 0.f, 0.f, 0.f, red, tot);
@@ -383,30 +396,77 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_prepare(Batch bt, int weighte
   __shared__ int srow[2];  // the tile's (LDS atomics)
   if (threadIdx.x == 0) { srow[0] = NY; srow[1] = -1; }
   const int um = (bt.nx - u) & (bt.nx - 1);
+  // the problem's choices: binary phase or amplitude SLM (centro-symmetric
+  // replay: symmetrised target), region of interest, caller weights
+  const bool sym = uni(d.L) == 2 || uni(d.mod);
+  const uint8_t* roi = bt.any_roi ? uni_ptr(d.roi) : nullptr;
+  const bool uw = weighted && uni(d.user_weights);
+  gptr<const float> tg = to_global(uni_ptr(d.target));
+  // Every load first, in straight-line code, so that all of them are in
+  // flight together (with the element branches inside the loop below, each
+  // element's load was waited for alone).
+  float tv[kE], tm[kE], wv[kE];
+  uint32_t cv[kE], cmv[kE];  // mask bytes of the pixel and of its mirror image
+#pragma unroll
+  for (int j = 0; j < kE; ++j) {
+    tv[j] = tg[(size_t)(t + T * j) * bt.nx + u];
+    tm[j] = 0.f;
+    cv[j] = cmv[j] = 1u;
+    wv[j] = 1.0f;
+  }
+  if (sym) {
+#pragma unroll
+    for (int j = 0; j < kE; ++j) tm[j] = tg[(size_t)((bt.ny - (t + T * j)) & (bt.ny - 1)) * bt.nx + um];
+  }
+  if (roi) {
+    gptr<const uint8_t> rg = to_global(roi);
+#pragma unroll
+    for (int j = 0; j < kE; ++j) {
+      cv[j] = rg[(size_t)(t + T * j) * bt.nx + u];
+      cmv[j] = rg[(size_t)((bt.ny - (t + T * j)) & (bt.ny - 1)) * bt.nx + um];
+    }
+  }
+  if (uw) {
+    gptr<const float> wg = to_global(uni_ptr(d.weights));
+#pragma unroll
+    for (int j = 0; j < kE; ++j) wv[j] = wg[(size_t)(t + T * j) * bt.nx + u];
+  }
 #pragma unroll
   for (int j = 0; j < kE; ++j) {
     const int v = t + T * j;
-    const size_t idx = (size_t)v * bt.nx + u;
-    float tv = d.target[idx];
-    if (d.L == 2 || d.mod) {  // binary phase or amplitude SLM: centro-symmetric replay
-      const int vm = (bt.ny - v) & (bt.ny - 1);
-      const float tm = d.target[(size_t)vm * bt.nx + um];
-      tv = sqrtf(0.5f * (tv * tv + tm * tm));
+    // region of interest: the target outside it is ignored, and a pixel
+    // outside the controlled region (the region, with its mirror image for a
+    // centro-symmetric replay) is marked by a negative prepared target: the
+    // GS column passes leave it free and out of the NMSE
+    float a = tv[j];
+    bool ctl = true;
+    if (roi) {
+      ctl = cv[j] != 0u;
+      a = ctl ? a : 0.f;
     }
-    tv *= scale;
+    if (sym) {
+      float m = tm[j];
+      if (roi) {
+        const bool cm = cmv[j] != 0u;
+        m = cm ? m : 0.f;
+        ctl = ctl || cm;
+      }
+      a = sqrtf(0.5f * (a * a + m * m));
+    }
+    a *= scale;
+    if (!ctl) a = kRoiFree;
     const uint32_t ti = tix(v, u, bt.nx);
-    const float wv = (weighted && d.user_weights) ? d.weights[idx] : 1.0f;
     // a non-finite caller weight poisons its pixel's target, so the NMSE
     // turns NaN as for a non-finite target
-    if (!__builtin_isfinite(wv)) tv = __builtin_nanf("");
-    bt.tprep[off + ti] = tv;
+    if (!__builtin_isfinite(wv[j])) a = __builtin_nanf("");
+    bt.tprep[off + ti] = a;
     // support: every pixel whose target is not exactly zero (a NaN or
     // negative value counts, so the column passes read it and the NMSE
     // turns non-finite as it does in every kernel)
-    const bool sup = !(tv == 0.f);
+    const bool sup = !(a == 0.f);
     if (weighted) {
-      w[ti] = wv;
-      if (sup) ws += wv;
+      w[ti] = wv[j];
+      if (sup) ws += wv[j];
     }
     if (sup) { om += 1.f; rlo = min(rlo, v); rhi = max(rhi, v); }
   }
@@ -738,6 +798,8 @@ __global__ __launch_bounds__(RPB * (NX / EE), (row_min_waves<NX, RPB>())) void k
 enum ColMode {
   COL_GS = 0,          // iteration k = arg: partials for nmse[k-1], R' = T R/|R|
   COL_WGS = 1,         // as COL_GS with the weight update
+  COL_GSR = 2,         // as COL_GS, in the tile kernels of a size class that holds a region of interest:
+                       // pixels outside a region keep R and stay out of the NMSE sums
   COL_OSPR_FIRST = 3,  // T e^{i phi_1} -> inverse FFT
   COL_OSPR = 4,        // subframe arg >= 2: finish subframe arg-1, start arg
   COL_OSPR_FINAL = 5,  // finish the last subframe
@@ -755,8 +817,10 @@ __device__ __forceinline__ float clamp_w(float x) {
   return x < kWMin ? kWMin : (x > kWMax ? kWMax : x);
 }
 
-// LT: the GS pass also applies Liu-Taghizadeh regions (a separate instantiation,
-// so that plain GS does not carry the window test's registers).
+// LT: the GS pass also applies Liu-Taghizadeh regions and regions of
+// interest, and the final pass leaves pixels outside a region of interest out
+// of its sums (separate instantiations, so that plain GS does not carry the
+// tests' registers and its final pass sums exactly as the iterations do).
 // DUMP: GS / WGS pass that also writes each problem's replay before the
 // constraint to its r_out (one-iteration calls only; a separate instantiation).
 template <int NY, int C, int MODE, bool LT = false, bool DUMP = false>
@@ -831,7 +895,12 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
       const float A = a2 * inv * bt.fwd_scale;  // |R| of the unitary transform
       const float Tv = tp[ti];
       const bool zj = j == E / 2 && zo;
-      if (!zj) {
+      // free pixels keep R and stay out of the NMSE: the zero order, and a
+      // pixel outside the region of interest (a negative prepared target;
+      // size classes holding a problem with a region run the LT
+      // instantiations, so the others keep this pass's plain arithmetic)
+      const bool fr = zj || (LT && (MODE == COL_FINAL || MODE == COL_GS) && Tv < 0.f);
+      if (!fr) {
         s_ta += Tv * A;
         s_aa += A * A;
         s_tt += Tv * Tv;
@@ -858,7 +927,7 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_col(Batch bt, int arg, int ad
           const bool out = max(abs(t + T * j - (NY >> 1)), abs(u - (NX >> 1))) > ltr;
           v[j] = out ? cscale(Rr, bt.fwd_scale) : v[j];
         }
-        if (zj) v[j] = cscale(Rr, bt.fwd_scale);
+        if (fr) v[j] = cscale(Rr, bt.fwd_scale);
       }
     }
     block_sum4<NT>(s_ta, s_aa, s_tt, s_w, red, tot);
@@ -1051,7 +1120,12 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
       const float A = a2 * inv * bt.fwd_scale;  // |R| of the unitary transform
       const float Tv = tp[ti];
       const bool zj = i == E / 2 && zo;
-      if (!zj) {
+      // free pixels keep R and stay out of the NMSE: the zero order, and a
+      // pixel outside the region of interest (a negative prepared target;
+      // size classes holding a problem with a region run the LT
+      // instantiations, so the others keep this pass's plain arithmetic)
+      const bool fr = zj || (LT && (MODE == COL_FINAL || MODE == COL_GS) && Tv < 0.f);
+      if (!fr) {
         s_ta += Tv * A;
         s_aa += A * A;
         s_tt += Tv * Tv;
@@ -1078,7 +1152,7 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_colw(Batch bt, int arg, int a
           const bool out = max(abs(row - (NY >> 1)), abs(u - (NX >> 1))) > ltr;
           if (out) mine[lds_pad(row)] = cscale(Rr, bt.fwd_scale);
         }
-        if (zj) mine[lds_pad(row)] = cscale(Rr, bt.fwd_scale);
+        if (fr) mine[lds_pad(row)] = cscale(Rr, bt.fwd_scale);
       }
     }
     block_sum4<NT>(s_ta, s_aa, s_tt, s_w, red, tot);  // ends with a barrier
@@ -1323,7 +1397,7 @@ __device__ __forceinline__ void colp_load_in(const Batch& bt, int k, int vt, int
   in.active = d.iters >= k;
   if (!in.active) return;
   in.lt_r = -1;
-  if constexpr (MODE == COL_GS) {
+  if constexpr (MODE == COL_GS || MODE == COL_GSR) {
     if (d.lt) in.lt_r = (int)min((long long)d.lt_r0 + (long long)(k - 1) * d.lt_dr, (long long)(NY + bt.nx));
   }
   const int c = threadIdx.x % C, t = threadIdx.x / C;
@@ -1432,16 +1506,22 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
       const float inv = a2 > 0.f ? __builtin_amdgcn_rsqf(a2) : 0.f;
       const float A = a2 * inv * bt.fwd_scale;
       const float Tv = in.tv[j];
+      // COL_GSR: a pixel outside the region of interest (negative prepared
+      // target) keeps R and stays out of the NMSE sums, as does the
+      // amplitude SLM's zero order.  Tz is the target with such pixels at 0
+      // (a NaN target stays NaN).
+      const bool rf = MODE == COL_GSR && Tv < 0.f;
+      const float Tz = rf ? 0.f : Tv;
       if (!zj) {
-        s_ta += Tv * A;
-        s_aa += A * A;
-        s_tt += Tv * Tv;
+        s_ta += Tz * A;
+        s_aa += rf ? 0.f : A * A;
+        s_tt += Tz * Tz;
       }
       if constexpr (DUMP) {  // one-iteration calls: the replay before the constraint
         const Desc& dd = bt.desc[b];
         if (dd.r_out) to_global(dd.r_out)[(size_t)row * NX + u] = cscale(Rr, bt.fwd_scale);
       }
-      float amp = Tv;
+      float amp = Tz;
       if constexpr (WGS) {
         if (Tv > 0.f) {
           const float ratio = fmaxf(Tv, kWgsEps) * __builtin_amdgcn_rcpf(fmaxf(A, kWgsEps));
@@ -1452,8 +1532,11 @@ __device__ __forceinline__ void colp_tile(const Batch& bt, int k, int vt, int vt
           amp = wn * Tv;
         }
       }
-      v[j] = a2 > 0.f ? cscale(Rr, amp * inv) : make_float2(amp, 0.f);
-      if constexpr (MODE == COL_GS) {  // Liu-Taghizadeh: amplitude free outside the square
+      // R' = amp R/|R|, or R itself on a free pixel (unitary scale); R = 0
+      // gives (amp, 0), which is 0 on a free pixel
+      const float sc = rf ? bt.fwd_scale : amp * inv;
+      v[j] = a2 > 0.f ? cscale(Rr, sc) : make_float2(amp, 0.f);
+      if constexpr (MODE == COL_GS || MODE == COL_GSR) {  // Liu-Taghizadeh: amplitude free outside the square
         if (in.lt_r >= 0 && max(abs(t + T * j - (NY >> 1)), abs(u - (NX >> 1))) > in.lt_r)
           v[j] = cscale(Rr, bt.fwd_scale);
       }
@@ -1721,32 +1804,36 @@ __device__ __forceinline__ double nmse_from_sums(double sta, double saa, double 
 }
 
 // nmse[k] = 1 - sta^2 / (stt saa) from the block partials of slot k; a GS
-// problem has iters + 1 values, an OSPR problem `iters` (= subframes).
+// problem has iters + 1 values, an OSPR problem `iters` (= subframes).  One
+// wave per value: lane l sums tiles l, l + 64, ... and the wave adds the
+// lanes (slot_total's fixed order), so a value costs nblk / 64 loads per lane
+// instead of a chain of nblk loads in one thread.  Wave w of block (b, y)
+// takes values k = 4 y + w, then k + 4 gridDim.y, ... of problem b.
+constexpr int kFinishPerBlock = 4;
 static __global__ void k_finish(Batch bt, int count, int ospr) {
   const int b = blockIdx.x;
-  const int k = threadIdx.x + blockIdx.y * blockDim.x;
+  const int lane = threadIdx.x & 63;
   if (b >= count) return;
   const Desc& d = bt.desc[b];
-  if (!d.nmse_out || k >= d.iters + (ospr ? 0 : 1)) return;
-  // four interleaved running sums (tile mod 4), added pairwise at the end:
-  // a fixed order with four records' loads in flight
-  double a[4][3] = {};
-  int i = 0;
-  for (; i + 4 <= bt.nblk; i += 4) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double* pp = part_ptr(bt, b, k, i + u);
-      a[u][0] += pp[0]; a[u][1] += pp[1]; a[u][2] += pp[2];
+  if (!d.nmse_out) return;
+  const int nk = d.iters + (ospr ? 0 : 1);
+  for (int k = blockIdx.y * kFinishPerBlock + (int)(threadIdx.x >> 6); k < nk;
+       k += (int)gridDim.y * kFinishPerBlock) {  // uniform per wave
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int i = lane; i < bt.nblk; i += 64) {
+      const double* pp = part_ptr(bt, b, k, i);
+      s0 += pp[0]; s1 += pp[1]; s2 += pp[2];
     }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (lane == 0) d.nmse_out[k] = nmse_from_sums(s0, s1, s2, bt.status);
   }
-  for (int u = 0; i < bt.nblk; ++i, ++u) {
-    const double* pp = part_ptr(bt, b, k, i);
-    a[u][0] += pp[0]; a[u][1] += pp[1]; a[u][2] += pp[2];
-  }
-  double sum[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) sum[c] = (a[0][c] + a[1][c]) + (a[2][c] + a[3][c]);
-  d.nmse_out[k] = nmse_from_sums(sum[0], sum[1], sum[2], bt.status);
+}
+// Blocks along y for nk values (at most the grid limit; the waves loop).
+inline unsigned finish_grid_y(int nk) {
+  const int y = (nk + kFinishPerBlock - 1) / kFinishPerBlock;
+  return (unsigned)(y < 65535 ? y : 65535);
 }
 
 }  // namespace hg

@@ -168,6 +168,21 @@ def test_lt_validation():
     assert L.hg_gs_batched(probs, 1, 0, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG
 
 
+def test_roi_validation():
+    """A region of interest runs with plain GS: weighted or Liu-Taghizadeh
+    problems that carry one are rejected on the host before any launch."""
+    probs = (hg._binding.hg_problem * 1)()
+    probs[0] = hg._binding.hg_problem(64, 64, 2, 3, 1, 0, 0, 0, 0x10000, 0x10000, None)
+    probs[0].roi = 0x10000
+    assert L.hg_gs_batched(probs, 1, 1, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG  # weighted
+    assert "region of interest" in hg.hg_last_error()
+    probs[0].lt, probs[0].lt_r0, probs[0].lt_dr = 1, 8, 4
+    assert L.hg_gs_batched(probs, 1, 0, FAKE, 1 << 30, None) == hg.HG_ERR_INVALID_ARG  # LT
+    assert "region of interest" in hg.hg_last_error()
+    # the struct ends with the mask pointer, as in include/hologen.h
+    assert hg._binding.hg_problem.roi.offset == ctypes.sizeof(hg._binding.hg_problem) - ctypes.sizeof(ctypes.c_void_p)
+
+
 def test_ospr_batched_validation():
     P = hg._binding.hg_ospr_problem
     probs = (P * 2)()
