@@ -363,16 +363,23 @@ __global__ __launch_bounds__(C * (NY / kE)) void k_energy(Batch bt) {
   const int b = blockIdx.y, blk = xcd_tile(blockIdx.x, gridDim.x);
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int u = blk * C + c;
-  const float* tg = bt.desc[b].target;
-  const uint8_t* roi = bt.any_roi ? bt.desc[b].roi : nullptr;
+  gptr<const float> tg = to_global(uni_ptr(bt.desc[b].target));
+  const uint8_t* roi = bt.any_roi ? uni_ptr(bt.desc[b].roi) : nullptr;
+  // loads first (straight-line), then the sum
+  float v[kE];
+#pragma unroll
+  for (int j = 0; j < kE; ++j) v[j] = tg[(size_t)(t + T * j) * bt.nx + u];
+  if (roi) {  // the target outside the region is ignored
+    gptr<const uint8_t> rg = to_global(roi);
+    uint32_t m[kE];
+#pragma unroll
+    for (int j = 0; j < kE; ++j) m[j] = rg[(size_t)(t + T * j) * bt.nx + u];
+#pragma unroll
+    for (int j = 0; j < kE; ++j) v[j] = m[j] ? v[j] : 0.f;
+  }
   float e = 0.0f;
 #pragma unroll
-  for (int j = 0; j < kE; ++j) {
-    const size_t idx = (size_t)(t + T * j) * bt.nx + u;
-    float v = tg[idx];
-    if (roi) v = roi[idx] ? v : 0.f;  // the target outside the region is ignored
-    e += v * v;
-  }
+  for (int j = 0; j < kE; ++j) e += v[j] * v[j];
   block_sum4<NT>(e, 0.f, 0.f, 0.f, red, tot);
   if (threadIdx.x == 0) part_ptr(bt, b, bt.slots - 1, blk)[0] = tot[0];
 }
