@@ -617,10 +617,10 @@ __global__ __launch_bounds__(RPB * (NX / EE), (row_min_waves<NX, RPB>())) void k
   // LDS buffers for whole-line 16-byte accesses (rows of several waves then
   // exchange through one buffer each)
   constexpr bool STAGE = XCH && RPB == 4;
-  // row buffer pitch; staged rows are offset by 8 elements so that the four
-  // rows of a group, which the staging accesses interleave, fall in
-  // different LDS banks
-  constexpr int LW = NX + NX / 16 + (STAGE ? 8 : 0);
+  // row buffer pitch; staged rows are offset by 4 elements (32 bytes) so
+  // that the four rows of a group, which the staging's 16-byte accesses
+  // interleave, start 8 banks apart and eight lanes fill the 32 banks once
+  constexpr int LW = NX + NX / 16 + (STAGE ? 4 : 0);
   constexpr bool PP = !WAVE && !STAGE;
   constexpr int NBUF = PP ? 2 : 1;
   __shared__ __align__(16) float2 lds[XCH ? RPB * NBUF * LW : 1];
