@@ -324,6 +324,20 @@ hg_status hg_get_launch_config(int ny, int nx, int batch, int* col_tile, int* ro
  * results are identical up to the order of the NMSE partial sums. */
 hg_status hg_set_small_fused(int enable);
 
+/* Batched GS and weighted GS (hg_gs_batched) run each size class in chunks
+ * of problems whose field planes together take at most field_bytes (at
+ * least one problem per chunk), one chunk after another on the call's
+ * stream, each through all its iterations.  A chunk that fits the GPU's
+ * last-level cache (256 MB Infinity Cache on MI355X) keeps the field a pass
+ * writes there for the next pass, instead of a round trip through HBM.
+ * 0 runs each class whole.  Default 128 MiB, unless the environment sets
+ * HG_BATCH_CHUNK_MB.  Process-wide; results are identical for every chunk
+ * size (each problem keeps its own random stream and its own sums); the
+ * workspace size does not change.  HG_ERR_INVALID_ARG beyond 1 TiB.
+ * hg_get_batch_chunk returns the current value. */
+hg_status hg_set_batch_chunk(size_t field_bytes);
+size_t hg_get_batch_chunk(void);
+
 /* Kernel of the GS / weighted GS column passes, process-wide:
  *   0  one column tile per workgroup (the default, unless the environment
  *      sets HG_COLUMN_KERNEL=persistent or =classic);

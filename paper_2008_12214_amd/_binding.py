@@ -108,6 +108,10 @@ def lib():
         L.hg_set_small_fused.argtypes = [_i]
         L.hg_set_column_kernel.restype = _i
         L.hg_set_column_kernel.argtypes = [_i]
+        L.hg_set_batch_chunk.restype = _i
+        L.hg_set_batch_chunk.argtypes = [ctypes.c_size_t]
+        L.hg_get_batch_chunk.restype = ctypes.c_size_t
+        L.hg_get_batch_chunk.argtypes = []
         L.hg_get_launch_config.restype = _i
         L.hg_get_launch_config.argtypes = [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]
         L.hg_timing_enable.restype = None
@@ -165,6 +169,16 @@ COLUMN_TILE, COLUMN_PERSISTENT, COLUMN_CLASSIC = 0, 1, 2
 def hg_set_column_kernel(kind):
     """Column-pass kernel kind: COLUMN_TILE (default), COLUMN_PERSISTENT or COLUMN_CLASSIC."""
     _check(lib().hg_set_column_kernel(int(kind)))
+
+
+def hg_set_batch_chunk(field_bytes):
+    """Field bytes per chunk of a batched GS call (0: each size class whole)."""
+    _check(lib().hg_set_batch_chunk(int(field_bytes)))
+
+
+def hg_get_batch_chunk():
+    """Current field bytes per chunk of a batched GS call."""
+    return int(lib().hg_get_batch_chunk())
 
 
 def hg_set_small_fused(enable):

@@ -571,6 +571,16 @@ static std::atomic<int> g_column_kernel{[] {
 }()};
 
 namespace hg {
+// Field bytes per chunk of a batched GS call (hg_set_batch_chunk): 128 MiB
+// unless the environment sets HG_BATCH_CHUNK_MB; 0 runs each size class whole.
+constexpr long long kDefaultChunkBytes = 128ll << 20;
+static std::atomic<long long> g_chunk_bytes{[] {
+  const char* e = std::getenv("HG_BATCH_CHUNK_MB");
+  if (!e || !*e) return kDefaultChunkBytes;
+  const long long mb = std::atoll(e);
+  return mb > 0 ? (mb << 20) : 0ll;
+}()};
+
 bool small_enabled() { return g_small_fused.load(std::memory_order_relaxed) != 0; }
 int column_kernel() { return g_column_kernel.load(std::memory_order_relaxed); }
 }  // namespace hg
@@ -636,6 +646,15 @@ hg_status hg_set_column_kernel(int kind) {
   g_column_kernel.store(kind, std::memory_order_relaxed);
   return HG_OK;
 }
+
+hg_status hg_set_batch_chunk(size_t field_bytes) {
+  g_err[0] = 0;
+  if (field_bytes > ((size_t)1 << 40)) return fail(HG_ERR_INVALID_ARG, "chunk of %zu bytes beyond 1 TiB", field_bytes);
+  g_chunk_bytes.store((long long)field_bytes, std::memory_order_relaxed);
+  return HG_OK;
+}
+
+size_t hg_get_batch_chunk(void) { return (size_t)g_chunk_bytes.load(std::memory_order_relaxed); }
 
 hg_status hg_set_small_fused(int enable) {
   g_err[0] = 0;
@@ -917,9 +936,30 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
       kmax = std::max(kmax, p.iters);
     }
     const Layout Lo = make_layout(HG_OP_WGS, key.ny, key.nx, (int)idx.size(), kmax);
-    s = run_gs_class(key.ny, key.nx, ds, rates, weighted != 0, static_cast<char*>(workspace) + off, Lo, st,
-                     at<int>(workspace, 0), off == 0, key.f16 != 0);
-    if (s != HG_OK) return s;
+    // Chunks of the class whose field planes fit the last-level cache (256 MB
+    // Infinity Cache): the plane a pass writes is then mostly read back by
+    // the next pass from the cache, not from HBM.  Each chunk runs its whole
+    // pipeline in the class's workspace region before the next (stream
+    // order); every problem keeps its own Philox item, so results do not
+    // depend on the chunking.  Single-launch small problems run whole.
+    const size_t per = (size_t)key.ny * key.nx * (key.f16 ? 4 : 8);
+    const size_t chunk = (size_t)g_chunk_bytes.load(std::memory_order_relaxed);
+    const int B = (int)ds.size();
+    int cb = B;
+    if (chunk > 0 && !(small_ok(key.ny, key.nx) && small_enabled()))
+      cb = (int)std::max<size_t>(1, std::min<size_t>((size_t)B, chunk / per));
+    for (int c0 = 0; c0 < B; c0 += cb) {
+      const int nc = std::min(cb, B - c0);
+      const std::vector<Desc> dc(ds.begin() + c0, ds.begin() + c0 + nc);
+      const std::vector<double> rc(rates.begin() + c0, rates.begin() + c0 + nc);
+      int kc = 0;
+      for (const Desc& d : dc) kc = std::max(kc, d.iters);
+      const Layout Lc = nc == B ? Lo : make_layout(HG_OP_WGS, key.ny, key.nx, nc, kc);
+      if (Lc.total > Lo.total) return fail(HG_ERR_INVALID_ARG, "chunk layout exceeds its class's workspace");
+      s = run_gs_class(key.ny, key.nx, dc, rc, weighted != 0, static_cast<char*>(workspace) + off, Lc, st,
+                       at<int>(workspace, 0), off == 0 && c0 == 0, key.f16 != 0);
+      if (s != HG_OK) return s;
+    }
     off += Lo.total;
   }
   return HG_OK;

@@ -246,3 +246,19 @@ def test_search_argument_checks():
     assert call(algo=1, alpha=0.0) == hg.HG_ERR_INVALID_ARG
     assert call(ws=None) == hg.HG_ERR_WORKSPACE
     assert call(wsb=100) == hg.HG_ERR_WORKSPACE
+
+
+def test_batch_chunk_setting():
+    """hg_set_batch_chunk stores the chunk size process-wide and rejects sizes
+    beyond 1 TiB; 0 (whole size classes) is accepted."""
+    old = hg.hg_get_batch_chunk()
+    try:
+        hg.hg_set_batch_chunk(0)
+        assert hg.hg_get_batch_chunk() == 0
+        hg.hg_set_batch_chunk(3 << 20)
+        assert hg.hg_get_batch_chunk() == 3 << 20
+        assert L.hg_set_batch_chunk(ctypes.c_size_t((1 << 40) + 1)) == hg.HG_ERR_INVALID_ARG
+        assert "1 TiB" in hg.hg_last_error()
+        assert hg.hg_get_batch_chunk() == 3 << 20
+    finally:
+        hg.hg_set_batch_chunk(old)
