@@ -61,13 +61,13 @@ def kernel_source_hash():
 
 def committed_traffic(batch):
     """HBM bytes per column-pass launch from the committed rocprofv3 counter runs, if they
-    were taken on the current kernel sources and this batch; else None."""
+    were taken on the current kernel sources and launches of this many problems; else None."""
     path = os.path.join(ROOT, "profiles", "wgs1024_colpass_traffic.json")
     try:
         t = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("batch") != batch:
+    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("problems_per_launch") != batch:
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -649,6 +649,9 @@ def main():
     col_bytes = args.steps * (ITERS * col_px_bytes + COL_FINAL_BYTES) * px
     # row launches: one initial pass (writes the field, 8 B/px) + ITERS passes
     row_bytes = args.steps * (8 + ITERS * ROW_BYTES + 1) * px
+    # the call runs in chunks of problems whose field planes fit the chunk size
+    chunk = hg.hg_get_batch_chunk()
+    per_launch = B if chunk == 0 else max(1, min(B, chunk // (N * N * 8)))
     col_avg_ms = kt["col_ms"] / kt["col_launches"]
     row_avg_ms = kt["row_ms"] / kt["row_launches"]
     col_gbs = col_bytes / (kt["col_ms"] * 1e-3) / 1e9
@@ -702,11 +705,12 @@ def main():
         "config": {"workload": f"wgs_binary_{N}x{N}_{ITERS}it", "batch": B, "grid": [N, N], "iters": ITERS,
                    "slm_levels": LEVELS, "target": "gaussian sum, 32 blobs, central window"},
         "roofline": {"bound": "hbm", "achieved": round(col_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(col_gbs / HBM_PEAK_GBS, 4), "traffic": committed_traffic(B),
+                     "frac": round(col_gbs / HBM_PEAK_GBS, 4), "traffic": committed_traffic(per_launch),
                      "kernel": "column pass of weighted GS (one tile per workgroup, k_colq<1024,4,COL_WGS>)",
                      "bytes_per_launch": int(col_bytes / kt["col_launches"]),
                      "bytes_per_px": round(col_px_bytes, 3), "support_fraction": round(omega, 4),
-                     "avg_launch_us": round(col_avg_ms * 1e3, 2)},
+                     "avg_launch_us": round(col_avg_ms * 1e3, 2), "problems_per_launch": per_launch,
+                     "chunk_field_bytes": chunk},
         "cpu_baseline": cpu,
         "extra": {"row_pass": {"avg_launch_us": round(row_avg_ms * 1e3, 2), "achieved_GBs": round(row_gbs, 1)},
                   "whole_iteration_algorithmic_GBs": round(iter_gbs, 1),

@@ -332,8 +332,10 @@ hg_status hg_set_small_fused(int enable);
  * writes there for the next pass, instead of a round trip through HBM.
  * 0 runs each class whole.  Default 128 MiB, unless the environment sets
  * HG_BATCH_CHUNK_MB.  Process-wide; results are identical for every chunk
- * size (each problem keeps its own random stream and its own sums); the
- * workspace size does not change.  HG_ERR_INVALID_ARG beyond 1 TiB.
+ * size (each problem keeps its own random stream and its own sums, and the
+ * kernel and tile choices follow the whole size class); the workspace size
+ * does not change.  Single-launch small problems (each side 64 or 128) are
+ * not chunked.  HG_ERR_INVALID_ARG beyond 1 TiB.
  * hg_get_batch_chunk returns the current value. */
 hg_status hg_set_batch_chunk(size_t field_bytes);
 size_t hg_get_batch_chunk(void);

@@ -297,7 +297,8 @@ Batch make_batch(void* ws, const Layout& L, int ny, int nx, int C) {
 // f16: the class's field plane holds 16-bit elements (the default launch
 // configuration, whose kernels exist for them, and their power-of-two scales).
 hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::vector<double>& rates, bool weighted,
-                       void* ws, const Layout& L, hipStream_t st, int* status, bool first, bool f16 = false) {
+                       void* ws, const Layout& L, hipStream_t st, int* status, bool first, bool f16 = false,
+                       int class_b = 0) {
   const int B = (int)ds.size();
   int kmax = 0;
   bool all_bin = true;
@@ -307,10 +308,11 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
   }
   // 16-bit planes: the tile kernel's shape (256 threads: C = 4096 / ny) and
   // the default row grouping, the instantiations that exist for them
-  const Cfg cfg = f16 ? Cfg{4096 / ny, default_rpb(nx)} : get_cfg(ny, nx, B);
+  const Cfg cfg = f16 ? Cfg{4096 / ny, default_rpb(nx)} : get_cfg(ny, nx, std::max(B, class_b));
   if (!col_ok(ny, cfg.C) || !rpb_ok(nx, cfg.RPB))  // a pass with no compiled kernel would launch nothing
     return fail(HG_ERR_INVALID_ARG, "no kernel for %d-column tiles / %d rows per group at %dx%d", cfg.C, cfg.RPB, ny, nx);
   Batch bt = make_batch(ws, L, ny, nx, cfg.C);
+  bt.class_b = class_b;
   if (f16) {
     bt.f16 = 1;
     const int ex = ilog2(nx) / 2, ey = ilog2(ny) / 2;  // 2^-floor(log2(n) / 2)
@@ -940,8 +942,9 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
     // Infinity Cache): the plane a pass writes is then mostly read back by
     // the next pass from the cache, not from HBM.  Each chunk runs its whole
     // pipeline in the class's workspace region before the next (stream
-    // order); every problem keeps its own Philox item, so results do not
-    // depend on the chunking.  Single-launch small problems run whole.
+    // order); every problem keeps its own Philox item, and kernel and tile
+    // choices follow the whole class, so results do not depend on the
+    // chunking.  Single-launch small problems run whole.
     const size_t per = (size_t)key.ny * key.nx * (key.f16 ? 4 : 8);
     const size_t chunk = (size_t)g_chunk_bytes.load(std::memory_order_relaxed);
     const int B = (int)ds.size();
@@ -957,7 +960,7 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
       const Layout Lc = nc == B ? Lo : make_layout(HG_OP_WGS, key.ny, key.nx, nc, kc);
       if (Lc.total > Lo.total) return fail(HG_ERR_INVALID_ARG, "chunk layout exceeds its class's workspace");
       s = run_gs_class(key.ny, key.nx, dc, rc, weighted != 0, static_cast<char*>(workspace) + off, Lc, st,
-                       at<int>(workspace, 0), off == 0 && c0 == 0, key.f16 != 0);
+                       at<int>(workspace, 0), off == 0 && c0 == 0, key.f16 != 0, B);
       if (s != HG_OK) return s;
     }
     off += Lo.total;

@@ -77,6 +77,8 @@ struct Batch {
   const float2* tw_y8;  // OSPR columns of 512 with 8 elements per thread: staged twiddles of that plan (else null)
   int any_roi;          // a GS batch in which some problem has a region of interest (Desc::roi is read;
                         // the GS tile kernels run COL_GSR)
+  int class_b;          // problems of the whole size class when a call runs it in chunks (kernel choices
+                        // follow the class, not the chunk); 0: the launch's own count
 };
 
 // 16-bit field storage: one element as two IEEE binary16 values (real in the

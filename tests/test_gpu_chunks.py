@@ -6,7 +6,9 @@ Philox item and its own fixed-order sums, so levels, NMSE histories, weights
 and replays must be bit-identical for every chunk size, including a chunk of
 one problem and no chunking at all.  The mixed batch spans several size
 classes (Fourier and Fresnel, 8-level and binary, 16-bit field storage) with
-class sizes that the chunk sizes do not divide.
+class sizes that the chunk sizes do not divide, and a class of 64 problems of
+256^2, whose column pass runs the persistent pipelined kernel (at least 2048
+column tiles per launch) for the whole class and so for each of its chunks.
 """
 import numpy as np
 import pytest
@@ -73,6 +75,17 @@ def test_chunked_field16_batch_is_bit_identical(restore_chunk):
     ref = _run(Ts, [L] * 5, None, True, 5)
     hg.hg_set_batch_chunk(2 * 256 * 256 * 4)  # two problems of 4-byte elements per chunk
     got = _run(Ts, [L] * 5, None, True, 5)
+    for part, (a, b) in enumerate(zip(ref, got)):
+        for i, (x, y) in enumerate(zip(a, b)):
+            assert torch.equal(x, y), f"output {part} of problem {i} differs"
+
+
+def test_chunks_keep_the_class_kernel(restore_chunk):
+    Ts = [synth.gaussian_target(256, seed=4, batch_item=i) for i in range(64)]
+    hg.hg_set_batch_chunk(0)
+    ref = _run(Ts, [2] * 64, None, True, 4)
+    hg.hg_set_batch_chunk(3 * 256 * 256 * 8)  # three problems per chunk, 22 chunks
+    got = _run(Ts, [2] * 64, None, True, 4)
     for part, (a, b) in enumerate(zip(ref, got)):
         for i, (x, y) in enumerate(zip(a, b)):
             assert torch.equal(x, y), f"output {part} of problem {i} differs"
