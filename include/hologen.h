@@ -326,12 +326,15 @@ hg_status hg_set_small_fused(int enable);
 
 /* Batched GS and weighted GS (hg_gs_batched) run each size class in chunks
  * of problems whose field planes together take at most field_bytes (at
- * least one problem per chunk), one chunk after another on the call's
+ * least one problem per chunk, the class split into chunks of equal size as
+ * far as the count allows), one chunk after another on the call's
  * stream, each through all its iterations.  A chunk that fits the GPU's
  * last-level cache (256 MB Infinity Cache on MI355X) keeps the field a pass
  * writes there for the next pass, instead of a round trip through HBM.
  * 0 runs each class whole.  Default 128 MiB, unless the environment sets
- * HG_BATCH_CHUNK_MB.  Process-wide; results are identical for every chunk
+ * HG_BATCH_CHUNK_MB.  Batched OSPR (hg_ospr_batched) chunks the same way
+ * (by its field planes).
+ * Process-wide; results are identical for every chunk
  * size (each problem keeps its own random stream and its own sums, and the
  * kernel and tile choices follow the whole size class); the workspace size
  * does not change.  Single-launch small problems (each side 64 or 128) are

@@ -371,21 +371,43 @@ hg_status run_gs_class(int ny, int nx, const std::vector<Desc>& ds, const std::v
   return check_launch();
 }
 
+// Plane bytes per chunk of a batched call (hg_set_batch_chunk): 128 MiB
+// unless the environment sets HG_BATCH_CHUNK_MB; 0 runs each size class whole.
+constexpr long long kDefaultChunkBytes = 128ll << 20;
+static std::atomic<long long> g_chunk_bytes{[] {
+  const char* e = std::getenv("HG_BATCH_CHUNK_MB");
+  if (!e || !*e) return kDefaultChunkBytes;
+  const long long mb = std::atoll(e);
+  return mb > 0 ? (mb << 20) : 0ll;
+}()};
+
+// Problems per chunk of a size class of B problems of `per` plane bytes each
+// under the chunk size (hg_set_batch_chunk), balanced over the chunks.
+int chunk_problems(int B, size_t per, bool chunkable) {
+  const size_t chunk = (size_t)g_chunk_bytes.load(std::memory_order_relaxed);
+  if (chunk == 0 || !chunkable) return B;
+  const int cap = (int)std::max<size_t>(1, std::min<size_t>((size_t)B, chunk / per));
+  const int n = (B + cap - 1) / cap;
+  return (B + n - 1) / n;
+}
+
 // Whole OSPR / adaptive OSPR pipeline for one size class: B problems with
-// the same number of subframes, one batched launch per pass.
+// the same number of subframes, one batched launch per pass (class_b: problems of
+// the whole class when this is one of its chunks).
 hg_status run_ospr_class(int ny, int nx, const std::vector<Desc>& ds, int subframes, int adaptive, void* ws,
-                         const Layout& L, hipStream_t st, int* status, bool first) {
+                         const Layout& L, hipStream_t st, int* status, bool first, int class_b = 0) {
   const int B = (int)ds.size();
-  Cfg cfg = get_cfg(ny, nx, B);
+  const int SB = std::max(B, class_b);  // kernel and tile choices follow the whole class
+  Cfg cfg = get_cfg(ny, nx, SB);
   // fewer than 8 problems of 512 rows: 4-column tiles (the default unless a
   // configuration was tuned or set), which run with 8 elements per thread in
   // the column passes: twice the workgroups of the default tiles and half
   // the per-thread work
-  if (ny == 512 && batch_class(B) == 0 && !has_tuned_cfg(ny, nx, B)) {
+  if (ny == 512 && batch_class(SB) == 0 && !has_tuned_cfg(ny, nx, SB)) {
     cfg.C = 4;
     if (nx == 512) cfg.RPB = 4;  // 512-wide rows: 8 elements per thread there too, one wave per row
   }
-  const bool e8 = ny == 512 && batch_class(B) == 0 && cfg.C == 4 && column_kernel() == CK_TILE;
+  const bool e8 = ny == 512 && batch_class(SB) == 0 && cfg.C == 4 && column_kernel() == CK_TILE;
   if (!col_ok(ny, cfg.C) || !rpb_ok(nx, cfg.RPB))  // a pass with no compiled kernel would launch nothing
     return fail(HG_ERR_INVALID_ARG, "no kernel for %d-column tiles / %d rows per group at %dx%d", cfg.C, cfg.RPB, ny, nx);
   Batch bt = make_batch(ws, L, ny, nx, cfg.C);
@@ -573,15 +595,6 @@ static std::atomic<int> g_column_kernel{[] {
 }()};
 
 namespace hg {
-// Field bytes per chunk of a batched GS call (hg_set_batch_chunk): 128 MiB
-// unless the environment sets HG_BATCH_CHUNK_MB; 0 runs each size class whole.
-constexpr long long kDefaultChunkBytes = 128ll << 20;
-static std::atomic<long long> g_chunk_bytes{[] {
-  const char* e = std::getenv("HG_BATCH_CHUNK_MB");
-  if (!e || !*e) return kDefaultChunkBytes;
-  const long long mb = std::atoll(e);
-  return mb > 0 ? (mb << 20) : 0ll;
-}()};
 
 bool small_enabled() { return g_small_fused.load(std::memory_order_relaxed) != 0; }
 int column_kernel() { return g_column_kernel.load(std::memory_order_relaxed); }
@@ -803,9 +816,20 @@ hg_status hg_ospr_batched(const hg_ospr_problem* probs, int count, int subframes
       ds.push_back(d);
     }
     const Layout Lo = make_layout(HG_OP_OSPR, key.ny, key.nx, (int)idx.size(), subframes);
-    s = run_ospr_class(key.ny, key.nx, ds, subframes, adaptive, static_cast<char*>(workspace) + off, Lo, st,
-                       at<int>(workspace, 0), off == 0);
-    if (s != HG_OK) return s;
+    // chunks of at most the chunk size of field planes, as in hg_gs_batched
+    // (16 problems of 1024^2 by default: their field and accumulator planes,
+    // 192 MiB, measured faster than chunks of 8)
+    const int B = (int)ds.size();
+    const int cb = chunk_problems(B, (size_t)key.ny * key.nx * 8, true);
+    for (int c0 = 0; c0 < B; c0 += cb) {
+      const int nc = std::min(cb, B - c0);
+      const std::vector<Desc> dc(ds.begin() + c0, ds.begin() + c0 + nc);
+      const Layout Lc = nc == B ? Lo : make_layout(HG_OP_OSPR, key.ny, key.nx, nc, subframes);
+      if (Lc.total > Lo.total) return fail(HG_ERR_INVALID_ARG, "chunk layout exceeds its class's workspace");
+      s = run_ospr_class(key.ny, key.nx, dc, subframes, adaptive, static_cast<char*>(workspace) + off, Lc, st,
+                         at<int>(workspace, 0), off == 0 && c0 == 0, B);
+      if (s != HG_OK) return s;
+    }
     off += Lo.total;
   }
   return HG_OK;
@@ -945,12 +969,9 @@ hg_status hg_gs_batched(const hg_problem* probs, int count, int weighted, void* 
     // order); every problem keeps its own Philox item, and kernel and tile
     // choices follow the whole class, so results do not depend on the
     // chunking.  Single-launch small problems run whole.
-    const size_t per = (size_t)key.ny * key.nx * (key.f16 ? 4 : 8);
-    const size_t chunk = (size_t)g_chunk_bytes.load(std::memory_order_relaxed);
     const int B = (int)ds.size();
-    int cb = B;
-    if (chunk > 0 && !(small_ok(key.ny, key.nx) && small_enabled()))
-      cb = (int)std::max<size_t>(1, std::min<size_t>((size_t)B, chunk / per));
+    const int cb = chunk_problems(B, (size_t)key.ny * key.nx * (key.f16 ? 4 : 8),
+                                  !(small_ok(key.ny, key.nx) && small_enabled()));
     for (int c0 = 0; c0 < B; c0 += cb) {
       const int nc = std::min(cb, B - c0);
       const std::vector<Desc> dc(ds.begin() + c0, ds.begin() + c0 + nc);

@@ -89,3 +89,22 @@ def test_chunks_keep_the_class_kernel(restore_chunk):
     for part, (a, b) in enumerate(zip(ref, got)):
         for i, (x, y) in enumerate(zip(a, b)):
             assert torch.equal(x, y), f"output {part} of problem {i} differs"
+
+
+def test_chunked_ospr_batch_is_bit_identical(restore_chunk):
+    """Batched adaptive OSPR in chunks (counted by field planes, as for GS):
+    subframe levels, NMSE and the accumulated intensity equal those of the
+    whole call.  The 512^2 class of
+    three problems keeps its small-batch kernels in every chunk."""
+    shapes = [512] * 3 + [256] * 4
+    Ts = [torch.from_numpy(synth.gaussian_target(n, seed=6, batch_item=i)).to(DEV) for i, n in enumerate(shapes)]
+    out = {}
+    for chunk in (0, 512 * 512 * 8, 2 * 256 * 256 * 8):
+        say(f"OSPR chunk {chunk} bytes")
+        hg.hg_set_batch_chunk(chunk)
+        lv, nm, ac = hg.hg_ospr_batched(Ts, 6, True, seeds=[9] * len(Ts), want_accum=True)
+        torch.cuda.synchronize()
+        out[chunk] = [x.cpu() for x in lv + nm + ac]
+    for chunk, got in out.items():
+        for i, (x, y) in enumerate(zip(out[0], got)):
+            assert torch.equal(x, y), f"chunk {chunk}: output {i} differs"
